@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the lattice Boltzmann transport pipeline (test infrastructure).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+import this package.  The product path (``paper_1410_1921_amd``) never does.  The C
+source ``lbm_oracle.c`` shares no code, table or constant with the HIP library.
+
+Parity status of each function (what pins it, in ``tests/test_oracle_*.py``):
+
+* ``splitmix64`` -- published SplitMix64 outputs for seed 0 (golden file).
+* ``lens_volume`` -- closed forms (containment, tangency, equal spheres) and a
+  Monte-Carlo estimate.
+* ``reconstruct`` -- brute-force re-check of the acceptance rules over every accepted
+  pair and of the stop rule; porosity reached.
+* ``label18`` -- ``scipy.ndimage.label`` with the 18-neighbour structure on masks
+  whose y/z faces are solid, plus hand cases for the periodic wrap.
+* ``chords13`` -- closed values on boxes, slabs and single voxels, and an independent
+  pure-Python walk on tiny masks.
+* ``edt2`` -- ``scipy.ndimage.distance_transform_edt`` and O(N^6) brute force.
+* ``mis`` -- slit widths (odd H gives H, even gives H-1), single balls, brute force.
+* ``flow_solve`` -- exact discrete slit (plane Poiseuille) permeability, square duct
+  series solution, tube (Eq. 27) convergence, mass and momentum balance, mirror
+  symmetry, Stokes linearity.
+* ``knudsen_solve`` -- exact straight-duct flux (tortuosity 1 at tau = 1), parallel
+  columns with different tau, mass conservation, swap and linearity.
+* ``knudsen_diffusivity`` / ``fc`` -- the paper's printed D_K(60 nm, 323 K) and the
+  coefficient 64/(3 pi) of Eq. 28.
+"""
+from .oracle import *  # noqa: F401,F403
