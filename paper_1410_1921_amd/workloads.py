@@ -123,3 +123,35 @@ def random_state(n_nodes, q, scale, seed):
     """Seeded random population offsets (node-major [n_nodes, q]) of size `scale`."""
     rng = np.random.default_rng(seed)
     return scale * rng.standard_normal((n_nodes, q))
+
+
+def _fmix64(k):
+    """MurmurHash3's 64-bit finaliser (uint64 numpy arrays, wrapping arithmetic)."""
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xFF51AFD7ED558CCD)
+    k = k ^ (k >> np.uint64(33))
+    k = k * np.uint64(0xC4CEB9FE1A85EC53)
+    return k ^ (k >> np.uint64(33))
+
+
+def hash_uniform(seed, idx):
+    """Counter-based uniforms in [0, 1) for integer indices `idx`: any subset of a large
+    field can be drawn without drawing the rest (float64, 53 bits)."""
+    idx = np.asarray(idx, np.uint64)
+    with np.errstate(over="ignore"):
+        k = _fmix64(idx * np.uint64(0x9E3779B97F4A7C15) + _fmix64(np.uint64(seed) + np.uint64(1)))
+    return (k >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def hash_field(shape, seed, lo, hi, comps=1, lin=None):
+    """Seeded field of values uniform in [lo, hi): planar [comps, nz, ny, nx] float32
+    (comps > 1) or [nz, ny, nx].  With `lin` (linear voxel indices) only those voxels are
+    drawn, shape [comps, len(lin)]."""
+    nvox = int(np.prod(shape))
+    out = []
+    for c in range(comps):
+        idx = np.arange(nvox, dtype=np.uint64) if lin is None else np.asarray(lin, np.uint64)
+        u = hash_uniform(seed * 8 + c, idx + np.uint64(c) * np.uint64(nvox))
+        v = (lo + (hi - lo) * u).astype(np.float32)
+        out.append(v.reshape(shape) if lin is None else v)
+    return np.stack(out) if comps > 1 else out[0]

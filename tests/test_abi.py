@@ -1,0 +1,113 @@
+"""The C-ABI library loads, exports every entry point that include/lbm.h declares, and its
+host-only paths (struct layouts, workspace sizing, argument checks, properties) behave
+as documented.  No GPU needed: nothing here launches a kernel."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1410_1921_amd import lbm
+    return lbm
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    L = lib.load()
+    names = _declared()
+    assert len(names) == 15
+    for name in names:
+        assert hasattr(L, name), name
+    # and the binding wraps each of them
+    for name in names:
+        assert name in lib._SIGS, name
+
+
+def test_struct_layouts_match(lib):
+    for i, cls in enumerate(lib.STRUCTS):
+        assert lib.lbm_sizeof(i) == C.sizeof(cls), cls.__name__
+    assert lib.lbm_sizeof(99) == 0
+
+
+def test_version(lib):
+    assert "gfx950" in lib.lbm_version()
+
+
+def test_workspace_sizes(lib):
+    s_small = lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), 1000)
+    s_big = lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), 20000)
+    # two population buffers of 19 binary32 values per extra node, at least
+    assert s_big - s_small >= 2 * 19 * 4 * 19000
+    # n_fluid < 0 sizes for every voxel
+    assert lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), -1) >= \
+        lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), 32 ** 3)
+    assert lib.lbm_workspace_size(lib.LBM_WS_KNUDSEN, (16, 16, 16), 100) > 0
+    assert lib.lbm_workspace_size(lib.LBM_WS_LABEL, (16, 16, 16)) >= 2 * 16 ** 3
+    assert lib.lbm_workspace_size(lib.LBM_WS_PORE_DIAM, (16, 16, 16)) >= 12 * 16 ** 3
+    with pytest.raises(lib.LbmError) as e:
+        lib.lbm_workspace_size(7, (8, 8, 8))
+    assert e.value.status == lib.LBM_E_INVAL
+    with pytest.raises(lib.LbmError):
+        lib.lbm_workspace_size(lib.LBM_WS_FLOW, (2000, 8, 8))
+    with pytest.raises(lib.LbmError):
+        lib.lbm_workspace_size(lib.LBM_WS_FLOW, (8, 8, 8), 10_000)
+
+
+def test_argument_checks_before_device(lib):
+    L = lib.load()
+    n = (C.c_int32 * 3)(8, 8, 8)
+    dummy = C.c_void_p(1)
+    # tau <= 1/2 is rejected before anything touches a device
+    p = lib.lbm_flow_params(0.5, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, 0, 1e-7, 1.0, 0, 0)
+    r = lib.lbm_flow_result()
+    assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
+                            None) == lib.LBM_E_INVAL
+    assert "tau" in L.lbm_last_error().decode()
+    p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 0, 0, 1e-7, 1.0, 0, 0)
+    assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
+                            None) == lib.LBM_E_INVAL
+    kp = lib.lbm_knudsen_params(1.0, 60.0, 1.5, 1.0, 1.0, 323.0, 0.016, 10, 0, 10, 0, 1e-7)
+    kr = lib.lbm_knudsen_result()
+    assert L.lbm_knudsen_solve(n, dummy, dummy, C.byref(kp), C.byref(kr), None, None, None,
+                               dummy, 1 << 20, None) == lib.LBM_E_INVAL
+    rp = lib.lbm_recon_params((C.c_int32 * 3)(8, 8, 8), 1.5, 4.0, 1.0, 1.0, 0.5, 0.5, 1, 0)
+    rs = lib.lbm_recon_stats()
+    assert L.lbm_reconstruct(C.byref(rp), dummy, None, 0, C.byref(rs), None) == lib.LBM_E_INVAL
+    assert L.lbm_label(n, None, None, None, None, None, 0, None) == lib.LBM_E_INVAL
+    assert L.lbm_pore_diameter(n, dummy, 5, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
+    nbad = (C.c_int32 * 3)(0, 8, 8)
+    assert L.lbm_pore_diameter(nbad, dummy, 0, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
+
+
+def test_props_relations(lib, orc):
+    g = dict(n_pore=400, n_transport=380, n_components=2, porosity=0.4, connectivity=0.95)
+    f = dict(steps=100, n_fluid=400, converged=1, reserved=0, k_lattice=0.1, k_m2=2.25e-19,
+             k_mD=2.25e-19 / 9.869233e-16, residual=1e-8, mean_rho_u=[1e-6, 0, 0], mass_dev=0.0,
+             sweep_ms=1.0, mlups=1.0, gbps=1.0)
+    dk = orc.knudsen_diffusivity(60e-9, 323.0)
+    k = dict(steps=100, n_fluid=400, converged=1, reserved=0, Deff_lattice=0.0125,
+             Deff_over_DKref=0.1, Deff_m2s=0.1 * dk, DK_ref_m2s=dk, tortuosity=4.0,
+             tortuosity_local=3.0, phi_in=1.0, phi_out=1.0, flux_spread=0.0, residual=1e-8,
+             sum_c=1.0, sweep_ms=1.0, mlups=1.0, gbps=1.0)
+    out = lib.lbm_props(g, f, k, d_mean_nm=45.0, P=17236893.0, T=323.0, mu=1.73e-5)
+    assert out["k_KC_m2"] == pytest.approx(orc.k_kozeny_carman(45e-9, 0.4), rel=1e-14)
+    assert out["fc_dgm"] == pytest.approx(orc.fc_dgm(0.1 * dk, 1.73e-5, 2.25e-19, 17236893.0),
+                                          rel=1e-14)
+    assert out["k_apparent_m2"] == pytest.approx(2.25e-19 * out["fc_dgm"], rel=1e-14)
+    assert out["mean_free_path_m"] == pytest.approx(orc.mean_free_path(1.73e-5, 17236893.0, 323.0),
+                                                    rel=1e-14)
+    assert out["bruggeman_alpha"] == pytest.approx(math.log(0.1) / math.log(0.4), rel=1e-14)
+    partial = lib.lbm_props(g, None, None)
+    assert math.isnan(partial["k_m2"]) and partial["porosity"] == 0.4

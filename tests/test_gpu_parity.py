@@ -1,0 +1,375 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 CPU oracle.
+
+Geometry (reconstruction, labels, transport flags, pore-size maps) must match bit for
+bit.  The FP32 sweeps must match the FP64 oracle element by element at small sizes
+(several bricks plus ragged tails) within the tolerance derived from binary32 storage,
+and k / D_eff within 1e-4 relative at equal step count.  At full size the sweeps are
+checked on sampled nodes: both sides start from the same seeded synthetic field, the GPU
+runs two steps in the launch configuration of the benchmark, and the oracle recomputes
+each sampled node from the 5^3 window around it (two steps reach no further).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1410_1921_amd import lbm
+from paper_1410_1921_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+E19 = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+                (1, 1, 0), (-1, 1, 0), (1, -1, 0), (-1, -1, 0), (1, 0, 1), (-1, 0, 1), (1, 0, -1),
+                (-1, 0, -1), (0, 1, 1), (0, -1, 1), (0, 1, -1), (0, -1, -1)])
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def recon_both(orc, rp):
+    say("reconstruct", rp)
+    pore_g, sph_g, st_g = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                              rp["d_min"], rp["overlap_tol"], rp["p_overlap"],
+                                              rp["seed"])
+    pore_o, sph_o, st_o = orc.reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                          rp["d_min"], rp["overlap_tol"], rp["p_overlap"],
+                                          rp["seed"])
+    return pore_g, sph_g, st_g, pore_o, sph_o, st_o
+
+
+# ------------------------------------------------------------------ geometry, bit-exact
+@pytest.mark.parametrize("rp", [
+    W.SMALL_32["recon"],
+    dict(n=(21, 13, 30), porosity=0.3, d_mean=5.0, d_std=1.5, d_min=1.0, overlap_tol=0.2,
+         p_overlap=0.8, seed=77),
+    dict(n=(40, 40, 40), porosity=0.45, d_mean=7.0, d_std=2.0, d_min=1.0, overlap_tol=0.0,
+         p_overlap=0.5, seed=5),
+    dict(n=(24, 24, 24), porosity=0.3, d_mean=6.0, d_std=2.0, d_min=1.0, overlap_tol=1.0,
+         p_overlap=0.5, seed=6),
+    W.METHANE_128["recon"],
+], ids=["32", "ragged", "xi0", "xi1", "128"])
+def test_geometry_bit_exact(orc, rp):
+    pore_g, sph_g, st_g, pore_o, sph_o, st_o = recon_both(orc, rp)
+    assert np.array_equal(sph_g, sph_o)
+    assert np.array_equal(pore_g.cpu().numpy(), pore_o)
+    assert st_g["n_spheres"] == st_o["n_spheres"] and st_g["n_trials"] == st_o["n_trials"]
+    assert st_g["n_pore"] == st_o["n_pore"]
+    say("label", rp["n"])
+    lab_g, tr_g, ls_g = lbm.lbm_label(pore_g)
+    lab_o, tr_o, ls_o = orc.label18(pore_o)
+    assert np.array_equal(lab_g.cpu().numpy(), lab_o)
+    assert np.array_equal(tr_g.cpu().numpy(), tr_o)
+    assert (ls_g["n_pore"], ls_g["n_transport"], ls_g["n_components"]) == \
+        (ls_o["n_pore"], ls_o["n_transport"], ls_o["n_components"])
+    say("chords13", rp["n"])
+    d_g = lbm.lbm_pore_diameter(pore_g, lbm.LBM_PSD_CHORD13).cpu().numpy()
+    assert np.array_equal(d_g, orc.chords13(pore_o))
+    say("mis", rp["n"])
+    m_g = lbm.lbm_pore_diameter(pore_g, lbm.LBM_PSD_MIS).cpu().numpy()
+    assert np.array_equal(m_g, orc.mis(pore_o))
+
+
+def test_geometry_512_bit_exact(orc):
+    rp = W.LARGE_512["recon"]
+    pore_g, sph_g, st_g, pore_o, sph_o, st_o = recon_both(orc, rp)
+    assert np.array_equal(sph_g, sph_o)
+    assert torch.equal(pore_g, dev(pore_o))
+    say("label 512")
+    lab_g, tr_g, ls_g = lbm.lbm_label(pore_g)
+    lab_o, tr_o, ls_o = orc.label18(pore_o)
+    assert torch.equal(lab_g, dev(lab_o))
+    assert torch.equal(tr_g, dev(tr_o))
+    say("chords13 512")
+    d_g = lbm.lbm_pore_diameter(pore_g, lbm.LBM_PSD_CHORD13)
+    assert torch.equal(d_g, dev(orc.chords13(pore_o)))
+
+
+def test_label_random_masks(orc):
+    for seed, shape, p in [(1, (9, 17, 33), 0.35), (2, (16, 16, 16), 0.5), (3, (1, 5, 40), 0.7),
+                           (4, (33, 2, 7), 0.6)]:
+        m = W.random_mask(shape, p, seed)
+        say("label random", shape)
+        lab_g, tr_g, _ = lbm.lbm_label(dev(m))
+        lab_o, tr_o, _ = orc.label18(m)
+        assert np.array_equal(lab_g.cpu().numpy(), lab_o)
+        assert np.array_equal(tr_g.cpu().numpy(), tr_o)
+
+
+def test_pore_diameter_edge_cases(orc):
+    # an all-pore box has no distance map
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_pore_diameter(dev(np.ones((8, 8, 8), np.uint8)), lbm.LBM_PSD_MIS)
+    assert e.value.status == lbm.LBM_E_INVAL
+    # but its chords are defined
+    d = lbm.lbm_pore_diameter(dev(np.ones((5, 6, 7), np.uint8)), lbm.LBM_PSD_CHORD13)
+    assert np.array_equal(d.cpu().numpy(), orc.chords13(np.ones((5, 6, 7), np.uint8)))
+    # all solid: zeros
+    z = np.zeros((4, 4, 4), np.uint8)
+    assert lbm.lbm_pore_diameter(dev(z), lbm.LBM_PSD_MIS).abs().sum().item() == 0.0
+    for h in (1, 4, 7):
+        m = W.slit(11, h + 4, 9, h, axis=1)
+        assert np.array_equal(lbm.lbm_pore_diameter(dev(m), lbm.LBM_PSD_MIS).cpu().numpy(),
+                              orc.mis(m))
+
+
+# ------------------------------------------------------------------ sweeps, small sizes
+def _u_tol(u_ref):
+    # binary32 populations: errors of ~1e-7 of the populations' deviations, amplified by
+    # the 2000-step history; 1e-5 of the largest speed bounds them with margin
+    return 1e-5 * np.abs(u_ref).max()
+
+
+def test_flow_parity_32(orc):
+    w = W.SMALL_32
+    rp = w["recon"]
+    pore_g, _, _, pore_o, _, _ = recon_both(orc, rp)
+    fp = w["flow"]
+    say("flow 32^3", fp)
+    r = lbm.lbm_flow_solve(pore_g, tau=fp["tau"], force=fp["force"], fixed_steps=fp["fixed_steps"],
+                           check_every=fp["check_every"], voxel_nm=w["voxel_nm"], want_u=True)
+    o = orc.flow_solve(pore_o, tau=fp["tau"], force=fp["force"], fixed_steps=fp["fixed_steps"],
+                       check_every=fp["check_every"])
+    assert r["steps"] == o["steps"] == 2000
+    assert r["k_lattice"] == pytest.approx(o["k_lattice"], rel=1e-4)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= _u_tol(o["u"])
+    assert r["residual"] == pytest.approx(o["residual"], rel=1e-3)
+    assert abs(r["mass_dev"]) < 1e-3
+    say("k", r["k_lattice"], o["k_lattice"], "mlups", r["mlups"])
+
+
+@pytest.mark.parametrize("shape,seed,force", [((13, 21, 10), 3, (1e-5, 2e-6, -3e-6)),
+                                              ((17, 9, 26), 4, (0.0, 0.0, 1e-5)),
+                                              ((1, 12, 12), 5, (1e-5, 0.0, 0.0))])
+def test_flow_parity_ragged(orc, shape, seed, force):
+    m = W.blob_mask(shape, 0.55, seed)
+    say("flow ragged", shape)
+    r = lbm.lbm_flow_solve(dev(m), tau=0.7, force=force, fixed_steps=300, check_every=50,
+                           want_u=True)
+    o = orc.flow_solve(m, tau=0.7, force=force, fixed_steps=300, check_every=50)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= _u_tol(o["u"])
+    assert np.allclose(r["mean_rho_u"], o["mean_rho_u"], rtol=1e-4, atol=1e-4 * np.abs(force).max())
+
+
+def test_flow_slit_closed_form():
+    h, tau = 9, 0.8
+    m = W.slit(4, h + 2, 4, h, axis=1)
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=(1e-6, 0, 0), max_steps=100_000, tol=1e-10)
+    lam = (tau - 0.5) ** 2
+    assert r["converged"]
+    assert r["k_lattice"] == pytest.approx(h / (h + 2) * (h * h + 8 * lam - 1) / 12, rel=1e-5)
+
+
+def test_flow_warm_start_and_resume(orc):
+    m = W.blob_mask((16, 16, 16), 0.6, 9)
+    g = dev(m)
+    say("flow resume")
+    a = lbm.lbm_flow_solve(g, fixed_steps=500, want_u=True)
+    b = lbm.lbm_flow_solve(g, fixed_steps=300)
+    c = lbm.lbm_flow_solve(g, fixed_steps=200, workspace=b.workspace, resume=True, want_u=True)
+    assert c["steps"] == 200
+    assert torch.equal(a.field, c.field)
+    assert a["k_lattice"] == c["k_lattice"]
+    # determinism: the same solve twice gives the same bits
+    a2 = lbm.lbm_flow_solve(g, fixed_steps=500, want_u=True)
+    assert torch.equal(a.field, a2.field) and a["k_lattice"] == a2["k_lattice"]
+    # warm start from a converged field converges at once to the same k
+    full = lbm.lbm_flow_solve(g, max_steps=200_000, tol=1e-8, want_u=True)
+    warm = lbm.lbm_flow_solve(g, max_steps=200_000, tol=1e-8, u_init=full.field.contiguous())
+    assert warm["steps"] < full["steps"] / 2
+    assert warm["k_lattice"] == pytest.approx(full["k_lattice"], rel=1e-4)
+
+
+def test_flow_errors():
+    m = dev(W.blob_mask((8, 8, 8), 0.5, 1))
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_flow_solve(dev(np.zeros((8, 8, 8), np.uint8)), fixed_steps=10, n_fluid=0)
+    assert e.value.status == lbm.LBM_E_INVAL
+    small = lbm.Workspace(4096, "cuda")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_flow_solve(m, fixed_steps=10, workspace=small)
+    assert e.value.status == lbm.LBM_E_NOMEM
+    # a force far beyond the low-Mach range blows up; the check reports it
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_flow_solve(m, tau=0.5001, force=(0.5, 0.3, 0.0), fixed_steps=4000, check_every=100)
+    assert e.value.status == lbm.LBM_E_DIVERGED
+    r = lbm.lbm_flow_solve(m, max_steps=200, tol=1e-30)
+    assert r.status == lbm.LBM_W_NOT_CONVERGED and r["steps"] == 200
+
+
+def test_knudsen_parity_32(orc):
+    w = W.SMALL_32
+    rp = w["recon"]
+    pore_g, _, _, pore_o, _, _ = recon_both(orc, rp)
+    kp = w["knudsen"]
+    d_g = lbm.lbm_pore_diameter(pore_g, lbm.LBM_PSD_CHORD13)
+    d_o = orc.chords13(pore_o)
+    dref = kp["d_ref_nm"] / w["voxel_nm"]
+    tg = np.where(pore_o == 1, orc.tau_g(d_o, dref, kp["tau_ref"]), 1.0)
+    say("knudsen 32^3")
+    r = lbm.lbm_knudsen_solve(pore_g, d_g, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+                              voxel_nm=w["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
+                              T=kp["T"], fixed_steps=kp["fixed_steps"],
+                              check_every=kp["check_every"], want_c=True)
+    o = orc.knudsen_solve(pore_o, tg, kp["c_in"], kp["c_out"], fixed_steps=kp["fixed_steps"],
+                          check_every=kp["check_every"])
+    assert r["steps"] == o["steps"] == 2000
+    assert r["Deff_lattice"] == pytest.approx(o["Deff_lattice"], rel=1e-4)
+    assert r["phi_in"] == pytest.approx(o["phi_in"], rel=1e-4)
+    assert np.abs(r.field.cpu().numpy() - o["c"]).max() < 1e-5
+    assert np.allclose(r["plane_flux"], o["plane_flux"], rtol=1e-4, atol=1e-6)
+    assert r["residual"] == pytest.approx(o["residual"], rel=1e-3)
+    say("Deff", r["Deff_lattice"], o["Deff_lattice"])
+
+
+@pytest.mark.parametrize("shape,seed", [((19, 10, 14), 2), ((33, 7, 5), 8)])
+def test_knudsen_parity_ragged(orc, shape, seed):
+    m = W.blob_mask(shape, 0.6, seed)
+    diam = W.hash_field(shape, seed, 1.0, 40.0).astype(np.float64) * m
+    tg = np.where(m == 1, orc.tau_g(diam, 20.0, 1.0), 1.0)
+    say("knudsen ragged", shape)
+    r = lbm.lbm_knudsen_solve(dev(m), dev(diam), d_ref_nm=30.0, voxel_nm=1.5, c_in=0.8, c_out=0.3,
+                              fixed_steps=400, check_every=50, want_c=True)
+    o = orc.knudsen_solve(m, tg, 0.8, 0.3, fixed_steps=400, check_every=50)
+    assert np.abs(r.field.cpu().numpy() - o["c"]).max() < 1e-5
+    assert r["Deff_lattice"] == pytest.approx(o["Deff_lattice"], rel=1e-4)
+
+
+def test_knudsen_duct_exact():
+    nx = 20
+    m = W.square_duct(nx, 3)
+    for tau in (0.7, 1.0):
+        d = np.full(m.shape, (tau - 0.5) / 0.5 * 40.0)
+        r = lbm.lbm_knudsen_solve(dev(m), dev(d), d_ref_nm=60.0, voxel_nm=1.5, max_steps=500_000,
+                                  tol=1e-9)
+        want = m.mean() * 0.25 * (tau - 0.5) * (nx + 1) / (nx - 1 + 2 * tau)
+        assert r["Deff_lattice"] == pytest.approx(want, rel=1e-5)
+        if tau == 1.0:
+            assert r["tortuosity"] == pytest.approx(1.0, rel=1e-5)
+        assert r["flux_spread"] < 1e-4
+
+
+def test_knudsen_sphere_in_cube():
+    # paper, Section 3.5: D_eff/D = 0.3317 for a solid sphere inscribed in a cube of 100^3
+    m = W.sphere_in_cube(100)
+    d = np.full(m.shape, 40.0)  # tau_g = tau_ref = 1
+    say("sphere in cube 100^3")
+    r = lbm.lbm_knudsen_solve(dev(m), dev(d), d_ref_nm=60.0, voxel_nm=1.5, max_steps=2_000_000,
+                              tol=1e-8)
+    say("sphere-in-cube D_eff/D", r["Deff_over_DKref"], r["steps"])
+    assert r["Deff_over_DKref"] == pytest.approx(0.3317, rel=0.03)
+
+
+# ------------------------------------------------------------------ sweeps, full size sampled
+def _window(lin_shape, centre, half, wrap_x=True):
+    """Voxel index grids of the (2h+1)^3 window around centre (z, y, x); y and z wrap,
+    x wraps or is clipped to the domain."""
+    nz, ny, nx = lin_shape
+    z, y, x = centre
+    zz = (np.arange(z - half, z + half + 1)) % nz
+    yy = (np.arange(y - half, y + half + 1)) % ny
+    xs = np.arange(x - half, x + half + 1)
+    if wrap_x:
+        xs = xs % nx
+    else:
+        xs = xs[(xs >= 0) & (xs < nx)]
+    return zz, yy, xs
+
+
+def _sample_nodes(mask_np, count, seed):
+    fl = np.flatnonzero(mask_np.reshape(-1))
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(fl, size=min(count, len(fl)), replace=False)
+    # include nodes on every face of the box
+    nz, ny, nx = mask_np.shape
+    faces = []
+    for cond in (lambda z, y, x: x == 0, lambda z, y, x: x == nx - 1, lambda z, y, x: y == 0,
+                 lambda z, y, x: z == nz - 1):
+        zz, yy, xx = np.unravel_index(fl, mask_np.shape)
+        sel = fl[cond(zz, yy, xx)]
+        faces.extend(sel[:20].tolist())
+    return np.unique(np.concatenate([pick, np.array(faces, np.int64)]))
+
+
+def _flow_sampled(orc, pore_g, pore_o, seed, nsamp):
+    shape = pore_o.shape
+    nvox = pore_o.size
+    tau, force = 0.8, (2e-5, -1e-5, 5e-6)
+    say("flow sampled", shape, "u_init")
+    u0 = W.hash_field(shape, seed, -2e-3, 2e-3, comps=3)
+    r = lbm.lbm_flow_solve(pore_g, tau=tau, force=force, fixed_steps=2, check_every=100,
+                           u_init=dev(u0))
+    nodes = _sample_nodes(pore_o, nsamp, seed)
+    say("flow sampled nodes", len(nodes))
+    f_g, flag = lbm.lbm_flow_sample(r.workspace, nodes)
+    assert flag.all()
+    worst = 0.0
+    scale = 0.0
+    for k, v in enumerate(nodes):
+        c = np.unravel_index(v, shape)
+        zz, yy, xx = _window(shape, c, 2)
+        mw = np.ascontiguousarray(pore_o[np.ix_(zz, yy, xx)])
+        uw = np.ascontiguousarray(u0[:, zz][:, :, yy][:, :, :, xx].astype(np.float64))
+        f = orc.flow_init(mw, uw)
+        orc.flow_solve(mw, tau=tau, force=force, fixed_steps=2, f=f, want_u=False)
+        ref = f[2, 2, 2] - W19
+        worst = max(worst, np.abs(f_g[k] - ref).max())
+        scale = max(scale, np.abs(ref).max())
+    say("flow sampled worst", worst, "scale", scale)
+    assert worst <= 2e-6 * scale
+    del r
+
+
+def test_flow_sampled_128(orc):
+    rp = W.METHANE_128["recon"]
+    pore_g, _, _, pore_o, _, _ = recon_both(orc, rp)
+    _flow_sampled(orc, pore_g, pore_o, 11, 1500)
+
+
+def test_flow_sampled_512(orc):
+    rp = W.LARGE_512["recon"]
+    pore_g, _, _, pore_o, _, _ = recon_both(orc, rp)
+    _flow_sampled(orc, pore_g, pore_o, 12, 1500)
+    torch.cuda.empty_cache()
+
+
+def test_knudsen_sampled_128(orc):
+    rp = W.METHANE_128["recon"]
+    pore_g, _, _, pore_o, _, _ = recon_both(orc, rp)
+    shape = pore_o.shape
+    seed = 13
+    c0 = W.hash_field(shape, seed, 0.0, 1.0)
+    diam = W.hash_field(shape, seed + 1, 0.5, 40.0).astype(np.float64)
+    dref = 60.0 / 2.0
+    say("knudsen sampled 128")
+    r = lbm.lbm_knudsen_solve(pore_g, dev(diam), d_ref_nm=60.0, voxel_nm=2.0, c_in=1.0, c_out=0.0,
+                              fixed_steps=2, check_every=100, c_init=dev(c0))
+    nodes = _sample_nodes(pore_o, 2000, seed)
+    g_g, tau_g, flag = lbm.lbm_knudsen_sample(r.workspace, nodes)
+    assert flag.all()
+    worst = 0.0
+    for k, v in enumerate(nodes):
+        c = np.unravel_index(v, shape)
+        zz, yy, xx = _window(shape, c, 2, wrap_x=False)
+        mw = np.ascontiguousarray(pore_o[np.ix_(zz, yy, xx)])
+        cw = np.ascontiguousarray(c0[np.ix_(zz, yy, xx)].astype(np.float64))
+        tw = orc.tau_g(diam[np.ix_(zz, yy, xx)], dref, 1.0)
+        tw = np.where(mw == 1, tw, 1.0)
+        g = orc.knudsen_init(mw, cw)
+        orc.knudsen_solve(mw, tw, 1.0, 0.0, fixed_steps=2, g=g, want_c=False, want_planes=False)
+        ix = list(xx).index(c[2])
+        ref = g[2, 2, ix]
+        worst = max(worst, np.abs(g_g[k] - ref).max())
+        assert tau_g[k] == pytest.approx(orc.tau_g(diam[c], dref, 1.0), rel=1e-6)
+    say("knudsen sampled worst", worst)
+    assert worst <= 1e-6
