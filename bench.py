@@ -1,0 +1,222 @@
+"""Benchmark of the whole transport pipeline on one MI355X.
+
+One step = one pass of the hot path over the 128^3 methane workload (2 nm voxels,
+porosity 0.40, sphere diameters N(12, 3) voxels, overlap tolerance 0.3): reconstruction,
+18-neighbour labelling, maximum-inscribed-sphere pore map, the D3Q19 flow solve to
+residual 1e-7 (-> k) and the D3Q7 Knudsen solve to residual 1e-7 (-> D_eff,
+tortuosity), and the derived properties.  `value` is fluid-node updates (both lattices)
+per second of the whole step, in MLUPS.
+
+The JSON line also carries the roofline of the dominant sweep kernel (algorithmic bytes
+per launch / mean launch time from HIP events on the solve's stream), the same figure
+for the D3Q19 sweep on the 512^3 workload (working set far beyond the 256 MB Infinity
+Cache), and the FP64 CPU oracle timed on a bounded sample of the workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline; time-to-converged k and D_eff, plain vs warm-start+FP16"
+HBM_PEAK_GBS = 8000.0
+BYTES_D3Q19 = 152  # 19 loads + 19 stores of binary32 per fluid-node update
+BYTES_D3Q7 = 60    # 7 loads + 7 stores of binary32 + 1/tau_g
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pipeline(lbm, W, w):
+    """One pass of the hot path; returns a dict of results and per-stage timings."""
+    import torch
+    rp = w["recon"]
+    t = {}
+    t0 = time.perf_counter()
+    pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                      rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    t["reconstruct"] = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    _, _, ls = lbm.lbm_label(pore, want_transport=False)
+    t["label"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    method = lbm.LBM_PSD_MIS if rp["psd"] == "mis" else lbm.LBM_PSD_CHORD13
+    diam = lbm.lbm_pore_diameter(pore, method)
+    torch.cuda.synchronize()
+    t["pore_diameter"] = time.perf_counter() - t1
+    fp, kp = w["flow"], w["knudsen"]
+    t1 = time.perf_counter()
+    fr = lbm.lbm_flow_solve(pore, tau=fp["tau"], force=fp["force"], max_steps=fp["max_steps"],
+                            fixed_steps=fp["fixed_steps"], check_every=fp["check_every"],
+                            tol=fp["tol"], voxel_nm=w["voxel_nm"], n_fluid=ls["n_pore"])
+    t["flow"] = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    kr = lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+                               voxel_nm=w["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
+                               T=kp["T"], max_steps=kp["max_steps"], fixed_steps=kp["fixed_steps"],
+                               check_every=kp["check_every"], tol=kp["tol"],
+                               n_fluid=ls["n_pore"])
+    t["knudsen"] = time.perf_counter() - t1
+    props = lbm.lbm_props(ls, fr, kr, d_mean_nm=rp["d_mean"] * w["voxel_nm"], T=kp["T"])
+    torch.cuda.synchronize()
+    t["total"] = time.perf_counter() - t0
+    return dict(recon=rs, label=ls, flow=fr, knudsen=kr, props=props, t=t)
+
+
+def roofline_512(lbm, W, steps):
+    """Mean launch time of the plain D3Q19 sweep on the 512^3 workload, from HIP events
+    on the current stream around `steps` launches."""
+    import torch
+    w = W.LARGE_512
+    rp = w["recon"]
+    pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                      rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    nf = rs["n_pore"]
+    fp = w["flow"]
+    r = lbm.lbm_flow_solve(pore, tau=fp["tau"], force=fp["force"], fixed_steps=20,
+                           check_every=fp["check_every"], voxel_nm=w["voxel_nm"], n_fluid=nf)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lbm.lbm_flow_step(r.workspace, 10)
+    torch.cuda.synchronize()
+    e0.record(s)
+    lbm.lbm_flow_step(r.workspace, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = nf * BYTES_D3Q19 / (ms * 1e-3) / 1e9
+    del r, pore
+    torch.cuda.empty_cache()
+    return {"kernel": "k_sweep19<false>", "workload": w["name"], "n_fluid": nf,
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": ms,
+            "mlups": nf / (ms * 1e3)}
+
+
+def cpu_baseline(W, w, steps):
+    """The FP64 oracle on a bounded sample of the workload: the whole geometry stage plus
+    `steps` steps of each lattice (instead of running to convergence)."""
+    import numpy as np
+    import oracle as orc
+    rp = w["recon"]
+    t0 = time.perf_counter()
+    pore, _, info = orc.reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                    rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    orc.label18(pore)
+    d = orc.mis(pore) if rp["psd"] == "mis" else orc.chords13(pore)
+    fp, kp = w["flow"], w["knudsen"]
+    orc.flow_solve(pore, tau=fp["tau"], force=fp["force"], fixed_steps=steps, want_u=False)
+    tg = np.where(pore == 1, orc.tau_g(d, kp["d_ref_nm"] / w["voxel_nm"], kp["tau_ref"]), 1.0)
+    orc.knudsen_solve(pore, tg, kp["c_in"], kp["c_out"], fixed_steps=steps, want_c=False,
+                      want_planes=False)
+    dt = time.perf_counter() - t0
+    updates = 2 * steps * info["n_pore"]
+    return {"value": round(updates / dt / 1e6, 3), "unit": "MLUPS", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{w['name']}: reconstruction + labelling + pore map + {steps} D3Q19 and "
+                      f"{steps} D3Q7 steps (FP64, dense lattice), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="recon128_eps0.40_d12_mis_ch4_400K")
+    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-512", action="store_true")
+    ap.add_argument("--roofline-steps", type=int, default=100)
+    ap.add_argument("--only-512", action="store_true",
+                    help="only the 512^3 sweep roofline, after a 2 GiB torch copy that "
+                         "calibrates the HBM byte counters (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
+              "decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1410_1921_amd import lbm
+    from paper_1410_1921_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    lbm.load()
+    if args.only_512:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
+                          "copy_bytes_each_way": 1 << 31}), flush=True)
+        return
+    w = W.WORKLOADS[args.workload]
+    log("workload", w["name"])
+    for i in range(args.warmup):
+        r = pipeline(lbm, W, w)
+        log(f"warmup {i}: {r['t']['total']:.2f} s, flow {r['flow']['steps']} steps, "
+            f"knudsen {r['knudsen']['steps']} steps")
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        runs.append(pipeline(lbm, W, w))
+        log(f"step {i}: {runs[-1]['t']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    last = runs[-1]
+    nf = last["flow"]["n_fluid"]
+    updates = sum((r["flow"]["steps"] + r["knudsen"]["steps"]) * nf for r in runs)
+    value = updates / wall / 1e6
+
+    # dominant kernel over the timed region, from the library's HIP events
+    fl_ms = sum(r["flow"]["sweep_ms"] for r in runs)
+    kn_ms = sum(r["knudsen"]["sweep_ms"] for r in runs)
+    fl_n = sum(r["flow"]["steps"] for r in runs)
+    kn_n = sum(r["knudsen"]["steps"] for r in runs)
+    if kn_ms >= fl_ms:
+        name, per, bpu, ms = "k_sweep7", kn_ms / kn_n, BYTES_D3Q7, kn_ms
+    else:
+        name, per, bpu, ms = "k_sweep19", fl_ms / fl_n, BYTES_D3Q19, fl_ms
+    achieved = nf * bpu / (per * 1e-3) / 1e9
+    roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_update": bpu, "n_fluid": nf, "ms_per_launch": per,
+            "share_of_step": round(ms / (wall * 1e3), 4)}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "n": list(w["recon"]["n"]), "n_fluid": nf,
+                   "tol": w["flow"]["tol"], "storage": "f32 (f - w_i)", "init": "zero"},
+        "time_to_converged_s": round(ms_per_step / 1e3, 3),
+        "flow": {k: last["flow"][k] for k in ("steps", "k_lattice", "k_m2", "k_mD", "residual",
+                                              "mlups", "gbps")},
+        "knudsen": {k: last["knudsen"][k] for k in ("steps", "Deff_lattice", "Deff_over_DKref",
+                                                    "Deff_m2s", "tortuosity", "residual",
+                                                    "flux_spread", "mlups", "gbps")},
+        "geometry": {"porosity": last["label"]["porosity"],
+                     "connectivity": last["label"]["connectivity"],
+                     "n_spheres": last["recon"]["n_spheres"]},
+        "stage_s": {k: round(v, 4) for k, v in last["t"].items()},
+        "roofline": roof,
+    }
+    if not args.no_512:
+        log("512^3 roofline")
+        out["roofline_512"] = roofline_512(lbm, W, args.roofline_steps)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(W, w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

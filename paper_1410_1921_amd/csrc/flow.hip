@@ -117,18 +117,21 @@ __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
             sy[k] = ((ys[k] >> kBrickLog) * g.nbx << 9) | ((ys[k] & (kBrick - 1)) << kBrickLog);
             sz[k] = ((zs[k] >> kBrickLog) * g.nbx * g.nby << 9) | ((zs[k] & (kBrick - 1)) << (2 * kBrickLog));
         }
+        // three phases, so that each one's loads are all in flight together: the 18
+        // neighbour ids, then the 19 populations (pull from x - e_i; bounce back from
+        // the node itself when that neighbour is solid)
+        int ids[19];
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            ids[i] = a.idmap[sx[1 - EX[i]] + sy[1 - EY[i]] + sz[1 - EZ[i]]];
+        uint32_t off[19];
+        off[0] = (uint32_t)n;
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
         float f[19];
-        int64_t idx[19];
-        idx[0] = n;
 #pragma unroll
-        for (int i = 1; i < 19; i++) {
-            // pull from x - e_i; bounce back from the node itself when that is solid
-            const int slot = sx[1 - EX[i]] + sy[1 - EY[i]] + sz[1 - EZ[i]];
-            const int id = a.idmap[slot];
-            idx[i] = id >= 0 ? (int64_t)i * a.stride + id : (int64_t)OPP[i] * a.stride + n;
-        }
-#pragma unroll
-        for (int i = 0; i < 19; i++) f[i] = a.src[idx[i]];
+        for (int i = 0; i < 19; i++) f[i] = a.src[off[i]];
 
         float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -301,6 +304,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     FlowWs w = carve_flow(workspace, g, nf);
+    LBM_REQUIRE(19 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
                 "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
                 (long long)nf);

@@ -387,6 +387,11 @@ extern "C" lbm_status lbm_pore_diameter(const int32_t n[3], const uint8_t *pore,
     st = count_nonzero(g, pore, counter, &n_pore, s);
     if (st != LBM_OK) return st;
     LBM_REQUIRE(n_pore < nv, LBM_E_INVAL, "the domain holds no solid voxel: no distance map");
+    if (n_pore == 0) {  // all solid: no pore width anywhere
+        LBM_TRY_HIP(hipMemsetAsync(diam, 0, nv * sizeof(double), s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));
+        return LBM_OK;
+    }
     k_edt_x<<<(unsigned)(((int64_t)g.ny * g.nz + 255) / 256), 256, 0, s>>>(g, pore, a);
     LBM_CHECK_LAUNCH();
     k_edt_axis<<<blocks, 256, 0, s>>>(g, 1, a, b);

@@ -3,7 +3,14 @@
 // links, periodic in y and z, equilibrium ghost planes at x = -1 and x = nx (Section
 // 3.3), and the outlet-plane flux of Eq. 14.
 //
-// Storage: g[i][node] in binary32 (C is O(1), so no shift), 1/tau_g per node in
+// Storage: s[i][node] = g_i - w_i C_ref(x) in binary32, where C_ref(x) is a reference
+// profile along x: the mean concentration of plane x, refreshed at every convergence
+// check (ghost planes: C_ref(-1) = C_in, C_ref(nx) = C_out).  The collision is carried
+// out on these deviations, so rounding acts on numbers far smaller than g itself: both
+// the transient front and the steady state keep binary32 errors near 1e-7 relative,
+// where storing g directly freezes the iteration (per-step changes below half an ulp)
+// up to ~1e-3 away from its steady state on long channels.  The reference costs no
+// bandwidth: it depends on x alone (a table of nx + 2 values).  1/tau_g per node in
 // binary32.  Per fluid-node update: 7 loads + 7 stores of 4 bytes + 4 bytes of 1/tau_g.
 #include <cmath>
 #include <cstring>
@@ -42,6 +49,8 @@ struct KnWs {
     float *omega;
     float *csnap;
     double *partials;
+    double *ref, *ref_new;  // reference profile C_ref(x), index x + 1 for x = -1..nx
+    float *shm, *shp;       // w_1 (C_ref(x -+ 1) - C_ref(x)), index x + 1
     int64_t stride;
     size_t bytes;
 };
@@ -68,6 +77,10 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     w.omega = c.take<float>(w.stride);
     w.csnap = c.take<float>(w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(kn_blocks(nfp)) * kKnSums);
+    w.ref = c.take<double>(kMaxEdge + 2);
+    w.ref_new = c.take<double>(kMaxEdge + 2);
+    w.shm = c.take<float>(kMaxEdge + 2);
+    w.shp = c.take<float>(kMaxEdge + 2);
     w.bytes = c.off;
     return w;
 }
@@ -85,12 +98,13 @@ struct Sweep7 {
     const float *__restrict__ omega;
     const float *__restrict__ src;
     float *__restrict__ dst;
-    float gin_lo, gin_hi;  // w C_in and w C_out (face weight)
+    const float *__restrict__ shm;  // change of reference along a +x link into x
+    const float *__restrict__ shp;  // change of reference along a -x link into x
     // check variant
+    const double *__restrict__ ref;
     float *__restrict__ csnap;
     float *__restrict__ c_out;
     double *__restrict__ partials;
-    double win, wout;      // w C_in, w C_out in FP64 for the fluxes
 };
 
 template <bool CHECK>
@@ -106,46 +120,61 @@ __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
         const int xm = x - 1, xp = x + 1;  // ghost planes beyond the x faces
         const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        // neighbour slots in direction order 1..6 (source x - e_i)
-        int src_slot[7];
-        src_slot[1] = xm >= 0 ? (int)g.slot(xm, y, z) : -1;
-        src_slot[2] = xp < g.nx ? (int)g.slot(xp, y, z) : -1;
-        src_slot[3] = (int)g.slot(x, ym, z);
-        src_slot[4] = (int)g.slot(x, yp, z);
-        src_slot[5] = (int)g.slot(x, y, zm);
-        src_slot[6] = (int)g.slot(x, y, zp);
-        int64_t idx[7];
-        idx[0] = n;
+        // neighbour slots in direction order 1..6 (source x - e_i); beyond an x face the
+        // slot of the node itself stands in, its id is replaced by -2 (ghost plane)
+        int slot[7];
+        slot[1] = (int)g.slot(xm >= 0 ? xm : x, y, z);
+        slot[2] = (int)g.slot(xp < g.nx ? xp : x, y, z);
+        slot[3] = (int)g.slot(x, ym, z);
+        slot[4] = (int)g.slot(x, yp, z);
+        slot[5] = (int)g.slot(x, y, zm);
+        slot[6] = (int)g.slot(x, y, zp);
+        // phase 1: ids, 1/tau_g and the link shifts, all in flight together
+        int ids[7];
 #pragma unroll
-        for (int i = 1; i < 7; i++) {
-            const int id = src_slot[i] >= 0 ? a.idmap[src_slot[i]] : -2;
-            idx[i] = id >= 0 ? (int64_t)i * a.stride + id : (int64_t)OPP[i] * a.stride + n;
-        }
-        float gi[7];
-#pragma unroll
-        for (int i = 0; i < 7; i++) gi[i] = a.src[idx[i]];
-        if (xm < 0) gi[1] = a.gin_lo;
-        if (xp >= g.nx) gi[2] = a.gin_hi;
+        for (int i = 1; i < 7; i++) ids[i] = a.idmap[slot[i]];
         const float om = a.omega[n];
-        float conc = 0.f;
+        const float sm = a.shm[x + 1], sp = a.shp[x + 1];
+        if (xm < 0) ids[1] = -2;
+        if (xp >= g.nx) ids[2] = -2;
+        // phase 2: the populations (id -1: solid, bounce back; -2: ghost plane)
+        uint32_t off[7];
+        off[0] = (uint32_t)n;
 #pragma unroll
-        for (int i = 0; i < 7; i++) conc += gi[i];
-        float go[7];
+        for (int i = 1; i < 7; i++)
+            off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+        float ai[7];
+#pragma unroll
+        for (int i = 0; i < 7; i++) ai[i] = a.src[off[i]];
+        // incoming deviations from this node's reference w_i C_ref(x): a population
+        // streamed along +-x from a fluid neighbour (or a ghost plane, whose deviation is
+        // 0) changes reference plane; bounced and y/z populations keep theirs
+        if (ids[1] == -2) ai[1] = 0.f;
+        if (ids[2] == -2) ai[2] = 0.f;
+        if (ids[1] != -1) ai[1] += sm;
+        if (ids[2] != -1) ai[2] += sp;
+        float cdev = 0.f;  // C - C_ref(x)
+#pragma unroll
+        for (int i = 0; i < 7; i++) cdev += ai[i];
+        float so[7];
 #pragma unroll
         for (int i = 0; i < 7; i++) {
             const float w = i == 0 ? kW0 : kW1;
-            go[i] = gi[i] - om * (gi[i] - w * conc);
-            a.dst[(int64_t)i * a.stride + n] = go[i];
+            so[i] = ai[i] - om * (ai[i] - w * cdev);
+            a.dst[(int64_t)i * a.stride + n] = so[i];
         }
         if (CHECK) {
-            const double dc = (double)conc - (double)a.csnap[n];
-            acc[0] = dc * dc;
-            acc[1] = (double)conc * conc;
-            if (xp >= g.nx) acc[2] = (double)go[1] - a.wout;
-            if (xm < 0) acc[3] = a.win - (double)go[2];
+            const double conc = a.ref[x + 1] + (double)cdev;
+            const double d = conc - (double)a.csnap[n];
+            acc[0] = d * d;
+            acc[1] = conc * conc;
+            // net +x flux into the outlet ghost plane and out of the inlet one, as
+            // streamed (in the node's reference frame)
+            if (xp >= g.nx) acc[2] = (double)so[1] - (double)sp;
+            if (xm < 0) acc[3] = (double)sm - (double)so[2];
             acc[4] = conc;
-            a.csnap[n] = conc;
-            if (a.c_out) a.c_out[g.lin(x, y, z)] = conc;
+            a.csnap[n] = (float)conc;
+            if (a.c_out) a.c_out[g.lin(x, y, z)] = (float)conc;
         }
     }
     if (CHECK) {
@@ -179,6 +208,8 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
         omega[n] = (float)(1.0 / tau);
         acc[0] = tau - 0.5;
         if (init_pop) {
+            // equilibrium w_i C_init against a zero reference; the solve re-centres it
+            // on the plane means before the first step
             const float c0 = c_init ? c_init[v] : 0.f;
             gbuf[n] = kW0 * c0;
             for (int i = 1; i < 7; i++) gbuf[(int64_t)i * stride + n] = kW1 * c0;
@@ -195,8 +226,9 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
 // over links with both ends fluid (ghost planes count as fluid).
 __global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
                                                     const int32_t *__restrict__ idmap,
-                                                    const float *__restrict__ gcur, double win,
-                                                    double wout, double *__restrict__ plane) {
+                                                    const float *__restrict__ gcur,
+                                                    const float *__restrict__ shm,
+                                                    double *__restrict__ plane) {
     const int px = blockIdx.x;
     const int left = px - 1, right = px;
     double acc[1] = {0.0};
@@ -205,9 +237,11 @@ __global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
         const int il = left >= 0 ? idmap[g.slot(left, y, z)] : -2;
         const int ir = right < g.nx ? idmap[g.slot(right, y, z)] : -2;
         if (il == -1 || ir == -1) continue;
-        const double fwd = left >= 0 ? (double)gcur[stride + il] : win;
-        const double bwd = right < g.nx ? (double)gcur[2 * stride + ir] : wout;
-        acc[0] += fwd - bwd;
+        // g_{+x}(left) - g_{-x}(right) in the frame of `right`: s_{+x}(left) + shm(right) -
+        // s_{-x}(right); the ghost planes hold zero deviation
+        const double fwd = left >= 0 ? (double)gcur[stride + il] : 0.0;
+        const double bwd = right < g.nx ? (double)gcur[2 * stride + ir] : 0.0;
+        acc[0] += (fwd + (double)shm[right + 1]) - bwd;
     }
     __shared__ double lds[4];
     double out[1];
@@ -217,16 +251,81 @@ __global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
 
 __global__ void k_kn_sample(Grid g, int64_t count, int64_t stride, const int64_t *__restrict__ vox,
                             const int32_t *__restrict__ idmap, const float *__restrict__ gcur,
-                            const float *__restrict__ omega, double *__restrict__ out,
-                            uint8_t *__restrict__ flag) {
+                            const float *__restrict__ omega, const double *__restrict__ cref,
+                            double *__restrict__ out, uint8_t *__restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
     const int64_t v = vox[s];
     const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
     const int id = idmap[g.slot(x, y, z)];
     flag[s] = id >= 0;
-    for (int i = 0; i < 7; i++) out[s * 8 + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] : 0.0;
+    const double ref = cref[x + 1];
+    for (int i = 0; i < 7; i++)
+        out[s * 8 + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] + (i ? 0.125 : 0.25) * ref
+                                 : 0.0;
     out[s * 8 + 7] = id >= 0 ? 1.0 / (double)omega[id] : 0.0;
+}
+
+// The reference profile follows the solution: at each check the plane means of C become
+// the new C_ref (planes without fluid keep theirs), the stored state is moved onto it,
+// and the link shift tables are rebuilt.  All three steps are deterministic.
+__global__ __launch_bounds__(256) void k_plane_mean(Grid g, const int32_t *__restrict__ idmap,
+                                                    const float *__restrict__ csnap,
+                                                    const double *__restrict__ ref,
+                                                    double *__restrict__ ref_new) {
+    const int x = blockIdx.x;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
+        const int id = idmap[g.slot(x, (int)(k % g.ny), (int)(k / g.ny))];
+        if (id >= 0) {
+            acc[0] += (double)csnap[id];
+            acc[1] += 1.0;
+        }
+    }
+    __shared__ double lds[8];
+    double out[2];
+    block_sum<2>(acc, lds, out);
+    if (threadIdx.x == 0) ref_new[x + 1] = out[1] > 0.0 ? out[0] / out[1] : ref[x + 1];
+}
+
+__global__ __launch_bounds__(256) void k_recenter(int64_t nf, int64_t stride,
+                                                  const uint32_t *__restrict__ coords,
+                                                  const double *__restrict__ ref,
+                                                  const double *__restrict__ ref_new,
+                                                  float *__restrict__ s) {
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nf) return;
+    const int x = coords[n] & 1023;
+    const double d = ref[x + 1] - ref_new[x + 1];
+    s[n] += (float)(0.25 * d);
+    const float d1 = (float)(0.125 * d);
+    for (int i = 1; i < 7; i++) s[(int64_t)i * stride + n] += d1;
+}
+
+__global__ __launch_bounds__(1024) void k_ref_commit(int nx, double c_in, double c_out,
+                                                     double *__restrict__ ref,
+                                                     const double *__restrict__ ref_new,
+                                                     float *__restrict__ shm,
+                                                     float *__restrict__ shp) {
+    for (int k = threadIdx.x; k < nx + 2; k += 1024)
+        ref[k] = k == 0 ? c_in : (k == nx + 1 ? c_out : ref_new[k]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nx + 2; k += 1024) {
+        shm[k] = k >= 1 ? (float)(0.125 * (ref[k - 1] - ref[k])) : 0.f;
+        shp[k] = k <= nx ? (float)(0.125 * (ref[k + 1] - ref[k])) : 0.f;
+    }
+}
+
+static lbm_status kn_recenter(const KnWs &w, const Grid &g, int64_t nf, const KnHeader &h,
+                              int cur, hipStream_t s) {
+    k_plane_mean<<<(unsigned)g.nx, 256, 0, s>>>(g, w.idmap, w.csnap, w.ref, w.ref_new);
+    LBM_CHECK_LAUNCH();
+    k_recenter<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(nf, w.stride, w.coords, w.ref, w.ref_new,
+                                                       w.g[cur]);
+    LBM_CHECK_LAUNCH();
+    k_ref_commit<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.ref, w.ref_new, w.shm, w.shp);
+    LBM_CHECK_LAUNCH();
+    return LBM_OK;
 }
 
 static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, const KnHeader &h, int &cur,
@@ -239,10 +338,9 @@ static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, const KnHe
     a.coords = w.coords;
     a.idmap = w.idmap;
     a.omega = w.omega;
-    a.gin_lo = (float)(0.125 * h.c_in);
-    a.gin_hi = (float)(0.125 * h.c_out);
-    a.win = (double)a.gin_lo;  // the ghost values as streamed
-    a.wout = (double)a.gin_hi;
+    a.shm = w.shm;
+    a.shp = w.shp;
+    a.ref = w.ref;
     a.csnap = w.csnap;
     a.c_out = c_field;
     a.partials = w.partials;
@@ -292,6 +390,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     KnWs w = carve_kn(workspace, g, nf);
+    LBM_REQUIRE(7 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
                 "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
                 (long long)nf);
@@ -316,11 +416,16 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.c_out = p->c_out;
     const double d_ref = p->d_ref_nm / p->voxel_nm;
     LBM_TRY_HIP(hipMemsetAsync(w.counter, 0, sizeof(unsigned long long), s));
+    if (!p->resume) LBM_TRY_HIP(hipMemsetAsync(w.ref, 0, sizeof(double) * (kMaxEdge + 2), s));
     k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, pore_diam, d_ref,
                                                       p->tau_ref, c_init, w.g[cur], w.omega,
                                                       w.csnap, p->resume ? 0 : 1, w.counter,
                                                       w.partials);
     LBM_CHECK_LAUNCH();
+    if (!p->resume) {
+        st = kn_recenter(w, g, nf, h, cur, s);
+        if (st != LBM_OK) return st;
+    }
     st = reduce_partials(w.partials, kn_blocks(nf), 1, w.res + 8, s);
     if (st != LBM_OK) return st;
     unsigned long long bad = 0;
@@ -351,6 +456,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         LBM_TRY_HIP(hipEventRecord(e1, s));
         out = reduce_partials(w.partials, kn_blocks(nf), kKnSums, w.res, s);
         if (out != LBM_OK) break;
+        out = kn_recenter(w, g, nf, h, cur, s);
+        if (out != LBM_OK) break;
         LBM_TRY_HIP(hipMemcpyAsync(sums, w.res, sizeof(sums), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
@@ -376,9 +483,7 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.steps_done = t0 + t;
     LBM_TRY_HIP(hipMemcpyAsync(w.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
     // link-plane fluxes of the final state
-    const double win = (double)(float)(0.125 * p->c_in);
-    const double wout = (double)(float)(0.125 * p->c_out);
-    k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.idmap, w.g[cur], win, wout,
+    k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.idmap, w.g[cur], w.shm,
                                                       w.plane);
     LBM_CHECK_LAUNCH();
     double planes[kMaxEdge + 1];
@@ -478,6 +583,7 @@ extern "C" lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const
     LBM_TRY_HIP(hipMemcpyAsync(w.samp_vox, vox_h, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
     k_kn_sample<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(g, count, w.stride, w.samp_vox,
                                                                w.idmap, w.g[h.cur], w.omega,
+                                                               w.ref,
                                                                w.samp_out, w.samp_flag);
     LBM_CHECK_LAUNCH();
     std::vector<double> tmp((size_t)count * 8);
