@@ -97,6 +97,27 @@ def roofline_512(lbm, W, steps):
             "mlups": nf / (ms * 1e3)}
 
 
+def copy_ceiling(lbm, nbytes=1 << 30, reps=5):
+    """Attainable HBM bandwidth: the library's streaming copy kernel on `nbytes` buffers,
+    read + write bytes per second from HIP events on the current stream (best of reps)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    lbm.lbm_copy_probe(dst, src)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        lbm.lbm_copy_probe(dst, src)
+        e1.record(s)
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return round(best, 1)
+
+
 def cpu_baseline(W, w, steps):
     """The FP64 oracle on a bounded sample of the workload: the whole geometry stage plus
     `steps` steps of each lattice (instead of running to convergence)."""
@@ -147,14 +168,11 @@ def main():
     torch.cuda.set_device(0)
     lbm.load()
     if args.only_512:
-        src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        # counter calibration: three 2 GiB copies by the library's copy kernel
+        ceiling = copy_ceiling(lbm, 1 << 31, 3)
         print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
-                          "copy_bytes_each_way": 1 << 31}), flush=True)
+                          "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
+                          "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
         return
     w = W.WORKLOADS[args.workload]
     log("workload", w["name"])
@@ -212,6 +230,8 @@ def main():
     if not args.no_512:
         log("512^3 roofline")
         out["roofline_512"] = roofline_512(lbm, W, args.roofline_steps)
+    log("copy ceiling")
+    out["attainable_copy_gbs"] = copy_ceiling(lbm)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(W, w, args.cpu_steps)

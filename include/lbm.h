@@ -63,6 +63,17 @@ typedef int32_t lbm_status;
 /* population storage of the flow solve */
 #define LBM_STORE_FP32 0 /* f - w_i in binary32 */
 
+/* sweep kernel variant (the `variant` field of the solve parameters): 0 lets the library
+ * choose from the working-set size; otherwise LBM_VARIANT_EXPLICIT plus any of
+ *   LBM_VARIANT_REMAP   workgroups ordered so that each XCD walks one contiguous region
+ *   LBM_VARIANT_NTSTORE non-temporal (streaming) population stores
+ * All variants compute identical results; they differ only in speed.  Any other bit
+ * (2 included) is rejected with LBM_E_INVAL. */
+#define LBM_VARIANT_AUTO 0
+#define LBM_VARIANT_EXPLICIT 1
+#define LBM_VARIANT_REMAP 4
+#define LBM_VARIANT_NTSTORE 8
+
 /* ------------------------------------------------------------------------------
  * Reconstruction (Section 2, Steps 1-3): pore spheres with random centres and
  * diameters are placed one by one; a trial must overlap an existing sphere with
@@ -183,7 +194,7 @@ typedef struct {
     double tol;
     double voxel_nm;      /* lattice spacing, for k in m^2 and mD */
     int32_t resume;       /* 1: continue from the state in the workspace */
-    int32_t reserved;
+    int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
 } lbm_flow_params;
 
 typedef struct {
@@ -248,6 +259,8 @@ typedef struct {
     int32_t check_every;
     int32_t resume;
     double tol;
+    int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
+    int32_t reserved;
 } lbm_knudsen_params;
 
 typedef struct {
@@ -301,6 +314,12 @@ lbm_status lbm_workspace_size(int32_t kind, const int32_t n[3], int64_t n_fluid,
 
 const char *lbm_last_error(void);
 const char *lbm_version(void);
+
+/* Measurement aid: copies `bytes` (a multiple of 16) from device buffer src to device
+ * buffer dst with a plain streaming kernel (16-byte loads and stores, grid-stride).  Its
+ * time is the attainable HBM bandwidth the sweeps are compared with, and its byte
+ * counters calibrate FETCH_SIZE / WRITE_SIZE.  The buffers must not overlap. */
+lbm_status lbm_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 /* sizeof() of the parameter and result structs, for bindings to check their mirrors:
  * 0 recon_params, 1 recon_stats, 2 label_stats, 3 flow_params, 4 flow_result,

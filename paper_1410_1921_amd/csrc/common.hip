@@ -79,92 +79,108 @@ lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, doub
 }
 
 // ---------------------------------------------------------------- sparse layout
-// One workgroup per brick, one thread per voxel slot of the brick.
-__device__ inline bool brick_voxel(const Grid &g, int64_t brick, int t, int &x, int &y, int &z) {
-    int bx = (int)(brick % g.nbx);
-    int by = (int)((brick / g.nbx) % g.nby);
-    int bz = (int)(brick / ((int64_t)g.nbx * g.nby));
-    x = (bx << kBrickLog) | (t & (kBrick - 1));
-    y = (by << kBrickLog) | ((t >> kBrickLog) & (kBrick - 1));
-    z = (bz << kBrickLog) | (t >> (2 * kBrickLog));
-    return x < g.nx && y < g.ny && z < g.nz;
+// One wave per row segment: its ballot is the segment's occupancy.  The count goes to
+// the base field until the scan turns it into the segment's first node id.
+__global__ __launch_bounds__(256) void k_seg_count(Grid g, const uint8_t *__restrict__ fluid,
+                                                   RankWord *__restrict__ rank) {
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (sg >= g.nsegs()) return;  // uniform per wave
+    const int sx = (int)(sg % g.nseg);
+    const int64_t row = sg / g.nseg;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const int x = sx * kSeg + lane;
+    const bool flag = x < g.nx && fluid[g.lin(x, y, z)] != 0;
+    const uint64_t ball = __ballot(flag);
+    if (lane == 0) {
+        RankWord r;
+        r.lo = (uint32_t)ball;
+        r.hi = (uint32_t)(ball >> 32);
+        r.base = (uint32_t)__popcll(ball);
+        r.pad = 0;
+        rank[sg] = r;
+    }
 }
 
-__global__ __launch_bounds__(kBrickVox) void k_brick_count(Grid g, const uint8_t *__restrict__ fluid,
-                                                           int32_t *__restrict__ bcount) {
-    int x, y, z;
-    int64_t brick = blockIdx.x;
-    bool in = brick_voxel(g, brick, threadIdx.x, x, y, z);
-    int flag = in && fluid[g.lin(x, y, z)] != 0;
-    int c = __syncthreads_count(flag);
-    if (threadIdx.x == 0) bcount[brick] = c;
+// Row of position r in column order over the padded cross-section; false outside.
+__device__ inline bool column_row(const Grid &g, int64_t r, int &y, int &z) {
+    const int64_t col = r / (kCol * kCol);
+    const int q = (int)(r % (kCol * kCol));
+    z = (int)(col / g.ncy) * kCol + q / kCol;
+    y = (int)(col % g.ncy) * kCol + q % kCol;
+    return y < g.ny && z < g.nz;
 }
 
-// Exclusive scan of nb counts in place, total at [nb]; one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(int32_t *__restrict__ a, int64_t nb) {
+// Exclusive scan, in list order, of the segment counts held in rank[].base, in place;
+// the total goes to *total.  One block of 1024 threads, each over a run of rows.
+__global__ __launch_bounds__(1024) void k_seg_scan(RankWord *__restrict__ rank, Grid g,
+                                                   int32_t *__restrict__ total) {
     __shared__ int64_t part[1024];
-    int64_t per = (nb + 1023) / 1024;
-    int64_t lo = threadIdx.x * per, hi = lo + per < nb ? lo + per : nb;
+    const int64_t nrows = (int64_t)g.ncz * g.ncy * kCol * kCol;
+    const int64_t per = (nrows + 1023) / 1024;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < nrows ? lo + per : nrows;
     int64_t sum = 0;
-    for (int64_t i = lo; i < hi; i++) sum += a[i];
+    int y, z;
+    for (int64_t r = lo; r < hi; r++) {
+        if (!column_row(g, r, y, z)) continue;
+        const int64_t s0 = g.seg(0, y, z);
+        for (int sx = 0; sx < g.nseg; sx++) sum += rank[s0 + sx].base;
+    }
     part[threadIdx.x] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t run = 0;
         for (int i = 0; i < 1024; i++) {
-            int64_t v = part[i];
+            const int64_t v = part[i];
             part[i] = run;
             run += v;
         }
-        a[nb] = (int32_t)run;
+        *total = (int32_t)run;
     }
     __syncthreads();
     int64_t run = part[threadIdx.x];
-    for (int64_t i = lo; i < hi; i++) {
-        int32_t v = a[i];
-        a[i] = (int32_t)run;
-        run += v;
+    for (int64_t r = lo; r < hi; r++) {
+        if (!column_row(g, r, y, z)) continue;
+        const int64_t s0 = g.seg(0, y, z);
+        for (int sx = 0; sx < g.nseg; sx++) {
+            const uint32_t v = rank[s0 + sx].base;
+            rank[s0 + sx].base = (uint32_t)run;
+            run += v;
+        }
     }
 }
 
-__global__ __launch_bounds__(kBrickVox) void k_brick_fill(Grid g, const uint8_t *__restrict__ fluid,
-                                                          const int32_t *__restrict__ boff,
-                                                          int32_t *__restrict__ idmap,
-                                                          uint32_t *__restrict__ coords) {
-    __shared__ int wave_tot[kBrickVox / 64];
-    int x, y, z;
-    int64_t brick = blockIdx.x;
-    bool in = brick_voxel(g, brick, threadIdx.x, x, y, z);
-    bool flag = in && fluid[g.lin(x, y, z)] != 0;
-    uint64_t ball = __ballot(flag);
-    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int before = __popcll(ball & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-    if (lane == 0) wave_tot[wave] = __popcll(ball);
-    __syncthreads();
-    int base = boff[brick];
-    for (int w = 0; w < wave; w++) base += wave_tot[w];
-    int32_t id = flag ? base + before : -1;
-    idmap[brick * kBrickVox + threadIdx.x] = id;
-    if (flag) coords[id] = pack_xyz(x, y, z);
+__global__ __launch_bounds__(256) void k_seg_fill(Grid g, const RankWord *__restrict__ rank,
+                                                  uint32_t *__restrict__ coords) {
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (sg >= g.nsegs()) return;
+    const RankWord w = rank[sg];
+    const uint64_t bits = (uint64_t)w.hi << 32 | w.lo;
+    if (!((bits >> lane) & 1)) return;
+    const int sx = (int)(sg % g.nseg);
+    const int64_t row = sg / g.nseg;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const uint32_t id = w.base + (uint32_t)__popcll(bits & ((1ull << lane) - 1));
+    coords[id] = pack_xyz(sx * kSeg + lane, y, z);
 }
 
-lbm_status layout_count(const Grid &g, const uint8_t *fluid, int32_t *bcount, int64_t *nf_h,
-                        hipStream_t s) {
-    int64_t nb = g.nbricks();
-    k_brick_count<<<(unsigned)nb, kBrickVox, 0, s>>>(g, fluid, bcount);
+lbm_status layout_count(const Grid &g, const uint8_t *fluid, RankWord *rank, int32_t *total_d,
+                        int64_t *nf_h, hipStream_t s) {
+    const int64_t blocks = (g.nsegs() + 3) / 4;
+    k_seg_count<<<(unsigned)blocks, 256, 0, s>>>(g, fluid, rank);
     LBM_CHECK_LAUNCH();
-    k_scan<<<1, 1024, 0, s>>>(bcount, nb);
+    k_seg_scan<<<1, 1024, 0, s>>>(rank, g, total_d);
     LBM_CHECK_LAUNCH();
     int32_t total = 0;
-    LBM_TRY_HIP(hipMemcpyAsync(&total, bcount + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipMemcpyAsync(&total, total_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
     *nf_h = total;
     return LBM_OK;
 }
 
-lbm_status layout_fill(const Grid &g, const uint8_t *fluid, const int32_t *boff, int32_t *idmap,
-                       uint32_t *coords, hipStream_t s) {
-    k_brick_fill<<<(unsigned)g.nbricks(), kBrickVox, 0, s>>>(g, fluid, boff, idmap, coords);
+lbm_status layout_fill(const Grid &g, const RankWord *rank, uint32_t *coords, hipStream_t s) {
+    k_seg_fill<<<(unsigned)((g.nsegs() + 3) / 4), 256, 0, s>>>(g, rank, coords);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }

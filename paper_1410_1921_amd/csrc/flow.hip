@@ -6,6 +6,7 @@
 // populations: the flow signal lives in deviations of order 1e-6 from w_i, which
 // binary32 keeps to ~1e-13 absolute once the constant w_i is removed).  Two buffers,
 // ping-pong.  Per fluid-node update the method moves 19 loads + 19 stores of 4 bytes.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -33,13 +34,15 @@ struct FlowHeader {
     int32_t nx, ny, nz, cur;
     int64_t n_fluid, steps_done;
     double tau, force[3];
+    int32_t variant, reserved;
 };
 
 struct FlowWs {
     FlowHeader *hdr;
     unsigned long long *counter;
     double *res;
-    int32_t *bcount, *idmap;
+    int32_t *total;
+    RankWord *rank;
     int64_t *samp_vox;
     double *samp_out;
     uint8_t *samp_flag;
@@ -59,8 +62,8 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf) {
     w.hdr = c.take<FlowHeader>(1);
     w.counter = c.take<unsigned long long>(4);
     w.res = c.take<double>(32);
-    w.bcount = c.take<int32_t>(g.nbricks() + 1);
-    w.idmap = c.take<int32_t>(g.nbricks() * kBrickVox);
+    w.total = c.take<int32_t>(1);
+    w.rank = c.take<RankWord>(g.nsegs());
     w.samp_vox = c.take<int64_t>(kSampleMax);
     w.samp_out = c.take<double>((size_t)kSampleMax * 19);
     w.samp_flag = c.take<uint8_t>(kSampleMax);
@@ -81,10 +84,11 @@ struct Sweep19 {
     Grid g;
     int64_t nf, stride, launched;
     const uint32_t *__restrict__ coords;
-    const int32_t *__restrict__ idmap;
+    const RankWord *__restrict__ rank;
     const float *__restrict__ src;
     float *__restrict__ dst;
     float omega, fpre, Fx, Fy, Fz;
+    int remap;                         // XCD-contiguous workgroup order
     // check variant
     float *__restrict__ usnap;
     float *__restrict__ u_out;
@@ -92,101 +96,125 @@ struct Sweep19 {
     int update_snap;
 };
 
-// One stream-collide step for one fluid node per thread.  CHECK also forms the FP64
-// partial sums of the convergence check and writes the velocity snapshot / field.
-template <bool CHECK>
-__global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
+// Kernel variants (chosen per solve from the working-set size, or forced):
+//   REMAP: XCD-contiguous workgroup order, so neighbouring rows share an L2;
+//   NT: populations are written with streaming (non-temporal) stores; right when the
+//     arrays far exceed the 256 MB Infinity Cache, wrong when they fit in it.
+
+// The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
+// the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
+template <bool CHECK, bool NT>
+__device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
+                              const int (&ids)[19], double (&acc)[kFlowSums]) {
     LBM_D3Q19_TABLES
     constexpr float W0 = 1.0f / 3.0f, W1 = 1.0f / 18.0f, W2 = 1.0f / 36.0f;
-    const int64_t lb = xcd_block(blockIdx.x, a.launched);
+    uint32_t off[19];
+    off[0] = (uint32_t)n;
+#pragma unroll
+    for (int i = 1; i < 19; i++)
+        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+    float f[19];
+#pragma unroll
+    for (int i = 0; i < 19; i++) f[i] = a.src[off[i]];
+
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        drho += f[i];
+        if (EX[i]) jx += EX[i] > 0 ? f[i] : -f[i];
+        if (EY[i]) jy += EY[i] > 0 ? f[i] : -f[i];
+        if (EZ[i]) jz += EZ[i] > 0 ? f[i] : -f[i];
+    }
+    const float rho = 1.0f + drho;
+    const float inv = 1.0f / rho;
+    const float mx = jx + 0.5f * a.Fx, my = jy + 0.5f * a.Fy, mz = jz + 0.5f * a.Fz;
+    const float ux = mx * inv, uy = my * inv, uz = mz * inv;
+    const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+    const float uF = ux * a.Fx + uy * a.Fy + uz * a.Fz;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        const float w = i == 0 ? W0 : (i < 7 ? W1 : W2);
+        const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        const float eF = EX[i] * a.Fx + EY[i] * a.Fy + EZ[i] * a.Fz;
+        const float feq = w * (drho + rho * (3.0f * eu + 4.5f * eu * eu - uu15));
+        const float src = a.fpre * w * (3.0f * (eF - uF) + 9.0f * eu * eF);
+        const float out = f[i] - a.omega * (f[i] - feq) + src;
+        if (NT)
+            __builtin_nontemporal_store(out, &a.dst[(int64_t)i * a.stride + n]);
+        else
+            a.dst[(int64_t)i * a.stride + n] = out;
+    }
+    if (CHECK) {
+        const double dux = (double)ux - (double)a.usnap[n];
+        const double duy = (double)uy - (double)a.usnap[a.stride + n];
+        const double duz = (double)uz - (double)a.usnap[2 * a.stride + n];
+        acc[0] += dux * dux + duy * duy + duz * duz;
+        acc[1] += (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        acc[2] += (double)jx + 0.5 * (double)a.Fx;
+        acc[3] += (double)jy + 0.5 * (double)a.Fy;
+        acc[4] += (double)jz + 0.5 * (double)a.Fz;
+        acc[5] += drho;
+        if (a.update_snap) {
+            a.usnap[n] = ux;
+            a.usnap[a.stride + n] = uy;
+            a.usnap[2 * a.stride + n] = uz;
+        }
+        if (a.u_out) {
+            const int64_t v = a.g.lin(x, y, z), nv = a.g.nvox();
+            a.u_out[v] = ux;
+            a.u_out[nv + v] = uy;
+            a.u_out[2 * nv + v] = uz;
+        }
+    }
+}
+
+template <int NV>
+__device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid, double *part) {
+    __shared__ double lds[4 * NV];
+    double out[NV];
+    block_sum<NV>(acc, lds, out);
+    if (threadIdx.x == 0 && valid)
+#pragma unroll
+        for (int k = 0; k < NV; k++) part[row * NV + k] = out[k];
+}
+
+// One stream-collide step, one fluid node per thread, neighbour ids gathered from the
+// global id map.  CHECK also forms the FP64 partial sums of the convergence check and
+// writes the velocity snapshot / field.
+template <bool CHECK, bool NT>
+__global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
+    LBM_D3Q19_TABLES
+    const int64_t lb = a.remap ? xcd_block(blockIdx.x, a.launched) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
     if (n < a.nf) {
         const uint32_t c = a.coords[n];
         const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
         const Grid &g = a.g;
-        // per-axis pieces of the brick-major slot of x-1, x, x+1 (periodic), etc.
+        // per-axis pieces of the rank word and bit of x-1, x, x+1 (periodic), etc.
         int xs[3], ys[3], zs[3];
         xs[0] = x == 0 ? g.nx - 1 : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? 0 : x + 1;
         ys[0] = y == 0 ? g.ny - 1 : y - 1; ys[1] = y; ys[2] = y == g.ny - 1 ? 0 : y + 1;
         zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
-        int sx[3], sy[3], sz[3];
+        int wx[3], wy[3], wz[3], bx[3];
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            sx[k] = ((xs[k] >> kBrickLog) << 9) | (xs[k] & (kBrick - 1));
-            sy[k] = ((ys[k] >> kBrickLog) * g.nbx << 9) | ((ys[k] & (kBrick - 1)) << kBrickLog);
-            sz[k] = ((zs[k] >> kBrickLog) * g.nbx * g.nby << 9) | ((zs[k] & (kBrick - 1)) << (2 * kBrickLog));
+            wx[k] = xs[k] >> kSegLog;
+            wy[k] = ys[k] * g.nseg;
+            wz[k] = zs[k] * (g.ny * g.nseg);
+            bx[k] = xs[k] & (kSeg - 1);
         }
-        // three phases, so that each one's loads are all in flight together: the 18
-        // neighbour ids, then the 19 populations (pull from x - e_i; bounce back from
-        // the node itself when that neighbour is solid)
+        // the 18 rank words are loaded as one batch, then the 19 populations as another
+        RankWord rw[19];
+#pragma unroll
+        for (int i = 1; i < 19; i++) rw[i] = a.rank[wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]]];
         int ids[19];
+        ids[0] = 0;
 #pragma unroll
-        for (int i = 1; i < 19; i++)
-            ids[i] = a.idmap[sx[1 - EX[i]] + sy[1 - EY[i]] + sz[1 - EZ[i]]];
-        uint32_t off[19];
-        off[0] = (uint32_t)n;
-#pragma unroll
-        for (int i = 1; i < 19; i++)
-            off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
-        float f[19];
-#pragma unroll
-        for (int i = 0; i < 19; i++) f[i] = a.src[off[i]];
-
-        float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-        for (int i = 0; i < 19; i++) {
-            drho += f[i];
-            if (EX[i]) jx += EX[i] > 0 ? f[i] : -f[i];
-            if (EY[i]) jy += EY[i] > 0 ? f[i] : -f[i];
-            if (EZ[i]) jz += EZ[i] > 0 ? f[i] : -f[i];
-        }
-        const float rho = 1.0f + drho;
-        const float inv = 1.0f / rho;
-        const float mx = jx + 0.5f * a.Fx, my = jy + 0.5f * a.Fy, mz = jz + 0.5f * a.Fz;
-        const float ux = mx * inv, uy = my * inv, uz = mz * inv;
-        const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-        const float uF = ux * a.Fx + uy * a.Fy + uz * a.Fz;
-#pragma unroll
-        for (int i = 0; i < 19; i++) {
-            const float w = i == 0 ? W0 : (i < 7 ? W1 : W2);
-            const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-            const float eF = EX[i] * a.Fx + EY[i] * a.Fy + EZ[i] * a.Fz;
-            const float feq = w * (drho + rho * (3.0f * eu + 4.5f * eu * eu - uu15));
-            const float src = a.fpre * w * (3.0f * (eF - uF) + 9.0f * eu * eF);
-            a.dst[(int64_t)i * a.stride + n] = f[i] - a.omega * (f[i] - feq) + src;
-        }
-        if (CHECK) {
-            const double dux = (double)ux - (double)a.usnap[n];
-            const double duy = (double)uy - (double)a.usnap[a.stride + n];
-            const double duz = (double)uz - (double)a.usnap[2 * a.stride + n];
-            acc[0] = dux * dux + duy * duy + duz * duz;
-            acc[1] = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-            acc[2] = (double)jx + 0.5 * (double)a.Fx;
-            acc[3] = (double)jy + 0.5 * (double)a.Fy;
-            acc[4] = (double)jz + 0.5 * (double)a.Fz;
-            acc[5] = drho;
-            if (a.update_snap) {
-                a.usnap[n] = ux;
-                a.usnap[a.stride + n] = uy;
-                a.usnap[2 * a.stride + n] = uz;
-            }
-            if (a.u_out) {
-                const int64_t v = g.lin(x, y, z), nv = g.nvox();
-                a.u_out[v] = ux;
-                a.u_out[nv + v] = uy;
-                a.u_out[2 * nv + v] = uz;
-            }
-        }
+        for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
+        node19<CHECK, NT>(a, n, x, y, z, ids, acc);
     }
-    if (CHECK) {
-        __shared__ double lds[4 * kFlowSums];
-        double out[kFlowSums];
-        block_sum<kFlowSums>(acc, lds, out);
-        if (threadIdx.x == 0 && lb * 256 < a.nf)
-#pragma unroll
-            for (int k = 0; k < kFlowSums; k++) a.partials[lb * kFlowSums + k] = out[k];
-    }
+    if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
 // f - w_i at the equilibrium of rho = 1 and u_init (zero without it); the snapshot
@@ -216,33 +244,62 @@ __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t s
 }
 
 __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
-                              const int64_t *__restrict__ vox, const int32_t *__restrict__ idmap,
+                              const int64_t *__restrict__ vox, const RankWord *__restrict__ rank,
                               const float *__restrict__ f, double *__restrict__ out,
                               uint8_t *__restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
     const int64_t v = vox[s];
     const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
-    const int id = idmap[g.slot(x, y, z)];
+    const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
     for (int i = 0; i < 19; i++) out[s * 19 + i] = id >= 0 ? (double)f[(int64_t)i * stride + id] : 0.0;
 }
 
+// Kernel variant: explicit bits, or chosen from the working set: when the two
+// population arrays exceed ~3/4 of the 256 MB Infinity Cache the sweep streams from HBM
+// (plain workgroup order, non-temporal stores), otherwise it keeps the state in the cache
+// (XCD-contiguous order, ordinary stores).
+struct Variant19 {
+    bool remap, nt;
+};
+
+static Variant19 pick_variant(int32_t v, int64_t stride) {
+    Variant19 m;
+    if (v & LBM_VARIANT_EXPLICIT) {
+        m.remap = v & LBM_VARIANT_REMAP;
+        m.nt = v & LBM_VARIANT_NTSTORE;
+        return m;
+    }
+    const bool stream = 2.0 * 19 * 4 * (double)stride > 192e6;
+    m.remap = !stream;
+    m.nt = stream;
+    return m;
+}
+
+template <bool CHECK>
+static void launch19(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
+    const unsigned grid = (unsigned)a.launched;
+    if (m.nt) k_sweep19<CHECK, true><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<CHECK, false><<<grid, 256, 0, s>>>(a);
+}
+
 static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, const FlowHeader &h,
-                                int &cur, int64_t steps, bool check_last, float *u_out,
-                                hipStream_t s) {
+                                const Variant19 &m, int &cur, int64_t steps, bool check_last,
+                                float *u_out, hipStream_t s) {
     Sweep19 a;
     a.g = g;
     a.nf = nf;
     a.stride = w.stride;
     a.launched = xcd_launch(blocks_for(nf));
     a.coords = w.coords;
-    a.idmap = w.idmap;
+    a.rank = w.rank;
     a.omega = (float)(1.0 / h.tau);
     a.fpre = (float)(1.0 - 0.5 / h.tau);
     a.Fx = (float)h.force[0];
     a.Fy = (float)h.force[1];
     a.Fz = (float)h.force[2];
+    a.remap = m.remap;
     a.usnap = w.usnap;
     a.u_out = u_out;
     a.partials = w.partials;
@@ -251,9 +308,9 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
         if (check_last && t == steps - 1)
-            k_sweep19<true><<<(unsigned)a.launched, 256, 0, s>>>(a);
+            launch19<true>(a, m, s);
         else
-            k_sweep19<false><<<(unsigned)a.launched, 256, 0, s>>>(a);
+            launch19<false>(a, m, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
@@ -290,6 +347,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32, LBM_E_INVAL, "unknown storage %d", p->storage);
+    LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
+                p->variant);
     st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -300,7 +359,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
-    st = layout_count(g, fluid, w0.bcount, &nf, s);
+    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     FlowWs w = carve_flow(workspace, g, nf);
@@ -322,12 +381,15 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         t0 = h.steps_done;
         cur = h.cur;
     }
-    st = layout_fill(g, fluid, w.bcount, w.idmap, w.coords, s);
+    st = layout_fill(g, w.rank, w.coords, s);
     if (st != LBM_OK) return st;
     h.magic = kFlowMagic;
     h.nx = n[0]; h.ny = n[1]; h.nz = n[2];
     h.n_fluid = nf;
     h.tau = p->tau;
+    h.variant = p->variant;
+    h.reserved = 0;
+    const Variant19 mode = pick_variant(p->variant, w.stride);
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
         k_flow_init<<<(unsigned)blocks_for(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, u_init,
@@ -352,7 +414,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         int64_t chunk = nc - (abs_t % nc);
         if (chunk > limit - t) chunk = limit - t;
         LBM_TRY_HIP(hipEventRecord(e0, s));
-        out = launch_sweeps(w, g, nf, h, cur, chunk, true, u_out, s);
+        out = launch_sweeps(w, g, nf, h, mode, cur, chunk, true, u_out, s);
         if (out != LBM_OK) break;
         LBM_TRY_HIP(hipEventRecord(e1, s));
         out = reduce_partials(w.partials, blocks_for(nf), kFlowSums, w.res, s);
@@ -433,7 +495,8 @@ extern "C" lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t st
     if (st != LBM_OK) return st;
     LBM_REQUIRE(steps >= 0, LBM_E_INVAL, "negative step count");
     int cur = h.cur;
-    st = launch_sweeps(w, g, h.n_fluid, h, cur, steps, false, nullptr, s);
+    st = launch_sweeps(w, g, h.n_fluid, h, pick_variant(h.variant, w.stride), cur, steps, false,
+                       nullptr, s);
     if (st != LBM_OK) return st;
     h.cur = cur;
     h.steps_done += steps;
@@ -459,7 +522,7 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
                     (long long)vox_h[i]);
     LBM_TRY_HIP(hipMemcpyAsync(w.samp_vox, vox_h, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
     k_flow_sample<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(g, count, w.stride, w.samp_vox,
-                                                                 w.idmap, w.f[h.cur], w.samp_out,
+                                                                 w.rank, w.f[h.cur], w.samp_out,
                                                                  w.samp_flag);
     LBM_CHECK_LAUNCH();
     LBM_TRY_HIP(hipMemcpyAsync(f_h, w.samp_out, sizeof(double) * 19 * count, hipMemcpyDeviceToHost, s));

@@ -4,14 +4,17 @@
 // 3.3), and the outlet-plane flux of Eq. 14.
 //
 // Storage: s[i][node] = g_i - w_i C_ref(x) in binary32, where C_ref(x) is a reference
-// profile along x: the mean concentration of plane x, refreshed at every convergence
-// check (ghost planes: C_ref(-1) = C_in, C_ref(nx) = C_out).  The collision is carried
-// out on these deviations, so rounding acts on numbers far smaller than g itself: both
-// the transient front and the steady state keep binary32 errors near 1e-7 relative,
-// where storing g directly freezes the iteration (per-step changes below half an ulp)
-// up to ~1e-3 away from its steady state on long channels.  The reference costs no
-// bandwidth: it depends on x alone (a table of nx + 2 values).  1/tau_g per node in
-// binary32.  Per fluid-node update: 7 loads + 7 stores of 4 bytes + 4 bytes of 1/tau_g.
+// profile along x (the "frame" of the state): the mean concentration of plane x at the
+// latest convergence check (ghost planes: C_ref(-1) = C_in, C_ref(nx) = C_out).  The
+// collision is carried out on these deviations, so rounding acts on numbers far smaller
+// than g itself: both the transient front and the steady state keep binary32 errors
+// near 1e-7 relative, where storing g directly freezes the iteration (per-step changes
+// below half an ulp) up to ~1e-3 away from its steady state on long channels.
+// A new frame costs no extra pass: the first sweep after a check reads the state in the
+// old frame and writes it in the new one, through a per-x table of reference shifts.
+// 1/tau_g per node in binary32.  Per fluid-node update: 7 loads + 7 stores of 4 bytes +
+// 4 bytes of 1/tau_g.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -23,16 +26,27 @@ namespace lbm {
 // D3Q7: rest, then +x, -x, +y, -y, +z, -z.
 #define LBM_D3Q7_TABLES [[maybe_unused]] constexpr int OPP[7] = {0, 2, 1, 4, 3, 6, 5};
 
-constexpr uint64_t kKnMagic = 0x4c424d4b4e554431ull;  // "LBMKNUD1"
+constexpr uint64_t kKnMagic = 0x4c424d4b4e554432ull;  // "LBMKNUD2"
 constexpr int kKnSums = 5;  // |dC|^2, C^2, Phi_out, Phi_in, C
 constexpr int kKnSampleMax = 65536;
 constexpr float kW0 = 0.25f, kW1 = 0.125f;
+constexpr int kPlaneParts = 16;  // workgroups per plane in the plane-mean pass
 
 struct KnHeader {
     uint64_t magic;
     int32_t nx, ny, nz, cur;
     int64_t n_fluid, steps_done;
     double c_in, c_out;
+    int32_t frame;    // reference profile the stored state is relative to
+    int32_t variant;  // LBM_VARIANT_* of the solve
+};
+
+// Reference shifts for a sweep from frame `in` to frame `out`, per x (index x + 1):
+// t0 = w_1 (ref_in(x) - ref_out(x))      rest (x2), y/z and bounced populations
+// tm = w_1 (ref_in(x - 1) - ref_out(x))  +x population streamed from x - 1
+// tp = w_1 (ref_in(x + 1) - ref_out(x))  -x population streamed from x + 1
+struct Shift {
+    float t0, tm, tp, pad;
 };
 
 struct KnWs {
@@ -40,7 +54,8 @@ struct KnWs {
     unsigned long long *counter;
     double *res;
     double *plane;
-    int32_t *bcount, *idmap;
+    int32_t *total;
+    RankWord *rank;
     int64_t *samp_vox;
     double *samp_out;
     uint8_t *samp_flag;
@@ -49,8 +64,10 @@ struct KnWs {
     float *omega;
     float *csnap;
     double *partials;
-    double *ref, *ref_new;  // reference profile C_ref(x), index x + 1 for x = -1..nx
-    float *shm, *shp;       // w_1 (C_ref(x -+ 1) - C_ref(x)), index x + 1
+    double *ref[2];    // the two reference profiles, index x + 1 for x = -1..nx
+    Shift *steady[2];  // shifts within each frame (t0 = 0)
+    Shift *trans;      // shifts from the current frame to the other one
+    double *part;      // plane-mean partial sums [nx][kPlaneParts][2]
     int64_t stride;
     size_t bytes;
 };
@@ -64,11 +81,15 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     w.counter = c.take<unsigned long long>(4);
     w.res = c.take<double>(32);
     w.plane = c.take<double>(kMaxEdge + 1);
-    w.bcount = c.take<int32_t>(g.nbricks() + 1);
-    w.idmap = c.take<int32_t>(g.nbricks() * kBrickVox);
+    w.total = c.take<int32_t>(1);
+    w.rank = c.take<RankWord>(g.nsegs());
     w.samp_vox = c.take<int64_t>(kKnSampleMax);
     w.samp_out = c.take<double>((size_t)kKnSampleMax * 8);
     w.samp_flag = c.take<uint8_t>(kKnSampleMax);
+    for (int f = 0; f < 2; f++) w.ref[f] = c.take<double>(kMaxEdge + 2);
+    for (int f = 0; f < 2; f++) w.steady[f] = c.take<Shift>(kMaxEdge + 2);
+    w.trans = c.take<Shift>(kMaxEdge + 2);
+    w.part = c.take<double>((size_t)kMaxEdge * kPlaneParts * 2);
     int64_t nfp = nf < 1 ? 1 : nf;
     w.stride = (nfp + 63) / 64 * 64;
     w.coords = c.take<uint32_t>(nfp);
@@ -77,10 +98,6 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     w.omega = c.take<float>(w.stride);
     w.csnap = c.take<float>(w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(kn_blocks(nfp)) * kKnSums);
-    w.ref = c.take<double>(kMaxEdge + 2);
-    w.ref_new = c.take<double>(kMaxEdge + 2);
-    w.shm = c.take<float>(kMaxEdge + 2);
-    w.shp = c.take<float>(kMaxEdge + 2);
     w.bytes = c.off;
     return w;
 }
@@ -94,23 +111,88 @@ struct Sweep7 {
     Grid g;
     int64_t nf, stride, launched;
     const uint32_t *__restrict__ coords;
-    const int32_t *__restrict__ idmap;
+    const RankWord *__restrict__ rank;
     const float *__restrict__ omega;
     const float *__restrict__ src;
     float *__restrict__ dst;
-    const float *__restrict__ shm;  // change of reference along a +x link into x
-    const float *__restrict__ shp;  // change of reference along a -x link into x
+    const Shift *__restrict__ shift;
+    int remap;                         // XCD-contiguous workgroup order
     // check variant
-    const double *__restrict__ ref;
+    const double *__restrict__ ref_out;
     float *__restrict__ csnap;
     float *__restrict__ c_out;
     double *__restrict__ partials;
 };
 
-template <bool CHECK>
-__global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
+// The update of fluid node n at (x, y, z) with its 6 pull sources resolved: ids[i] is the
+// node at x - e_i, -1 when that voxel is solid (bounce back), -2 beyond an x face (ghost
+// plane).
+template <bool CHECK, bool NT>
+__device__ inline void node7(const Sweep7 &a, int64_t n, int x, int y, int z, const int (&ids)[7],
+                             double (&acc)[kKnSums]) {
     LBM_D3Q7_TABLES
-    const int64_t lb = xcd_block(blockIdx.x, a.launched);
+    const float om = a.omega[n];
+    const Shift sh = a.shift[x + 1];
+    uint32_t off[7];
+    off[0] = (uint32_t)n;
+#pragma unroll
+    for (int i = 1; i < 7; i++)
+        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+    float ai[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) ai[i] = a.src[off[i]];
+    // incoming deviations, moved onto this node's output reference w_i C_ref(x): a
+    // population streamed along +-x from a fluid neighbour (or a ghost plane, whose
+    // deviation is 0) also changes plane
+    if (ids[1] == -2) ai[1] = 0.f;
+    if (ids[2] == -2) ai[2] = 0.f;
+    ai[0] += 2.f * sh.t0;
+    ai[1] += ids[1] == -1 ? sh.t0 : sh.tm;
+    ai[2] += ids[2] == -1 ? sh.t0 : sh.tp;
+#pragma unroll
+    for (int i = 3; i < 7; i++) ai[i] += sh.t0;
+    float cdev = 0.f;  // C - C_ref(x)
+#pragma unroll
+    for (int i = 0; i < 7; i++) cdev += ai[i];
+    float so[7];
+#pragma unroll
+    for (int i = 0; i < 7; i++) {
+        const float w = i == 0 ? kW0 : kW1;
+        so[i] = ai[i] - om * (ai[i] - w * cdev);
+        if (NT)
+            __builtin_nontemporal_store(so[i], &a.dst[(int64_t)i * a.stride + n]);
+        else
+            a.dst[(int64_t)i * a.stride + n] = so[i];
+    }
+    if (CHECK) {
+        const double conc = a.ref_out[x + 1] + (double)cdev;
+        const double d = conc - (double)a.csnap[n];
+        acc[0] += d * d;
+        acc[1] += conc * conc;
+        // net +x flux into the outlet ghost plane and out of the inlet one, as streamed
+        // (both sides in the node's output frame)
+        if (ids[2] == -2) acc[2] += (double)so[1] - (double)sh.tp;
+        if (ids[1] == -2) acc[3] += (double)sh.tm - (double)so[2];
+        acc[4] += conc;
+        a.csnap[n] = (float)conc;
+        if (a.c_out) a.c_out[a.g.lin(x, y, z)] = (float)conc;
+    }
+}
+
+template <int NV>
+__device__ inline void write_partials7(double (&acc)[NV], int64_t row, bool valid, double *part) {
+    __shared__ double lds[4 * NV];
+    double out[NV];
+    block_sum<NV>(acc, lds, out);
+    if (threadIdx.x == 0 && valid)
+#pragma unroll
+        for (int k = 0; k < NV; k++) part[row * NV + k] = out[k];
+}
+
+// One step, one fluid node per thread, neighbour ids found through the rank map.
+template <bool CHECK, bool NT>
+__global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
+    const int64_t lb = a.remap ? xcd_block(blockIdx.x, a.launched) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
     if (n < a.nf) {
@@ -120,75 +202,29 @@ __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
         const int xm = x - 1, xp = x + 1;  // ghost planes beyond the x faces
         const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
         const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        // neighbour slots in direction order 1..6 (source x - e_i); beyond an x face the
-        // slot of the node itself stands in, its id is replaced by -2 (ghost plane)
-        int slot[7];
-        slot[1] = (int)g.slot(xm >= 0 ? xm : x, y, z);
-        slot[2] = (int)g.slot(xp < g.nx ? xp : x, y, z);
-        slot[3] = (int)g.slot(x, ym, z);
-        slot[4] = (int)g.slot(x, yp, z);
-        slot[5] = (int)g.slot(x, y, zm);
-        slot[6] = (int)g.slot(x, y, zp);
-        // phase 1: ids, 1/tau_g and the link shifts, all in flight together
-        int ids[7];
+        // neighbour voxels in direction order 1..6 (source x - e_i); beyond an x face the
+        // node itself stands in, its id is replaced by -2 (ghost plane)
+        const int x1 = xm >= 0 ? xm : x, x2 = xp < g.nx ? xp : x;
+        const int nxs[7] = {x, x1, x2, x, x, x, x};
+        const int nys[7] = {y, y, y, ym, yp, y, y};
+        const int nzs[7] = {z, z, z, z, z, zm, zp};
+        RankWord rw[7];
 #pragma unroll
-        for (int i = 1; i < 7; i++) ids[i] = a.idmap[slot[i]];
-        const float om = a.omega[n];
-        const float sm = a.shm[x + 1], sp = a.shp[x + 1];
+        for (int i = 1; i < 7; i++) rw[i] = a.rank[g.seg(nxs[i], nys[i], nzs[i])];
+        int ids[7];
+        ids[0] = 0;
+#pragma unroll
+        for (int i = 1; i < 7; i++) ids[i] = rank_lookup(rw[i], nxs[i] & (kSeg - 1));
         if (xm < 0) ids[1] = -2;
         if (xp >= g.nx) ids[2] = -2;
-        // phase 2: the populations (id -1: solid, bounce back; -2: ghost plane)
-        uint32_t off[7];
-        off[0] = (uint32_t)n;
-#pragma unroll
-        for (int i = 1; i < 7; i++)
-            off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
-        float ai[7];
-#pragma unroll
-        for (int i = 0; i < 7; i++) ai[i] = a.src[off[i]];
-        // incoming deviations from this node's reference w_i C_ref(x): a population
-        // streamed along +-x from a fluid neighbour (or a ghost plane, whose deviation is
-        // 0) changes reference plane; bounced and y/z populations keep theirs
-        if (ids[1] == -2) ai[1] = 0.f;
-        if (ids[2] == -2) ai[2] = 0.f;
-        if (ids[1] != -1) ai[1] += sm;
-        if (ids[2] != -1) ai[2] += sp;
-        float cdev = 0.f;  // C - C_ref(x)
-#pragma unroll
-        for (int i = 0; i < 7; i++) cdev += ai[i];
-        float so[7];
-#pragma unroll
-        for (int i = 0; i < 7; i++) {
-            const float w = i == 0 ? kW0 : kW1;
-            so[i] = ai[i] - om * (ai[i] - w * cdev);
-            a.dst[(int64_t)i * a.stride + n] = so[i];
-        }
-        if (CHECK) {
-            const double conc = a.ref[x + 1] + (double)cdev;
-            const double d = conc - (double)a.csnap[n];
-            acc[0] = d * d;
-            acc[1] = conc * conc;
-            // net +x flux into the outlet ghost plane and out of the inlet one, as
-            // streamed (in the node's reference frame)
-            if (xp >= g.nx) acc[2] = (double)so[1] - (double)sp;
-            if (xm < 0) acc[3] = (double)sm - (double)so[2];
-            acc[4] = conc;
-            a.csnap[n] = (float)conc;
-            if (a.c_out) a.c_out[g.lin(x, y, z)] = (float)conc;
-        }
+        node7<CHECK, NT>(a, n, x, y, z, ids, acc);
     }
-    if (CHECK) {
-        __shared__ double lds[4 * kKnSums];
-        double out[kKnSums];
-        block_sum<kKnSums>(acc, lds, out);
-        if (threadIdx.x == 0 && lb * 256 < a.nf)
-#pragma unroll
-            for (int k = 0; k < kKnSums; k++) a.partials[lb * kKnSums + k] = out[k];
-    }
+    if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
 // 1/tau_g per node from the pore diameter (Eq. 12); counts nodes with tau_g <= 1/2 and
-// forms the partial sums of tau_g - 1/2 (for the local tortuosity).
+// forms the partial sums of tau_g - 1/2 (for the local tortuosity).  With init_pop the
+// populations start at the equilibrium w_i C_init in frame 0 (C_ref = 0 inside).
 __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t stride,
                                                  const uint32_t *__restrict__ coords,
                                                  const double *__restrict__ diam, double d_ref,
@@ -208,8 +244,6 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
         omega[n] = (float)(1.0 / tau);
         acc[0] = tau - 0.5;
         if (init_pop) {
-            // equilibrium w_i C_init against a zero reference; the solve re-centres it
-            // on the plane means before the first step
             const float c0 = c_init ? c_init[v] : 0.f;
             gbuf[n] = kW0 * c0;
             for (int i = 1; i < 7; i++) gbuf[(int64_t)i * stride + n] = kW1 * c0;
@@ -222,61 +256,32 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
     if (threadIdx.x == 0) partials[blockIdx.x] = out[0];
 }
 
-// Net +x flux through the link plane x = px - 1/2 (px = 0..nx), one block per plane,
-// over links with both ends fluid (ghost planes count as fluid).
-__global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
-                                                    const int32_t *__restrict__ idmap,
-                                                    const float *__restrict__ gcur,
-                                                    const float *__restrict__ shm,
-                                                    double *__restrict__ plane) {
-    const int px = blockIdx.x;
-    const int left = px - 1, right = px;
-    double acc[1] = {0.0};
-    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
-        const int y = (int)(k % g.ny), z = (int)(k / g.ny);
-        const int il = left >= 0 ? idmap[g.slot(left, y, z)] : -2;
-        const int ir = right < g.nx ? idmap[g.slot(right, y, z)] : -2;
-        if (il == -1 || ir == -1) continue;
-        // g_{+x}(left) - g_{-x}(right) in the frame of `right`: s_{+x}(left) + shm(right) -
-        // s_{-x}(right); the ghost planes hold zero deviation
-        const double fwd = left >= 0 ? (double)gcur[stride + il] : 0.0;
-        const double bwd = right < g.nx ? (double)gcur[2 * stride + ir] : 0.0;
-        acc[0] += (fwd + (double)shm[right + 1]) - bwd;
+// Frame 0: C_ref = 0 inside, C_in / C_out on the ghost planes, and its steady shifts.
+__global__ __launch_bounds__(1024) void k_frame0(int nx, double c_in, double c_out,
+                                                 double *__restrict__ ref,
+                                                 Shift *__restrict__ steady) {
+    for (int k = threadIdx.x; k < nx + 2; k += 1024)
+        ref[k] = k == 0 ? c_in : (k == nx + 1 ? c_out : 0.0);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nx + 2; k += 1024) {
+        Shift s;
+        s.t0 = 0.f;
+        s.tm = k >= 1 ? (float)(0.125 * (ref[k - 1] - ref[k])) : 0.f;
+        s.tp = k <= nx ? (float)(0.125 * (ref[k + 1] - ref[k])) : 0.f;
+        s.pad = 0.f;
+        steady[k] = s;
     }
-    __shared__ double lds[4];
-    double out[1];
-    block_sum<1>(acc, lds, out);
-    if (threadIdx.x == 0) plane[px] = out[0];
 }
 
-__global__ void k_kn_sample(Grid g, int64_t count, int64_t stride, const int64_t *__restrict__ vox,
-                            const int32_t *__restrict__ idmap, const float *__restrict__ gcur,
-                            const float *__restrict__ omega, const double *__restrict__ cref,
-                            double *__restrict__ out, uint8_t *__restrict__ flag) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= count) return;
-    const int64_t v = vox[s];
-    const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
-    const int id = idmap[g.slot(x, y, z)];
-    flag[s] = id >= 0;
-    const double ref = cref[x + 1];
-    for (int i = 0; i < 7; i++)
-        out[s * 8 + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] + (i ? 0.125 : 0.25) * ref
-                                 : 0.0;
-    out[s * 8 + 7] = id >= 0 ? 1.0 / (double)omega[id] : 0.0;
-}
-
-// The reference profile follows the solution: at each check the plane means of C become
-// the new C_ref (planes without fluid keep theirs), the stored state is moved onto it,
-// and the link shift tables are rebuilt.  All three steps are deterministic.
-__global__ __launch_bounds__(256) void k_plane_mean(Grid g, const int32_t *__restrict__ idmap,
+// Plane sums of the checked concentration, kPlaneParts workgroups per plane.
+__global__ __launch_bounds__(256) void k_plane_mean(Grid g, const RankWord *__restrict__ rank,
                                                     const float *__restrict__ csnap,
-                                                    const double *__restrict__ ref,
-                                                    double *__restrict__ ref_new) {
-    const int x = blockIdx.x;
+                                                    double *__restrict__ part) {
+    const int p = blockIdx.x, x = blockIdx.y;
     double acc[2] = {0.0, 0.0};
-    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
-        const int id = idmap[g.slot(x, (int)(k % g.ny), (int)(k / g.ny))];
+    const int64_t m = (int64_t)g.ny * g.nz;
+    for (int64_t k = (int64_t)p * 256 + threadIdx.x; k < m; k += kPlaneParts * 256) {
+        const int id = node_at(rank, g, x, (int)(k % g.ny), (int)(k / g.ny));
         if (id >= 0) {
             acc[0] += (double)csnap[id];
             acc[1] += 1.0;
@@ -285,72 +290,166 @@ __global__ __launch_bounds__(256) void k_plane_mean(Grid g, const int32_t *__res
     __shared__ double lds[8];
     double out[2];
     block_sum<2>(acc, lds, out);
-    if (threadIdx.x == 0) ref_new[x + 1] = out[1] > 0.0 ? out[0] / out[1] : ref[x + 1];
-}
-
-__global__ __launch_bounds__(256) void k_recenter(int64_t nf, int64_t stride,
-                                                  const uint32_t *__restrict__ coords,
-                                                  const double *__restrict__ ref,
-                                                  const double *__restrict__ ref_new,
-                                                  float *__restrict__ s) {
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (n >= nf) return;
-    const int x = coords[n] & 1023;
-    const double d = ref[x + 1] - ref_new[x + 1];
-    s[n] += (float)(0.25 * d);
-    const float d1 = (float)(0.125 * d);
-    for (int i = 1; i < 7; i++) s[(int64_t)i * stride + n] += d1;
-}
-
-__global__ __launch_bounds__(1024) void k_ref_commit(int nx, double c_in, double c_out,
-                                                     double *__restrict__ ref,
-                                                     const double *__restrict__ ref_new,
-                                                     float *__restrict__ shm,
-                                                     float *__restrict__ shp) {
-    for (int k = threadIdx.x; k < nx + 2; k += 1024)
-        ref[k] = k == 0 ? c_in : (k == nx + 1 ? c_out : ref_new[k]);
-    __syncthreads();
-    for (int k = threadIdx.x; k < nx + 2; k += 1024) {
-        shm[k] = k >= 1 ? (float)(0.125 * (ref[k - 1] - ref[k])) : 0.f;
-        shp[k] = k <= nx ? (float)(0.125 * (ref[k + 1] - ref[k])) : 0.f;
+    if (threadIdx.x == 0) {
+        part[2 * (x * kPlaneParts + p)] = out[0];
+        part[2 * (x * kPlaneParts + p) + 1] = out[1];
     }
 }
 
-static lbm_status kn_recenter(const KnWs &w, const Grid &g, int64_t nf, const KnHeader &h,
-                              int cur, hipStream_t s) {
-    k_plane_mean<<<(unsigned)g.nx, 256, 0, s>>>(g, w.idmap, w.csnap, w.ref, w.ref_new);
+// The next frame: plane means (planes without fluid keep the current value), its steady
+// shifts, and the shifts from the current frame into it.  Sums in fixed order.
+__global__ __launch_bounds__(1024) void k_frame_next(int nx, double c_in, double c_out,
+                                                     const double *__restrict__ part,
+                                                     const double *__restrict__ ref_cur,
+                                                     double *__restrict__ ref_next,
+                                                     Shift *__restrict__ steady_next,
+                                                     Shift *__restrict__ trans) {
+    for (int k = threadIdx.x; k < nx + 2; k += 1024) {
+        double v;
+        if (k == 0) {
+            v = c_in;
+        } else if (k == nx + 1) {
+            v = c_out;
+        } else {
+            double s = 0.0, c = 0.0;
+            for (int q = 0; q < kPlaneParts; q++) {
+                s += part[2 * ((k - 1) * kPlaneParts + q)];
+                c += part[2 * ((k - 1) * kPlaneParts + q) + 1];
+            }
+            v = c > 0.0 ? s / c : ref_cur[k];
+        }
+        ref_next[k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nx + 2; k += 1024) {
+        Shift s, t;
+        s.t0 = 0.f;
+        s.tm = k >= 1 ? (float)(0.125 * (ref_next[k - 1] - ref_next[k])) : 0.f;
+        s.tp = k <= nx ? (float)(0.125 * (ref_next[k + 1] - ref_next[k])) : 0.f;
+        s.pad = 0.f;
+        t.t0 = (float)(0.125 * (ref_cur[k] - ref_next[k]));
+        t.tm = k >= 1 ? (float)(0.125 * (ref_cur[k - 1] - ref_next[k])) : 0.f;
+        t.tp = k <= nx ? (float)(0.125 * (ref_cur[k + 1] - ref_next[k])) : 0.f;
+        t.pad = 0.f;
+        steady_next[k] = s;
+        trans[k] = t;
+    }
+}
+
+// Net +x flux through the link plane x = px - 1/2 (px = 0..nx), one block per plane,
+// over links with both ends fluid (ghost planes count as fluid).  g_{+x}(left) -
+// g_{-x}(right) in the frame of `right` is s_{+x}(left) + tm(right) - s_{-x}(right); the
+// ghost planes hold zero deviation.
+__global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
+                                                    const RankWord *__restrict__ rank,
+                                                    const float *__restrict__ gcur,
+                                                    const Shift *__restrict__ steady,
+                                                    double *__restrict__ plane) {
+    const int px = blockIdx.x;
+    const int left = px - 1, right = px;
+    double acc[1] = {0.0};
+    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
+        const int y = (int)(k % g.ny), z = (int)(k / g.ny);
+        const int il = left >= 0 ? node_at(rank, g, left, y, z) : -2;
+        const int ir = right < g.nx ? node_at(rank, g, right, y, z) : -2;
+        if (il == -1 || ir == -1) continue;
+        const double fwd = left >= 0 ? (double)gcur[stride + il] : 0.0;
+        const double bwd = right < g.nx ? (double)gcur[2 * stride + ir] : 0.0;
+        acc[0] += (fwd + (double)steady[right + 1].tm) - bwd;
+    }
+    __shared__ double lds[4];
+    double out[1];
+    block_sum<1>(acc, lds, out);
+    if (threadIdx.x == 0) plane[px] = out[0];
+}
+
+__global__ void k_kn_sample(Grid g, int64_t count, int64_t stride, const int64_t *__restrict__ vox,
+                            const RankWord *__restrict__ rank, const float *__restrict__ gcur,
+                            const float *__restrict__ omega, const double *__restrict__ cref,
+                            double *__restrict__ out, uint8_t *__restrict__ flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const int64_t v = vox[s];
+    const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
+    const int id = node_at(rank, g, x, y, z);
+    flag[s] = id >= 0;
+    const double ref = cref[x + 1];
+    for (int i = 0; i < 7; i++)
+        out[s * 8 + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] + (i ? 0.125 : 0.25) * ref
+                                 : 0.0;
+    out[s * 8 + 7] = id >= 0 ? 1.0 / (double)omega[id] : 0.0;
+}
+
+// Plane means of the checked concentration become the next frame (kept pending until
+// the next sweep moves the state into it).
+static lbm_status kn_next_frame(const KnWs &w, const Grid &g, const KnHeader &h, hipStream_t s) {
+    k_plane_mean<<<dim3(kPlaneParts, g.nx), 256, 0, s>>>(g, w.rank, w.csnap, w.part);
     LBM_CHECK_LAUNCH();
-    k_recenter<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(nf, w.stride, w.coords, w.ref, w.ref_new,
-                                                       w.g[cur]);
-    LBM_CHECK_LAUNCH();
-    k_ref_commit<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.ref, w.ref_new, w.shm, w.shp);
+    const int f = h.frame;
+    k_frame_next<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.part, w.ref[f], w.ref[f ^ 1],
+                                    w.steady[f ^ 1], w.trans);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
 
-static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, const KnHeader &h, int &cur,
-                            int64_t steps, bool check_last, float *c_field, hipStream_t s) {
+// Kernel variant: explicit bits, or chosen from the working set (see the flow solve):
+// streaming (plain order, non-temporal stores) once the two population arrays exceed
+// ~3/4 of the 256 MB Infinity Cache, cache-resident (XCD-contiguous order) below.
+struct Variant7 {
+    bool remap, nt;
+};
+
+static Variant7 pick_variant7(int32_t v, int64_t stride) {
+    Variant7 m;
+    if (v & LBM_VARIANT_EXPLICIT) {
+        m.remap = v & LBM_VARIANT_REMAP;
+        m.nt = v & LBM_VARIANT_NTSTORE;
+        return m;
+    }
+    const bool stream = 2.0 * 7 * 4 * (double)stride > 192e6;
+    m.remap = !stream;
+    m.nt = stream;
+    return m;
+}
+
+template <bool CHECK>
+static void launch7(const Sweep7 &a, const Variant7 &m, hipStream_t s) {
+    const unsigned grid = (unsigned)a.launched;
+    if (m.nt) k_sweep7<CHECK, true><<<grid, 256, 0, s>>>(a);
+    else k_sweep7<CHECK, false><<<grid, 256, 0, s>>>(a);
+}
+
+// `steps` sweeps; the first one moves the state into the pending frame if there is one.
+static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, KnHeader &h,
+                            const Variant7 &m, int &cur, bool &pending, int64_t steps,
+                            bool check_last, float *c_field, hipStream_t s) {
     Sweep7 a;
     a.g = g;
     a.nf = nf;
     a.stride = w.stride;
     a.launched = xcd_launch(kn_blocks(nf));
     a.coords = w.coords;
-    a.idmap = w.idmap;
+    a.rank = w.rank;
     a.omega = w.omega;
-    a.shm = w.shm;
-    a.shp = w.shp;
-    a.ref = w.ref;
+    a.remap = m.remap;
     a.csnap = w.csnap;
     a.c_out = c_field;
     a.partials = w.partials;
     for (int64_t t = 0; t < steps; t++) {
+        if (pending) {
+            a.shift = w.trans;
+            h.frame ^= 1;
+            pending = false;
+        } else {
+            a.shift = w.steady[h.frame];
+        }
+        a.ref_out = w.ref[h.frame];
         a.src = w.g[cur];
         a.dst = w.g[cur ^ 1];
         if (check_last && t == steps - 1)
-            k_sweep7<true><<<(unsigned)a.launched, 256, 0, s>>>(a);
+            launch7<true>(a, m, s);
         else
-            k_sweep7<false><<<(unsigned)a.launched, 256, 0, s>>>(a);
+            launch7<false>(a, m, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
@@ -377,6 +476,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
     LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
                 "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
+    LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
+                p->variant);
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -386,7 +487,7 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
-    st = layout_count(g, fluid, w0.bcount, &nf, s);
+    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     KnWs w = carve_kn(workspace, g, nf);
@@ -402,12 +503,16 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         LBM_REQUIRE(h.magic == kKnMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
-                        h.n_fluid == nf,
-                    LBM_E_INVAL, "resume: the workspace holds no state for this geometry");
+                        h.n_fluid == nf && h.c_in == p->c_in && h.c_out == p->c_out,
+                    LBM_E_INVAL, "resume: the workspace holds no state for this problem");
         t0 = h.steps_done;
         cur = h.cur;
+    } else {
+        h.frame = 0;
     }
-    st = layout_fill(g, fluid, w.bcount, w.idmap, w.coords, s);
+    h.variant = p->variant;
+    const Variant7 mode = pick_variant7(p->variant, w.stride);
+    st = layout_fill(g, w.rank, w.coords, s);
     if (st != LBM_OK) return st;
     h.magic = kKnMagic;
     h.nx = n[0]; h.ny = n[1]; h.nz = n[2];
@@ -416,15 +521,19 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.c_out = p->c_out;
     const double d_ref = p->d_ref_nm / p->voxel_nm;
     LBM_TRY_HIP(hipMemsetAsync(w.counter, 0, sizeof(unsigned long long), s));
-    if (!p->resume) LBM_TRY_HIP(hipMemsetAsync(w.ref, 0, sizeof(double) * (kMaxEdge + 2), s));
     k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, pore_diam, d_ref,
                                                       p->tau_ref, c_init, w.g[cur], w.omega,
                                                       w.csnap, p->resume ? 0 : 1, w.counter,
                                                       w.partials);
     LBM_CHECK_LAUNCH();
+    bool pending = false;
     if (!p->resume) {
-        st = kn_recenter(w, g, nf, h, cur, s);
+        // frame 0 holds the initial state; its plane means become the first pending frame
+        k_frame0<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.ref[0], w.steady[0]);
+        LBM_CHECK_LAUNCH();
+        st = kn_next_frame(w, g, h, s);
         if (st != LBM_OK) return st;
+        pending = true;
     }
     st = reduce_partials(w.partials, kn_blocks(nf), 1, w.res + 8, s);
     if (st != LBM_OK) return st;
@@ -451,13 +560,14 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         int64_t chunk = nc - (abs_t % nc);
         if (chunk > limit - t) chunk = limit - t;
         LBM_TRY_HIP(hipEventRecord(e0, s));
-        out = kn_launch(w, g, nf, h, cur, chunk, true, c_field, s);
+        out = kn_launch(w, g, nf, h, mode, cur, pending, chunk, true, c_field, s);
         if (out != LBM_OK) break;
         LBM_TRY_HIP(hipEventRecord(e1, s));
         out = reduce_partials(w.partials, kn_blocks(nf), kKnSums, w.res, s);
         if (out != LBM_OK) break;
-        out = kn_recenter(w, g, nf, h, cur, s);
+        out = kn_next_frame(w, g, h, s);
         if (out != LBM_OK) break;
+        pending = true;
         LBM_TRY_HIP(hipMemcpyAsync(sums, w.res, sizeof(sums), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         float ms = 0.f;
@@ -479,12 +589,13 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (out != LBM_OK) return out;
+    // a pending frame that no sweep entered is dropped: the state stays in h.frame
     h.cur = cur;
     h.steps_done = t0 + t;
     LBM_TRY_HIP(hipMemcpyAsync(w.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
     // link-plane fluxes of the final state
-    k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.idmap, w.g[cur], w.shm,
-                                                      w.plane);
+    k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.rank, w.g[cur],
+                                                      w.steady[h.frame], w.plane);
     LBM_CHECK_LAUNCH();
     double planes[kMaxEdge + 1];
     LBM_TRY_HIP(hipMemcpyAsync(planes, w.plane, sizeof(double) * (g.nx + 1), hipMemcpyDeviceToHost, s));
@@ -555,7 +666,9 @@ extern "C" lbm_status lbm_knudsen_step(void *workspace, size_t ws_bytes, int64_t
     if (st != LBM_OK) return st;
     LBM_REQUIRE(steps >= 0, LBM_E_INVAL, "negative step count");
     int cur = h.cur;
-    st = kn_launch(w, g, h.n_fluid, h, cur, steps, false, nullptr, s);
+    bool pending = false;
+    st = kn_launch(w, g, h.n_fluid, h, pick_variant7(h.variant, w.stride), cur, pending, steps,
+                   false, nullptr, s);
     if (st != LBM_OK) return st;
     h.cur = cur;
     h.steps_done += steps;
@@ -582,9 +695,9 @@ extern "C" lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const
                     (long long)vox_h[i]);
     LBM_TRY_HIP(hipMemcpyAsync(w.samp_vox, vox_h, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
     k_kn_sample<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(g, count, w.stride, w.samp_vox,
-                                                               w.idmap, w.g[h.cur], w.omega,
-                                                               w.ref,
-                                                               w.samp_out, w.samp_flag);
+                                                               w.rank, w.g[h.cur], w.omega,
+                                                               w.ref[h.frame], w.samp_out,
+                                                               w.samp_flag);
     LBM_CHECK_LAUNCH();
     std::vector<double> tmp((size_t)count * 8);
     LBM_TRY_HIP(hipMemcpyAsync(tmp.data(), w.samp_out, sizeof(double) * 8 * count, hipMemcpyDeviceToHost, s));

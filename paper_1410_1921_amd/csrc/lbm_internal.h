@@ -52,36 +52,39 @@ struct Carver {
 };
 
 // ---------------------------------------------------------------- grid geometry
-// Bricks of 8x8x8 voxels; inside a brick voxels run x fastest.  The fluid-node list is
-// ordered brick by brick (bricks x fastest), so a brick's nodes are contiguous.
-constexpr int kBrickLog = 3;
-constexpr int kBrick = 1 << kBrickLog;
-constexpr int kBrickVox = kBrick * kBrick * kBrick;
+// Rows of the box (all x at one y, z) are cut into segments of 64 voxels along x;
+// segment (x / 64, y, z) has index seg(x, y, z).  The fluid-node list holds each segment's
+// nodes contiguously, in x order.  Segments follow each other in column order: the y-z
+// cross-section is tiled by columns of kCol x kCol rows (columns z-major, then y; rows
+// inside a column z-major), and each row's segments run in x order.  A wave of 64
+// consecutive nodes is then a run along one row, and each of its pulls reads one short
+// run of the list (the same run shifted to the neighbouring row or plane of the column),
+// which keeps the cache lines a wave touches per load close to the minimum.
+constexpr int kSegLog = 6;
+constexpr int kSeg = 1 << kSegLog;
+constexpr int kCol = 16;
 constexpr int kMaxEdge = 1024;  // coordinates packed in 10 bits each
 
 struct Grid {
     int nx, ny, nz;
-    int nbx, nby, nbz;
+    int nseg;      // segments per row
+    int ncy, ncz;  // columns along y and z
     __host__ __device__ int64_t nvox() const { return (int64_t)nx * ny * nz; }
-    __host__ __device__ int64_t nbricks() const { return (int64_t)nbx * nby * nbz; }
+    __host__ __device__ int64_t nsegs() const { return (int64_t)nseg * ny * nz; }
     __host__ __device__ int64_t lin(int x, int y, int z) const {
         return (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
     }
-    // brick-major voxel slot of in-domain coordinates
-    __host__ __device__ int64_t slot(int x, int y, int z) const {
-        int64_t b = ((int64_t)(z >> kBrickLog) * nby + (y >> kBrickLog)) * nbx + (x >> kBrickLog);
-        int l = (((z & (kBrick - 1)) << kBrickLog | (y & (kBrick - 1))) << kBrickLog) |
-                (x & (kBrick - 1));
-        return b * kBrickVox + l;
+    __host__ __device__ int64_t seg(int x, int y, int z) const {
+        return ((int64_t)z * ny + y) * nseg + (x >> kSegLog);
     }
 };
 
 inline Grid make_grid(const int32_t n[3]) {
     Grid g;
     g.nx = n[0]; g.ny = n[1]; g.nz = n[2];
-    g.nbx = (n[0] + kBrick - 1) / kBrick;
-    g.nby = (n[1] + kBrick - 1) / kBrick;
-    g.nbz = (n[2] + kBrick - 1) / kBrick;
+    g.nseg = (n[0] + kSeg - 1) / kSeg;
+    g.ncy = (n[1] + kCol - 1) / kCol;
+    g.ncz = (n[2] + kCol - 1) / kCol;
     return g;
 }
 
@@ -89,10 +92,13 @@ __host__ __device__ inline uint32_t pack_xyz(int x, int y, int z) {
     return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
 }
 
+// Variant bits a solve accepts.
+constexpr int32_t kVariantBits = LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE;
+
 // ---------------------------------------------------------------- XCD-aware mapping
 // Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD b % 8).
 // Remap so that each XCD walks one contiguous run of logical blocks: neighbouring
-// bricks then share an L2.  `launched` is a multiple of 8.
+// rows of a column then share an L2.  `launched` is a multiple of 8.
 constexpr int kXcd = 8;
 __device__ inline int64_t xcd_block(int64_t b, int64_t launched) {
     int64_t per = launched / kXcd;
@@ -129,14 +135,34 @@ lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, doub
                            hipStream_t s);
 
 // ---------------------------------------------------------------- sparse layout
-// The fluid-node list (node ids brick by brick) and the brick-major id map.
-// layout_count: per-brick fluid counts turned into exclusive offsets in bcount
-// [nbricks + 1]; the total goes to *nf_h (host sync).
-// layout_fill: idmap[slot] = node id or -1, coords[id] = packed x | y<<10 | z<<20.
-lbm_status layout_count(const Grid &g, const uint8_t *fluid, int32_t *bcount, int64_t *nf_h,
-                        hipStream_t s);
-lbm_status layout_fill(const Grid &g, const uint8_t *fluid, const int32_t *boff, int32_t *idmap,
-                       uint32_t *coords, hipStream_t s);
+// Node ids are found through the rank map: one 16-byte word per row segment, holding
+// the segment's 64-bit occupancy (bit x % 64) and the id of its first fluid node, so a
+// voxel's id is base + popcount(bits below it).  At 1/4 byte per voxel the map stays
+// cache resident.
+struct alignas(16) RankWord {
+    uint32_t lo, hi;  // occupancy bits 0-31, 32-63
+    uint32_t base;    // id of the first fluid node of the segment
+    uint32_t pad;
+};
+
+// Node id at bit `bit` (= x % 64) of rank word w, or -1 for a solid voxel.
+__device__ inline int rank_lookup(const RankWord w, int bit) {
+    const uint64_t bits = (uint64_t)w.hi << 32 | w.lo;
+    if (!((bits >> bit) & 1)) return -1;
+    return (int)(w.base + (uint32_t)__popcll(bits & ((1ull << bit) - 1)));
+}
+
+// Node id of the in-domain voxel (x, y, z), or -1.
+__device__ inline int node_at(const RankWord *__restrict__ rank, const Grid &g, int x, int y, int z) {
+    return rank_lookup(rank[g.seg(x, y, z)], x & (kSeg - 1));
+}
+
+// layout_count: the rank map's occupancy bits and bases (g.nsegs() words); the number
+// of fluid nodes goes to *nf_h (host sync); total_d is one int32 of device scratch.
+// layout_fill: coords[id] = packed x | y<<10 | z<<20 of every fluid node.
+lbm_status layout_count(const Grid &g, const uint8_t *fluid, RankWord *rank, int32_t *total_d,
+                        int64_t *nf_h, hipStream_t s);
+lbm_status layout_fill(const Grid &g, const RankWord *rank, uint32_t *coords, hipStream_t s);
 
 // Counting kernel usable by several entry points.
 lbm_status count_nonzero(const Grid &g, const uint8_t *mask, unsigned long long *dcount,

@@ -20,6 +20,7 @@ LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_RECON_STALL, LBM_E_DIVERGED = -1, 
 LBM_PSD_CHORD13, LBM_PSD_MIS = 0, 1
 LBM_WS_LABEL, LBM_WS_PORE_DIAM, LBM_WS_FLOW, LBM_WS_KNUDSEN = 0, 1, 2, 3
 LBM_STORE_FP32 = 0
+LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
 
 _STATUS = {0: "OK", 1: "W_NOT_CONVERGED", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE",
            -4: "E_RECON_STALL", -5: "E_DIVERGED"}
@@ -52,7 +53,7 @@ class lbm_flow_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("force", C.c_double * 3), ("max_steps", C.c_int64),
                 ("fixed_steps", C.c_int64), ("check_every", C.c_int32), ("storage", C.c_int32),
                 ("tol", C.c_double), ("voxel_nm", C.c_double), ("resume", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("variant", C.c_int32)]
 
 
 class lbm_flow_result(C.Structure):
@@ -67,7 +68,8 @@ class lbm_knudsen_params(C.Structure):
     _fields_ = [("tau_ref", C.c_double), ("d_ref_nm", C.c_double), ("voxel_nm", C.c_double),
                 ("c_in", C.c_double), ("c_out", C.c_double), ("T_K", C.c_double),
                 ("M_kg_mol", C.c_double), ("max_steps", C.c_int64), ("fixed_steps", C.c_int64),
-                ("check_every", C.c_int32), ("resume", C.c_int32), ("tol", C.c_double)]
+                ("check_every", C.c_int32), ("resume", C.c_int32), ("tol", C.c_double),
+                ("variant", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lbm_knudsen_result(C.Structure):
@@ -117,6 +119,7 @@ _SIGS = {
     "lbm_last_error": ([], C.c_char_p),
     "lbm_version": ([], C.c_char_p),
     "lbm_sizeof": ([C.c_int32], C.c_size_t),
+    "lbm_copy_probe": ([_P, _P, C.c_size_t, _P], C.c_int32),
 }
 
 _lib = None
@@ -199,6 +202,14 @@ def lbm_sizeof(which):
     return load().lbm_sizeof(which)
 
 
+def lbm_copy_probe(dst, src):
+    """Streaming device copy of src into dst (same byte size, multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("lbm_copy_probe: sizes differ")
+    _check(load().lbm_copy_probe(_ptr(dst), _ptr(src), nbytes, _stream()), "lbm_copy_probe")
+
+
 # ------------------------------------------------------------------ geometry
 def lbm_reconstruct(n, porosity, d_mean, d_std, d_min=1.0, overlap_tol=0.5, p_overlap=0.5,
                     seed=1, max_trials=0, sphere_cap=1 << 20, device="cuda"):
@@ -265,14 +276,14 @@ class Solve:
 
 def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
                    check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False, u_init=None,
-                   workspace=None, resume=False, n_fluid=None):
+                   workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO):
     _vol(fluid, torch.uint8, "fluid")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
     if workspace is None:
         workspace = Workspace(lbm_workspace_size(LBM_WS_FLOW, fluid.shape, n_fluid), fluid.device)
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
-                        LBM_STORE_FP32, tol, voxel_nm, int(bool(resume)), 0)
+                        LBM_STORE_FP32, tol, voxel_nm, int(bool(resume)), int(variant))
     r = lbm_flow_result()
     u = torch.empty((3,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
         if want_u else None
@@ -305,7 +316,7 @@ def lbm_flow_sample(workspace, vox):
 def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5, c_in=1.0,
                       c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000, fixed_steps=0,
                       check_every=100, tol=1e-7, want_c=False, c_init=None, want_planes=True,
-                      workspace=None, resume=False, n_fluid=None):
+                      workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO):
     _vol(fluid, torch.uint8, "fluid")
     _vol(pore_diam, torch.float64, "pore_diam")
     if n_fluid is None:
@@ -314,7 +325,7 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
         workspace = Workspace(lbm_workspace_size(LBM_WS_KNUDSEN, fluid.shape, n_fluid),
                               fluid.device)
     p = lbm_knudsen_params(tau_ref, d_ref_nm, voxel_nm, c_in, c_out, T, M, max_steps, fixed_steps,
-                           check_every, int(bool(resume)), tol)
+                           check_every, int(bool(resume)), tol, int(variant), 0)
     r = lbm_knudsen_result()
     c = torch.empty(fluid.shape, dtype=torch.float32, device=fluid.device) if want_c else None
     nx = fluid.shape[2]

@@ -27,7 +27,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(lib):
     L = lib.load()
     names = _declared()
-    assert len(names) == 15
+    assert len(names) == 16
     for name in names:
         assert hasattr(L, name), name
     # and the binding wraps each of them
@@ -78,7 +78,7 @@ def test_argument_checks_before_device(lib):
     p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 0, 0, 1e-7, 1.0, 0, 0)
     assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
                             None) == lib.LBM_E_INVAL
-    kp = lib.lbm_knudsen_params(1.0, 60.0, 1.5, 1.0, 1.0, 323.0, 0.016, 10, 0, 10, 0, 1e-7)
+    kp = lib.lbm_knudsen_params(1.0, 60.0, 1.5, 1.0, 1.0, 323.0, 0.016, 10, 0, 10, 0, 1e-7, 0, 0)
     kr = lib.lbm_knudsen_result()
     assert L.lbm_knudsen_solve(n, dummy, dummy, C.byref(kp), C.byref(kr), None, None, None,
                                dummy, 1 << 20, None) == lib.LBM_E_INVAL
@@ -89,6 +89,17 @@ def test_argument_checks_before_device(lib):
     assert L.lbm_pore_diameter(n, dummy, 5, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
     nbad = (C.c_int32 * 3)(0, 8, 8)
     assert L.lbm_pore_diameter(nbad, dummy, 0, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
+    # variant bits other than EXPLICIT | REMAP | NTSTORE are rejected by both solves
+    for bad in (2, 16, 1 << 20, -1):
+        p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, 0, 1e-7, 1.0, 0, bad)
+        assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
+                                None) == lib.LBM_E_INVAL
+        assert "variant" in L.lbm_last_error().decode()
+        kp = lib.lbm_knudsen_params(1.0, 60.0, 1.5, 1.0, 0.0, 323.0, 0.016, 10, 0, 10, 0, 1e-7,
+                                    bad, 0)
+        assert L.lbm_knudsen_solve(n, dummy, dummy, C.byref(kp), C.byref(kr), None, None, None,
+                                   dummy, 1 << 20, None) == lib.LBM_E_INVAL
+        assert "variant" in L.lbm_last_error().decode()
 
 
 def test_props_relations(lib, orc):
