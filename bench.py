@@ -97,6 +97,25 @@ def roofline_512(lbm, W, steps):
             "mlups": nf / (ms * 1e3)}
 
 
+def knudsen_sweeps(lbm, w, steps):
+    """`steps` D3Q7 sweeps on the workload's geometry: mean launch time from the
+    library's HIP events."""
+    rp, kp = w["recon"], w["knudsen"]
+    pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                      rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    method = lbm.LBM_PSD_MIS if rp["psd"] == "mis" else lbm.LBM_PSD_CHORD13
+    diam = lbm.lbm_pore_diameter(pore, method)
+    kr = lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+                               voxel_nm=w["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
+                               T=kp["T"], fixed_steps=steps, check_every=kp["check_every"],
+                               n_fluid=rs["n_pore"])
+    per = kr["sweep_ms"] / kr["steps"]
+    gbs = kr["n_fluid"] * BYTES_D3Q7 / (per * 1e-3) / 1e9
+    return {"kernel": "k_sweep7", "workload": w["name"], "n_fluid": kr["n_fluid"],
+            "steps": kr["steps"], "ms_per_launch": per, "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def copy_ceiling(lbm, nbytes=1 << 30, reps=5):
     """Attainable HBM bandwidth: the library's streaming copy kernel on `nbytes` buffers,
     read + write bytes per second from HIP events on the current stream (best of reps)."""
@@ -153,8 +172,11 @@ def main():
     ap.add_argument("--no-512", action="store_true")
     ap.add_argument("--roofline-steps", type=int, default=100)
     ap.add_argument("--only-512", action="store_true",
-                    help="only the 512^3 sweep roofline, after a 2 GiB torch copy that "
-                         "calibrates the HBM byte counters (for profiling runs)")
+                    help="only the 512^3 sweep roofline, after 2 GiB copies by the library's "
+                         "copy kernel that calibrate the HBM byte counters (profiling runs)")
+    ap.add_argument("--only-knudsen", type=int, default=0, metavar="STEPS",
+                    help="only the geometry stages and STEPS Knudsen sweeps of the workload, "
+                         "after the same copy calibration (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
@@ -175,6 +197,12 @@ def main():
                           "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
         return
     w = W.WORKLOADS[args.workload]
+    if args.only_knudsen:
+        ceiling = copy_ceiling(lbm, 1 << 31, 3)
+        print(json.dumps({"knudsen_sweeps": knudsen_sweeps(lbm, w, args.only_knudsen),
+                          "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
+                          "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
+        return
     log("workload", w["name"])
     for i in range(args.warmup):
         r = pipeline(lbm, W, w)

@@ -57,11 +57,17 @@ typedef int32_t lbm_status;
 /* workspace kinds for lbm_workspace_size() */
 #define LBM_WS_LABEL 0
 #define LBM_WS_PORE_DIAM 1
-#define LBM_WS_FLOW 2
+#define LBM_WS_FLOW 2      /* flow solve, binary32 storage */
 #define LBM_WS_KNUDSEN 3
+#define LBM_WS_FLOW_FP16 4 /* flow solve, binary16 storage */
+#define LBM_WS_FLOW_FP64 5 /* flow solve, binary64 storage */
 
-/* population storage of the flow solve */
-#define LBM_STORE_FP32 0 /* f - w_i in binary32 */
+/* population storage of the flow solve: the offsets f_i - w_i are stored in */
+#define LBM_STORE_FP32 0 /* binary32, collision in binary32 */
+#define LBM_STORE_FP16 1 /* binary16 offsets from w_i (1 + drho_w), drho_w = rho - 1 of the
+                            writing node (kept in binary32), times S = 2^k with
+                            S max|F| in [1, 2) (1 when F = 0); collision in binary32 */
+#define LBM_STORE_FP64 2 /* binary64, collision in binary64 */
 
 /* sweep kernel variant (the `variant` field of the solve parameters): 0 lets the library
  * choose from the working-set size; otherwise LBM_VARIANT_EXPLICIT plus any of
@@ -177,12 +183,22 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  *
  * fluid     : device uint8[N^3] in, 1 = fluid node (pass the pore mask, or the
  *             transport mask to drop dead pores).
- * u_out     : device float[3][N^3] out (planar, 0 at solids), nullable.
- * u_init    : device float[3][N^3] in, nullable (warm start).
- * workspace : LBM_WS_FLOW bytes for the fluid count; it also keeps the state for
- *             lbm_flow_step / lbm_flow_sample / resume.
- * Errors: LBM_E_INVAL (tau <= 1/2, check_every < 1, no fluid node, N > 1024),
- * LBM_E_NOMEM, LBM_E_DIVERGED, LBM_E_DEVICE.
+ * u_out     : device float[3][N^3] out (planar, 0 at solids), nullable; with
+ *             with_rho = 1 float[4][N^3], the fourth plane rho - 1.
+ * u_init    : device float[3][N^3] in, nullable (warm start: the populations start at
+ *             the equilibrium of u); with with_rho = 1 float[4][N^3], the fourth plane
+ *             rho - 1 (else rho = 1).
+ * workspace : LBM_WS_FLOW (_FP16, _FP64 for those storages) bytes for the fluid
+ *             count; it also keeps the state for lbm_flow_step / lbm_flow_sample /
+ *             resume (a resume must use the storage of the solve that left it).
+ * With binary16 storage a check interval without any change is reported as a stall
+ * (LBM_W_NOT_CONVERGED, converged = 0): the rounded iteration has reached a fixed point
+ * short of steady state.
+ * The convergence residual, the velocity snapshot it compares against and u_out are
+ * formed from the collision arithmetic and kept in binary32 (sums in binary64) for
+ * every storage.
+ * Errors: LBM_E_INVAL (tau <= 1/2, check_every < 1, no fluid node, N > 1024, unknown
+ * storage or variant bits), LBM_E_NOMEM, LBM_E_DIVERGED, LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
     double tau;
@@ -190,11 +206,13 @@ typedef struct {
     int64_t max_steps;
     int64_t fixed_steps;  /* > 0: run exactly this many steps */
     int32_t check_every;  /* n_c */
-    int32_t storage;      /* LBM_STORE_FP32 */
+    int32_t storage;      /* LBM_STORE_* */
     double tol;
     double voxel_nm;      /* lattice spacing, for k in m^2 and mD */
     int32_t resume;       /* 1: continue from the state in the workspace */
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
+    int32_t with_rho;     /* 1: u_init / u_out carry rho - 1 as a fourth plane */
+    int32_t reserved;     /* 0 */
 } lbm_flow_params;
 
 typedef struct {
@@ -206,7 +224,9 @@ typedef struct {
     double mass_dev;      /* sum over fluid of rho - 1 */
     double sweep_ms;      /* GPU time of the stream-collide kernels (HIP events) */
     double mlups;         /* fluid-node updates per microsecond of sweep_ms */
-    double gbps;          /* algorithmic bytes (152 per update) per second of sweep_ms */
+    double gbps;          /* algorithmic bytes per second of sweep_ms: 152 per update
+                             (binary32), 304 (binary64), 84 (binary16: 76 + the writer
+                             density store and load) */
 } lbm_flow_result;
 
 lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid, const lbm_flow_params *p,
@@ -218,9 +238,10 @@ lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid, const lbm_fl
 lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t steps, void *stream);
 
 /* Read the post-collision populations of `count` voxels from the state in
- * `workspace`: f_h[count][19] receives f_i - w_i (double, exact copies of the
- * stored values), fluid_h[count] whether the voxel is a fluid node (rows of solid
- * voxels are 0).  count <= 65536. */
+ * `workspace`: f_h[count][19] receives f_i - w_i (double: exact copies of the stored
+ * values; for binary16 storage the stored offset divided by S plus w_i drho of the
+ * node), fluid_h[count] whether the voxel is a fluid node (rows of solid voxels are 0).
+ * count <= 65536. */
 lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_h, int64_t count,
                            double *f_h, uint8_t *fluid_h, void *stream);
 

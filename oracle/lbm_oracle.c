@@ -466,17 +466,20 @@ static void gather19(int nx, int ny, int nz, const uint8_t *fluid, const double 
     }
 }
 
-/* initial populations: the equilibrium at rho = 1 and u (u_init planar
- * [3][N^3], or zero when null) */
-void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u_init, double *f) {
+/* initial populations: the D3Q19 equilibrium (Eq. 3) at rho = 1 + drho_init and u
+ * (u_init planar [3][N^3], drho_init [N^3]; zero where null) */
+void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u_init,
+                   const double *drho_init, double *f) {
     int64_t nvox = (int64_t)nx * ny * nz;
     for (int64_t v = 0; v < nvox; v++) {
         double u[3] = {0.0, 0.0, 0.0};
+        double rho = 1.0;
         if (u_init && fluid[v]) for (int a = 0; a < 3; a++) u[a] = u_init[a * nvox + v];
+        if (drho_init && fluid[v]) rho = 1.0 + drho_init[v];
         double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         for (int i = 0; i < 19; i++) {
             double eu = E19[i][0] * u[0] + E19[i][1] * u[1] + E19[i][2] * u[2];
-            f[19 * v + i] = fluid[v] ? w19(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) : 0.0;
+            f[19 * v + i] = fluid[v] ? w19(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) : 0.0;
         }
     }
 }

@@ -75,7 +75,8 @@ def lib():
     L.orc_tau_g.restype = C.c_double
     L.orc_collide19.argtypes = [_f64p, C.c_double, _f64p, _f64p, _nullable(_f64p)]
     L.orc_collide19.restype = None
-    L.orc_flow_init.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, _nullable(_f64p), _f64p]
+    L.orc_flow_init.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, _nullable(_f64p), _nullable(_f64p),
+                                _f64p]
     L.orc_flow_init.restype = None
     L.orc_flow_solve.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, C.c_double, _f64p, C.c_int64,
                                  C.c_int64, C.c_int, C.c_double, _nullable(_f64p), _f64p,
@@ -211,12 +212,15 @@ def tau_g(d_p, d_ref, tau_ref=1.0):
 
 
 # ---------------------------------------------------------------- flow (D3Q19)
-def flow_init(fluid, u_init=None):
+def flow_init(fluid, u_init=None, drho_init=None):
+    """Equilibrium populations (node-major) at rho = 1 + drho_init and u = u_init (rest
+    and 1 where not given)."""
     fluid = np.ascontiguousarray(fluid, np.uint8)
     nz, ny, nx = fluid.shape
     f = np.zeros(fluid.shape + (19,), np.float64)
     ui = None if u_init is None else np.ascontiguousarray(u_init, np.float64)
-    lib().orc_flow_init(nx, ny, nz, fluid, ui, f)
+    dr = None if drho_init is None else np.ascontiguousarray(drho_init, np.float64)
+    lib().orc_flow_init(nx, ny, nz, fluid, ui, dr, f)
     return f
 
 

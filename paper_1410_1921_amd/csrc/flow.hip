@@ -2,13 +2,28 @@
 // bounce-back, on the sparse fluid-node list (Section 3.1, Eqs. 1-3, 8-9; Section 3.3;
 // Darcy's law, Eq. 13).
 //
-// Storage: structure of arrays f[i][node] of f_i - w_i in binary32 ("shifted"
-// populations: the flow signal lives in deviations of order 1e-6 from w_i, which
-// binary32 keeps to ~1e-13 absolute once the constant w_i is removed).  Two buffers,
-// ping-pong.  Per fluid-node update the method moves 19 loads + 19 stores of 4 bytes.
+// Storage: structure of arrays f[i][node] of the offsets f_i - w_i ("shifted"
+// populations: the flow signal lives in deviations of order 1e-6 from w_i, which a float
+// keeps to ~1e-13 absolute once the constant w_i is removed), in binary32 (collision in
+// binary32) or binary64 (collision in binary64).  Two buffers, ping-pong.  Per
+// fluid-node update the method moves 19 loads + 19 stores of 4 or 8 bytes.
+//
+// binary16 storage (collision in binary32) keeps each outgoing population as an offset
+// from the equilibrium weight times the writing node's own density,
+// h_i = S (f_i - w_i (1 + drho_w)), with drho_w = rho - 1 of the writer kept once per
+// node in binary32 (ping-pong like the populations), and S = 2^k with S max|F| in [1, 2).
+// Offsets from w_i alone fail in low-permeability media: where the body force is held by
+// pressure (dead ends, tortuous paths) the density part w_i drho exceeds the velocity
+// part by up to four decades and binary16's 11-bit significand loses u entirely.
+// Relative to the writer's density the stored values carry only the velocity and
+// non-equilibrium parts (Stokes flow is linear in F, so S h_i is of order one to a few
+// hundred).  A reader adds back w_i drho of the node it pulled from.  Per update: 19 + 19
+// populations of 2 bytes, one drho store and 19 drho gathers (cache resident, one value
+// per node).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "lbm_internal.h"
 
@@ -25,7 +40,7 @@ namespace lbm {
     [[maybe_unused]] constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8,                  \
                                               7, 14, 13, 12, 11, 18, 17, 16, 15};
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5731ull;  // "LBMFLOW1"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5732ull;  // "LBMFLOW2"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -34,8 +49,57 @@ struct FlowHeader {
     int32_t nx, ny, nz, cur;
     int64_t n_fluid, steps_done;
     double tau, force[3];
-    int32_t variant, reserved;
+    int32_t variant, storage;
+    double scale;  // binary16 storage: stored = scale * (f_i - w_i)
 };
+
+// Storage policies: T is the stored type, R the collision arithmetic.
+struct StoreF32 {
+    using T = float;
+    using R = float;
+};
+struct StoreF64 {
+    using T = double;
+    using R = double;
+};
+struct StoreF16 {
+    using T = _Float16;
+    using R = float;
+};
+
+static int pop_bytes(int32_t storage) {
+    return storage == LBM_STORE_FP16 ? 2 : (storage == LBM_STORE_FP64 ? 8 : 4);
+}
+
+// Algorithmic HBM bytes per fluid-node update: 19 population loads and stores, plus the
+// writer densities for binary16 (one 4-byte store, and one 4-byte load per node).
+static double flow_bytes_per_update(int32_t storage) {
+    return 38.0 * pop_bytes(storage) + (storage == LBM_STORE_FP16 ? 8.0 : 0.0);
+}
+
+template <class P>
+__device__ inline typename P::R from_store(typename P::T v, float inv_scale) {
+    if constexpr (std::is_same<typename P::T, _Float16>::value)
+        return (float)v * inv_scale;  // a power of two: exact
+    else
+        return v;
+}
+
+template <class P>
+__device__ inline typename P::T to_store(typename P::R v, float scale) {
+    if constexpr (std::is_same<typename P::T, _Float16>::value)
+        return (_Float16)(v * scale);  // round to nearest even
+    else
+        return v;
+}
+
+template <class R>
+__device__ inline R par(float f, double d) {
+    if constexpr (std::is_same<R, double>::value)
+        return d;
+    else
+        return f;
+}
 
 struct FlowWs {
     FlowHeader *hdr;
@@ -47,7 +111,8 @@ struct FlowWs {
     double *samp_out;
     uint8_t *samp_flag;
     uint32_t *coords;
-    float *f[2];
+    void *f[2];
+    float *drho[2];  // binary16 storage: the writers' rho - 1 (ping-pong with f)
     float *usnap;
     double *partials;
     int64_t stride;  // distance between population arrays (elements)
@@ -56,7 +121,7 @@ struct FlowWs {
 
 static int64_t blocks_for(int64_t nf) { return (nf + 255) / 256; }
 
-static FlowWs carve_flow(void *base, const Grid &g, int64_t nf) {
+static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage) {
     FlowWs w;
     Carver c(base);
     w.hdr = c.take<FlowHeader>(1);
@@ -70,30 +135,40 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf) {
     int64_t nfp = nf < 1 ? 1 : nf;
     w.stride = (nfp + 63) / 64 * 64;
     w.coords = c.take<uint32_t>(nfp);
-    w.f[0] = c.take<float>((size_t)19 * w.stride);
-    w.f[1] = c.take<float>((size_t)19 * w.stride);
+    w.f[0] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
+    w.f[1] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
+    const size_t ndr = storage == LBM_STORE_FP16 ? (size_t)w.stride : 0;
+    w.drho[0] = c.take<float>(ndr);
+    w.drho[1] = c.take<float>(ndr);
     w.usnap = c.take<float>((size_t)3 * w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(blocks_for(nfp)) * kFlowSums);
     w.bytes = c.off;
     return w;
 }
 
-size_t flow_ws_bytes(const Grid &g, int64_t nf) { return carve_flow(nullptr, g, nf).bytes; }
+size_t flow_ws_bytes(const Grid &g, int64_t nf, int32_t storage) {
+    return carve_flow(nullptr, g, nf, storage).bytes;
+}
 
 struct Sweep19 {
     Grid g;
     int64_t nf, stride, launched;
     const uint32_t *__restrict__ coords;
     const RankWord *__restrict__ rank;
-    const float *__restrict__ src;
-    float *__restrict__ dst;
-    float omega, fpre, Fx, Fy, Fz;
-    int remap;                         // XCD-contiguous workgroup order
+    const void *__restrict__ src;
+    void *__restrict__ dst;
+    const float *__restrict__ drho_src;  // binary16 storage only
+    float *__restrict__ drho_dst;
+    float omega, fpre, Fx, Fy, Fz;     // collision parameters for binary32 arithmetic
+    double omega_d, fpre_d, Fd[3];     // and for binary64
+    float scale, inv_scale;            // binary16 storage scale
+    int64_t chunk;                     // XCD remap run length in blocks (0: none)
     // check variant
     float *__restrict__ usnap;
     float *__restrict__ u_out;
     double *__restrict__ partials;
     int update_snap;
+    int with_rho;                      // u_out carries a fourth plane, rho - 1
 };
 
 // Kernel variants (chosen per solve from the working-set size, or forced):
@@ -103,21 +178,37 @@ struct Sweep19 {
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
-template <bool CHECK, bool NT>
+template <class P, bool CHECK, bool NT>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
                               const int (&ids)[19], double (&acc)[kFlowSums]) {
+    using T = typename P::T;
+    using R = typename P::R;
     LBM_D3Q19_TABLES
-    constexpr float W0 = 1.0f / 3.0f, W1 = 1.0f / 18.0f, W2 = 1.0f / 36.0f;
+    const R W0 = R(1) / R(3), W1 = R(1) / R(18), W2 = R(1) / R(36);
+    const T *__restrict__ src = static_cast<const T *>(a.src);
+    T *__restrict__ dst = static_cast<T *>(a.dst);
+    const R omega = par<R>(a.omega, a.omega_d), fpre = par<R>(a.fpre, a.fpre_d);
+    const R Fx = par<R>(a.Fx, a.Fd[0]), Fy = par<R>(a.Fy, a.Fd[1]), Fz = par<R>(a.Fz, a.Fd[2]);
     uint32_t off[19];
     off[0] = (uint32_t)n;
 #pragma unroll
     for (int i = 1; i < 19; i++)
         off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
-    float f[19];
+    R f[19];
 #pragma unroll
-    for (int i = 0; i < 19; i++) f[i] = a.src[off[i]];
+    for (int i = 0; i < 19; i++) f[i] = from_store<P>(src[off[i]], a.inv_scale);
+    if constexpr (std::is_same<T, _Float16>::value) {
+        // add back w_i drho of the writer: the neighbour pulled from, or the node itself
+        // for the rest population and bounced ones
+        float dr[19];
+        dr[0] = a.drho_src[n];
+#pragma unroll
+        for (int i = 1; i < 19; i++) dr[i] = a.drho_src[ids[i] >= 0 ? ids[i] : n];
+#pragma unroll
+        for (int i = 0; i < 19; i++) f[i] += (i == 0 ? W0 : (i < 7 ? W1 : W2)) * dr[i];
+    }
 
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         drho += f[i];
@@ -125,45 +216,49 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
         if (EY[i]) jy += EY[i] > 0 ? f[i] : -f[i];
         if (EZ[i]) jz += EZ[i] > 0 ? f[i] : -f[i];
     }
-    const float rho = 1.0f + drho;
-    const float inv = 1.0f / rho;
-    const float mx = jx + 0.5f * a.Fx, my = jy + 0.5f * a.Fy, mz = jz + 0.5f * a.Fz;
-    const float ux = mx * inv, uy = my * inv, uz = mz * inv;
-    const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-    const float uF = ux * a.Fx + uy * a.Fy + uz * a.Fz;
+    const R rho = R(1) + drho;
+    const R inv = R(1) / rho;
+    const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
+    const R ux = mx * inv, uy = my * inv, uz = mz * inv;
+    const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
 #pragma unroll
     for (int i = 0; i < 19; i++) {
-        const float w = i == 0 ? W0 : (i < 7 ? W1 : W2);
-        const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-        const float eF = EX[i] * a.Fx + EY[i] * a.Fy + EZ[i] * a.Fz;
-        const float feq = w * (drho + rho * (3.0f * eu + 4.5f * eu * eu - uu15));
-        const float src = a.fpre * w * (3.0f * (eF - uF) + 9.0f * eu * eF);
-        const float out = f[i] - a.omega * (f[i] - feq) + src;
+        const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
+        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
+        const R feq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - uu15));
+        const R srcf = fpre * w * (R(3) * (eF - uF) + R(9) * eu * eF);
+        R post = f[i] - omega * (f[i] - feq) + srcf;
+        if constexpr (std::is_same<T, _Float16>::value) post -= w * drho;
+        const T out = to_store<P>(post, a.scale);
         if (NT)
-            __builtin_nontemporal_store(out, &a.dst[(int64_t)i * a.stride + n]);
+            __builtin_nontemporal_store(out, &dst[(int64_t)i * a.stride + n]);
         else
-            a.dst[(int64_t)i * a.stride + n] = out;
+            dst[(int64_t)i * a.stride + n] = out;
     }
+    if constexpr (std::is_same<T, _Float16>::value) a.drho_dst[n] = drho;
     if (CHECK) {
         const double dux = (double)ux - (double)a.usnap[n];
         const double duy = (double)uy - (double)a.usnap[a.stride + n];
         const double duz = (double)uz - (double)a.usnap[2 * a.stride + n];
         acc[0] += dux * dux + duy * duy + duz * duz;
         acc[1] += (double)ux * ux + (double)uy * uy + (double)uz * uz;
-        acc[2] += (double)jx + 0.5 * (double)a.Fx;
-        acc[3] += (double)jy + 0.5 * (double)a.Fy;
-        acc[4] += (double)jz + 0.5 * (double)a.Fz;
+        acc[2] += (double)jx + 0.5 * (double)Fx;
+        acc[3] += (double)jy + 0.5 * (double)Fy;
+        acc[4] += (double)jz + 0.5 * (double)Fz;
         acc[5] += drho;
         if (a.update_snap) {
-            a.usnap[n] = ux;
-            a.usnap[a.stride + n] = uy;
-            a.usnap[2 * a.stride + n] = uz;
+            a.usnap[n] = (float)ux;
+            a.usnap[a.stride + n] = (float)uy;
+            a.usnap[2 * a.stride + n] = (float)uz;
         }
         if (a.u_out) {
             const int64_t v = a.g.lin(x, y, z), nv = a.g.nvox();
-            a.u_out[v] = ux;
-            a.u_out[nv + v] = uy;
-            a.u_out[2 * nv + v] = uz;
+            a.u_out[v] = (float)ux;
+            a.u_out[nv + v] = (float)uy;
+            a.u_out[2 * nv + v] = (float)uz;
+            if (a.with_rho) a.u_out[3 * nv + v] = (float)drho;
         }
     }
 }
@@ -181,10 +276,10 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
 // One stream-collide step, one fluid node per thread, neighbour ids gathered from the
 // global id map.  CHECK also forms the FP64 partial sums of the convergence check and
 // writes the velocity snapshot / field.
-template <bool CHECK, bool NT>
+template <class P, bool CHECK, bool NT>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
     LBM_D3Q19_TABLES
-    const int64_t lb = a.remap ? xcd_block(blockIdx.x, a.launched) : (int64_t)blockIdx.x;
+    const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
     if (n < a.nf) {
@@ -212,40 +307,51 @@ __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
         ids[0] = 0;
 #pragma unroll
         for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
-        node19<CHECK, NT>(a, n, x, y, z, ids, acc);
+        node19<P, CHECK, NT>(a, n, x, y, z, ids, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
-// f - w_i at the equilibrium of rho = 1 and u_init (zero without it); the snapshot
-// starts at u_init.
+// f - w_i at the equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x,
+// u_y, u_z and, with with_rho, rho - 1; rest and rho = 1 without it); the snapshot
+// starts at that u.
+template <class P>
 __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t stride,
                                                    const uint32_t *__restrict__ coords,
-                                                   const float *__restrict__ u_init,
-                                                   float *__restrict__ f,
+                                                   const float *__restrict__ u_init, int with_rho,
+                                                   typename P::T *__restrict__ f, float scale,
+                                                   float *__restrict__ drho,
                                                    float *__restrict__ usnap) {
+    using R = typename P::R;
     LBM_D3Q19_TABLES
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (n >= nf) return;
-    float ux = 0.f, uy = 0.f, uz = 0.f;
+    R ux = 0, uy = 0, uz = 0, dr = 0;
     if (u_init) {
         const uint32_t c = coords[n];
         const int64_t v = g.lin(c & 1023, (c >> 10) & 1023, c >> 20), nv = g.nvox();
         ux = u_init[v]; uy = u_init[nv + v]; uz = u_init[2 * nv + v];
+        if (with_rho) dr = u_init[3 * nv + v];
     }
-    const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+    const R rho = R(1) + dr;
+    const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
-        const float w = i == 0 ? 1.0f / 3.0f : (i < 7 ? 1.0f / 18.0f : 1.0f / 36.0f);
-        const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-        f[(int64_t)i * stride + n] = w * (3.0f * eu + 4.5f * eu * eu - uu15);
+        const R w = i == 0 ? R(1) / R(3) : (i < 7 ? R(1) / R(18) : R(1) / R(36));
+        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        R dev = w * rho * (R(3) * eu + R(4.5) * eu * eu - uu15);  // f_eq - w_i (1 + drho)
+        if (!drho) dev += w * dr;                                 // f_eq - w_i
+        f[(int64_t)i * stride + n] = to_store<P>(dev, scale);
     }
-    usnap[n] = ux; usnap[stride + n] = uy; usnap[2 * stride + n] = uz;
+    usnap[n] = (float)ux; usnap[stride + n] = (float)uy; usnap[2 * stride + n] = (float)uz;
+    if (drho) drho[n] = (float)dr;
 }
 
+template <class P>
 __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
                               const int64_t *__restrict__ vox, const RankWord *__restrict__ rank,
-                              const float *__restrict__ f, double *__restrict__ out,
+                              const typename P::T *__restrict__ f, float inv_scale,
+                              const float *__restrict__ drho, double *__restrict__ out,
                               uint8_t *__restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
@@ -253,7 +359,12 @@ __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
     const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
     const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
-    for (int i = 0; i < 19; i++) out[s * 19 + i] = id >= 0 ? (double)f[(int64_t)i * stride + id] : 0.0;
+    for (int i = 0; i < 19; i++) {
+        double v = id >= 0 ? (double)from_store<P>(f[(int64_t)i * stride + id], inv_scale) : 0.0;
+        if (drho && id >= 0)  // binary16: offsets are taken from w_i (1 + drho) of the node
+            v += (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)) * (double)drho[id];
+        out[s * 19 + i] = v;
+    }
 }
 
 // Kernel variant: explicit bits, or chosen from the working set: when the two
@@ -264,34 +375,42 @@ struct Variant19 {
     bool remap, nt;
 };
 
-static Variant19 pick_variant(int32_t v, int64_t stride) {
+static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
     Variant19 m;
     if (v & LBM_VARIANT_EXPLICIT) {
         m.remap = v & LBM_VARIANT_REMAP;
         m.nt = v & LBM_VARIANT_NTSTORE;
         return m;
     }
-    const bool stream = 2.0 * 19 * 4 * (double)stride > 192e6;
+    const bool stream = 2.0 * 19 * pop_bytes(storage) * (double)stride > 192e6;
     m.remap = !stream;
     m.nt = stream;
     return m;
 }
 
-template <bool CHECK>
-static void launch19(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
+template <class P, bool CHECK>
+static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep19<CHECK, true><<<grid, 256, 0, s>>>(a);
-    else k_sweep19<CHECK, false><<<grid, 256, 0, s>>>(a);
+    if (m.nt) k_sweep19<P, CHECK, true><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<P, CHECK, false><<<grid, 256, 0, s>>>(a);
+}
+
+template <bool CHECK>
+static void launch19(const Sweep19 &a, const Variant19 &m, int32_t storage, hipStream_t s) {
+    if (storage == LBM_STORE_FP16) launch19p<StoreF16, CHECK>(a, m, s);
+    else if (storage == LBM_STORE_FP64) launch19p<StoreF64, CHECK>(a, m, s);
+    else launch19p<StoreF32, CHECK>(a, m, s);
 }
 
 static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, const FlowHeader &h,
                                 const Variant19 &m, int &cur, int64_t steps, bool check_last,
-                                float *u_out, hipStream_t s) {
+                                float *u_out, int with_rho, hipStream_t s) {
     Sweep19 a;
     a.g = g;
     a.nf = nf;
     a.stride = w.stride;
-    a.launched = xcd_launch(blocks_for(nf));
+    a.chunk = m.remap ? (blocks_for(nf) + kXcd - 1) / kXcd : 0;
+    a.launched = a.chunk ? xcd_launch(blocks_for(nf), a.chunk) : blocks_for(nf);
     a.coords = w.coords;
     a.rank = w.rank;
     a.omega = (float)(1.0 / h.tau);
@@ -299,18 +418,25 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
     a.Fx = (float)h.force[0];
     a.Fy = (float)h.force[1];
     a.Fz = (float)h.force[2];
-    a.remap = m.remap;
+    a.omega_d = 1.0 / h.tau;
+    a.fpre_d = 1.0 - 0.5 / h.tau;
+    for (int k = 0; k < 3; k++) a.Fd[k] = h.force[k];
+    a.scale = (float)h.scale;
+    a.inv_scale = (float)(1.0 / h.scale);
     a.usnap = w.usnap;
     a.u_out = u_out;
     a.partials = w.partials;
     a.update_snap = 1;
+    a.with_rho = with_rho;
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
+        a.drho_src = w.drho[cur];
+        a.drho_dst = w.drho[cur ^ 1];
         if (check_last && t == steps - 1)
-            launch19<true>(a, m, s);
+            launch19<true>(a, m, h.storage, s);
         else
-            launch19<false>(a, m, s);
+            launch19<false>(a, m, h.storage, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
@@ -330,9 +456,9 @@ static lbm_status validate_n(const int32_t n[3]) {
 }
 
 namespace lbm {
-size_t flow_ws_bytes_n(const int32_t n[3], int64_t nf) {
+size_t flow_ws_bytes_n(const int32_t n[3], int64_t nf, int32_t storage) {
     Grid g = make_grid(n);
-    return flow_ws_bytes(g, nf < 0 ? g.nvox() : nf);
+    return flow_ws_bytes(g, nf < 0 ? g.nvox() : nf, storage);
 }
 }  // namespace lbm
 
@@ -346,23 +472,26 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE(p->tau > 0.5 && std::isfinite(p->tau), LBM_E_INVAL, "tau must exceed 1/2");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
-    LBM_REQUIRE(p->storage == LBM_STORE_FP32, LBM_E_INVAL, "unknown storage %d", p->storage);
+    LBM_REQUIRE(p->storage == LBM_STORE_FP32 || p->storage == LBM_STORE_FP16 ||
+                    p->storage == LBM_STORE_FP64,
+                LBM_E_INVAL, "unknown storage %d", p->storage);
     LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
+    LBM_REQUIRE(p->with_rho == 0 || p->with_rho == 1, LBM_E_INVAL, "with_rho must be 0 or 1");
     st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Grid g = make_grid(n);
 
     // the grid-sized part of the workspace comes first: count the fluid nodes there
-    FlowWs w0 = carve_flow(workspace, g, 1);
+    FlowWs w0 = carve_flow(workspace, g, 1, p->storage);
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
     st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
-    FlowWs w = carve_flow(workspace, g, nf);
+    FlowWs w = carve_flow(workspace, g, nf, p->storage);
     LBM_REQUIRE(19 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
                 "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
@@ -376,8 +505,9 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         LBM_REQUIRE(h.magic == kFlowMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
-                        h.n_fluid == nf,
-                    LBM_E_INVAL, "resume: the workspace holds no state for this geometry");
+                        h.n_fluid == nf && h.storage == p->storage,
+                    LBM_E_INVAL,
+                    "resume: the workspace holds no state for this geometry and storage");
         t0 = h.steps_done;
         cur = h.cur;
     }
@@ -388,15 +518,35 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     h.n_fluid = nf;
     h.tau = p->tau;
     h.variant = p->variant;
-    h.reserved = 0;
-    const Variant19 mode = pick_variant(p->variant, w.stride);
+    h.storage = p->storage;
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
-        k_flow_init<<<(unsigned)blocks_for(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, u_init,
-                                                             w.f[0], w.usnap);
+        // binary16: a power of two S with S max|F| in [1, 2) (1 without a force)
+        const double fmax = std::max(std::fabs(p->force[0]),
+                                     std::max(std::fabs(p->force[1]), std::fabs(p->force[2])));
+        h.scale = p->storage == LBM_STORE_FP16 && fmax > 0 ? std::ldexp(1.0, -std::ilogb(fmax)) : 1.0;
+    }
+    const Variant19 mode = pick_variant(p->variant, w.stride, h.storage);
+    if (!p->resume) {
+        const unsigned nb = (unsigned)blocks_for(nf);
+        const float sc = (float)h.scale;
+        const int wr = p->with_rho;
+        if (h.storage == LBM_STORE_FP16)
+            k_flow_init<StoreF16><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
+                                                     static_cast<_Float16 *>(w.f[0]), sc,
+                                                     w.drho[0], w.usnap);
+        else if (h.storage == LBM_STORE_FP64)
+            k_flow_init<StoreF64><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
+                                                     static_cast<double *>(w.f[0]), sc,
+                                                     nullptr, w.usnap);
+        else
+            k_flow_init<StoreF32><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
+                                                     static_cast<float *>(w.f[0]), sc,
+                                                     nullptr, w.usnap);
         LBM_CHECK_LAUNCH();
     }
-    if (u_out) LBM_TRY_HIP(hipMemsetAsync(u_out, 0, sizeof(float) * 3 * g.nvox(), s));
+    if (u_out)
+        LBM_TRY_HIP(hipMemsetAsync(u_out, 0, sizeof(float) * (p->with_rho ? 4 : 3) * g.nvox(), s));
 
     hipEvent_t e0, e1;
     LBM_TRY_HIP(hipEventCreate(&e0));
@@ -405,7 +555,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     const int nc = p->check_every;
     double sums[kFlowSums] = {0, 0, 0, 0, 0, 0};
     double resid = INFINITY, sweep_ms = 0.0;
-    bool converged = false, diverged = false;
+    bool converged = false, diverged = false, stalled = false;
     int64_t t = 0;
     lbm_status out = LBM_OK;
     while (t < limit) {
@@ -414,7 +564,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         int64_t chunk = nc - (abs_t % nc);
         if (chunk > limit - t) chunk = limit - t;
         LBM_TRY_HIP(hipEventRecord(e0, s));
-        out = launch_sweeps(w, g, nf, h, mode, cur, chunk, true, u_out, s);
+        out = launch_sweeps(w, g, nf, h, mode, cur, chunk, true, u_out, p->with_rho, s);
         if (out != LBM_OK) break;
         LBM_TRY_HIP(hipEventRecord(e1, s));
         out = reduce_partials(w.partials, blocks_for(nf), kFlowSums, w.res, s);
@@ -431,6 +581,14 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         }
         if ((t0 + t) % nc == 0) {
             resid = std::sqrt(sums[0]) / ((double)nc * std::sqrt(sums[1]));
+            // binary16: a check interval with no change at all is a fixed point of the
+            // rounded iteration (every per-step increment below half an ulp), not steady
+            // state; the solve stops and says so
+            if (p->fixed_steps <= 0 && h.storage == LBM_STORE_FP16 && sums[0] == 0.0 &&
+                sums[1] > 0.0) {
+                stalled = true;
+                break;
+            }
             if (p->fixed_steps <= 0 && resid < p->tol) {
                 converged = true;
                 break;
@@ -461,12 +619,17 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     r->sweep_ms = sweep_ms;
     const double updates = (double)nf * (double)t;
     r->mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
-    r->gbps = sweep_ms > 0 ? updates * 152.0 / (sweep_ms * 1e-3) / 1e9 : 0.0;
+    r->gbps = sweep_ms > 0 ? updates * flow_bytes_per_update(h.storage) / (sweep_ms * 1e-3) / 1e9 : 0.0;
     if (diverged) {
         set_error("flow solve diverged (NaN/Inf) by step %lld", (long long)(t0 + t));
         return LBM_E_DIVERGED;
     }
     if (p->fixed_steps > 0 || converged) return LBM_OK;
+    if (stalled) {
+        set_error("binary16 state stalled after %lld steps (no change over a check interval)",
+                  (long long)t);
+        return LBM_W_NOT_CONVERGED;
+    }
     set_error("flow solve not converged after %lld steps (residual %.3e)", (long long)t, resid);
     return LBM_W_NOT_CONVERGED;
 }
@@ -481,7 +644,7 @@ static lbm_status read_flow_state(void *workspace, size_t ws_bytes, hipStream_t 
     LBM_REQUIRE(h.magic == kFlowMagic, LBM_E_INVAL, "the workspace holds no flow state");
     const int32_t n[3] = {h.nx, h.ny, h.nz};
     g = make_grid(n);
-    w = carve_flow(workspace, g, h.n_fluid);
+    w = carve_flow(workspace, g, h.n_fluid, h.storage);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace smaller than its state");
     return LBM_OK;
 }
@@ -495,8 +658,8 @@ extern "C" lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t st
     if (st != LBM_OK) return st;
     LBM_REQUIRE(steps >= 0, LBM_E_INVAL, "negative step count");
     int cur = h.cur;
-    st = launch_sweeps(w, g, h.n_fluid, h, pick_variant(h.variant, w.stride), cur, steps, false,
-                       nullptr, s);
+    st = launch_sweeps(w, g, h.n_fluid, h, pick_variant(h.variant, w.stride, h.storage), cur, steps, false,
+                       nullptr, 0, s);
     if (st != LBM_OK) return st;
     h.cur = cur;
     h.steps_done += steps;
@@ -521,9 +684,20 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
         LBM_REQUIRE(vox_h[i] >= 0 && vox_h[i] < g.nvox(), LBM_E_INVAL, "voxel %lld out of range",
                     (long long)vox_h[i]);
     LBM_TRY_HIP(hipMemcpyAsync(w.samp_vox, vox_h, sizeof(int64_t) * count, hipMemcpyHostToDevice, s));
-    k_flow_sample<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(g, count, w.stride, w.samp_vox,
-                                                                 w.rank, w.f[h.cur], w.samp_out,
-                                                                 w.samp_flag);
+    const unsigned nb = (unsigned)((count + 255) / 256);
+    const float inv = (float)(1.0 / h.scale);
+    if (h.storage == LBM_STORE_FP16)
+        k_flow_sample<StoreF16><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+                                                   static_cast<const _Float16 *>(w.f[h.cur]), inv,
+                                                   w.drho[h.cur], w.samp_out, w.samp_flag);
+    else if (h.storage == LBM_STORE_FP64)
+        k_flow_sample<StoreF64><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+                                                   static_cast<const double *>(w.f[h.cur]), inv,
+                                                   nullptr, w.samp_out, w.samp_flag);
+    else
+        k_flow_sample<StoreF32><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+                                                   static_cast<const float *>(w.f[h.cur]), inv,
+                                                   nullptr, w.samp_out, w.samp_flag);
     LBM_CHECK_LAUNCH();
     LBM_TRY_HIP(hipMemcpyAsync(f_h, w.samp_out, sizeof(double) * 19 * count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(fluid_h, w.samp_flag, count, hipMemcpyDeviceToHost, s));

@@ -116,7 +116,7 @@ struct Sweep7 {
     const float *__restrict__ src;
     float *__restrict__ dst;
     const Shift *__restrict__ shift;
-    int remap;                         // XCD-contiguous workgroup order
+    int64_t chunk;                     // XCD remap run length in blocks (0: none)
     // check variant
     const double *__restrict__ ref_out;
     float *__restrict__ csnap;
@@ -192,7 +192,7 @@ __device__ inline void write_partials7(double (&acc)[NV], int64_t row, bool vali
 // One step, one fluid node per thread, neighbour ids found through the rank map.
 template <bool CHECK, bool NT>
 __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
-    const int64_t lb = a.remap ? xcd_block(blockIdx.x, a.launched) : (int64_t)blockIdx.x;
+    const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
     if (n < a.nf) {
@@ -427,11 +427,11 @@ static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, KnHeader &
     a.g = g;
     a.nf = nf;
     a.stride = w.stride;
-    a.launched = xcd_launch(kn_blocks(nf));
+    a.chunk = m.remap ? (kn_blocks(nf) + kXcd - 1) / kXcd : 0;
+    a.launched = a.chunk ? xcd_launch(kn_blocks(nf), a.chunk) : kn_blocks(nf);
     a.coords = w.coords;
     a.rank = w.rank;
     a.omega = w.omega;
-    a.remap = m.remap;
     a.csnap = w.csnap;
     a.c_out = c_field;
     a.partials = w.partials;

@@ -97,14 +97,20 @@ constexpr int32_t kVariantBits = LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_
 
 // ---------------------------------------------------------------- XCD-aware mapping
 // Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD b % 8).
-// Remap so that each XCD walks one contiguous run of logical blocks: neighbouring
-// rows of a column then share an L2.  `launched` is a multiple of 8.
+// Remap so that each XCD walks runs of `chunk` consecutive logical blocks, the 8 XCDs
+// side by side: neighbouring rows of a column then share an L2.  The launch holds
+// xcd_launch(blocks, chunk) workgroups (a multiple of 8 * chunk, so the map is a
+// permutation of it); logical blocks >= blocks have no work.  chunk = ceil(blocks / 8)
+// gives each XCD one contiguous eighth of the list.
 constexpr int kXcd = 8;
-__device__ inline int64_t xcd_block(int64_t b, int64_t launched) {
-    int64_t per = launched / kXcd;
-    return (b % kXcd) * per + b / kXcd;
+__device__ inline int64_t xcd_block(int64_t b, int64_t chunk) {
+    const int64_t x = b % kXcd, j = b / kXcd;
+    return (j / chunk) * (kXcd * chunk) + x * chunk + j % chunk;
 }
-inline int64_t xcd_launch(int64_t blocks) { return (blocks + kXcd - 1) / kXcd * kXcd; }
+inline int64_t xcd_launch(int64_t blocks, int64_t chunk = 1) {
+    const int64_t g = kXcd * (chunk > 0 ? chunk : 1);
+    return (blocks + g - 1) / g * g;
+}
 
 // ---------------------------------------------------------------- reductions
 // Deterministic FP64 block reduction of NV values per thread.  Block size 256

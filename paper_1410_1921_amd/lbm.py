@@ -19,7 +19,10 @@ LBM_OK, LBM_W_NOT_CONVERGED = 0, 1
 LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_RECON_STALL, LBM_E_DIVERGED = -1, -2, -3, -4, -5
 LBM_PSD_CHORD13, LBM_PSD_MIS = 0, 1
 LBM_WS_LABEL, LBM_WS_PORE_DIAM, LBM_WS_FLOW, LBM_WS_KNUDSEN = 0, 1, 2, 3
-LBM_STORE_FP32 = 0
+LBM_WS_FLOW_FP16, LBM_WS_FLOW_FP64 = 4, 5
+LBM_STORE_FP32, LBM_STORE_FP16, LBM_STORE_FP64 = 0, 1, 2
+_WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
+                 LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
 
 _STATUS = {0: "OK", 1: "W_NOT_CONVERGED", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE",
@@ -53,7 +56,7 @@ class lbm_flow_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("force", C.c_double * 3), ("max_steps", C.c_int64),
                 ("fixed_steps", C.c_int64), ("check_every", C.c_int32), ("storage", C.c_int32),
                 ("tol", C.c_double), ("voxel_nm", C.c_double), ("resume", C.c_int32),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("with_rho", C.c_int32), ("reserved", C.c_int32)]
 
 
 class lbm_flow_result(C.Structure):
@@ -276,20 +279,27 @@ class Solve:
 
 def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
                    check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False, u_init=None,
-                   workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO):
+                   workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
+                   storage=LBM_STORE_FP32, with_rho=False):
+    """D3Q19 flow solve.  With with_rho the velocity field (want_u) and u_init carry a
+    fourth plane, rho - 1."""
     _vol(fluid, torch.uint8, "fluid")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
     if workspace is None:
-        workspace = Workspace(lbm_workspace_size(LBM_WS_FLOW, fluid.shape, n_fluid), fluid.device)
+        workspace = Workspace(lbm_workspace_size(_WS_FLOW_KIND.get(storage, LBM_WS_FLOW),
+                                                 fluid.shape, n_fluid), fluid.device)
+    planes = 4 if with_rho else 3
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
-                        LBM_STORE_FP32, tol, voxel_nm, int(bool(resume)), int(variant))
+                        int(storage), tol, voxel_nm, int(bool(resume)), int(variant),
+                        int(bool(with_rho)), 0)
     r = lbm_flow_result()
-    u = torch.empty((3,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
+    u = torch.empty((planes,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
         if want_u else None
     if u_init is not None and not (u_init.is_cuda and u_init.dtype == torch.float32 and
-                                   u_init.is_contiguous() and u_init.numel() == 3 * fluid.numel()):
-        raise ValueError("u_init must be a contiguous float32 CUDA tensor (3, nz, ny, nx)")
+                                   u_init.is_contiguous() and
+                                   u_init.numel() == planes * fluid.numel()):
+        raise ValueError(f"u_init must be a contiguous float32 CUDA tensor ({planes}, nz, ny, nx)")
     st = _check(load().lbm_flow_solve(_n3(fluid.shape), _ptr(fluid), C.byref(p), C.byref(r),
                                       _ptr(u), _ptr(u_init), workspace.ptr, workspace.nbytes,
                                       _stream()), "lbm_flow_solve")

@@ -53,6 +53,13 @@ def test_workspace_sizes(lib):
     # n_fluid < 0 sizes for every voxel
     assert lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), -1) >= \
         lib.lbm_workspace_size(lib.LBM_WS_FLOW, (32, 32, 32), 32 ** 3)
+    # binary16 / binary64 storage: 2 and 8 bytes per population (binary16 adds the
+    # two binary32 writer-density arrays)
+    s16 = [lib.lbm_workspace_size(lib.LBM_WS_FLOW_FP16, (32, 32, 32), m) for m in (1000, 20000)]
+    s64 = [lib.lbm_workspace_size(lib.LBM_WS_FLOW_FP64, (32, 32, 32), m) for m in (1000, 20000)]
+    assert s16[1] - s16[0] >= 2 * (19 * 2 + 4) * 19000
+    assert s16[1] - s16[0] < s_big - s_small < s64[1] - s64[0]
+    assert s64[1] - s64[0] >= 2 * 19 * 8 * 19000
     assert lib.lbm_workspace_size(lib.LBM_WS_KNUDSEN, (16, 16, 16), 100) > 0
     assert lib.lbm_workspace_size(lib.LBM_WS_LABEL, (16, 16, 16)) >= 2 * 16 ** 3
     assert lib.lbm_workspace_size(lib.LBM_WS_PORE_DIAM, (16, 16, 16)) >= 12 * 16 ** 3
@@ -89,6 +96,12 @@ def test_argument_checks_before_device(lib):
     assert L.lbm_pore_diameter(n, dummy, 5, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
     nbad = (C.c_int32 * 3)(0, 8, 8)
     assert L.lbm_pore_diameter(nbad, dummy, 0, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
+    # unknown storage and with_rho values are rejected
+    for storage, wr in ((3, 0), (-1, 0), (0, 2)):
+        p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, storage, 1e-7, 1.0,
+                                0, 0, wr, 0)
+        assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
+                                None) == lib.LBM_E_INVAL
     # variant bits other than EXPLICIT | REMAP | NTSTORE are rejected by both solves
     for bad in (2, 16, 1 << 20, -1):
         p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, 0, 1e-7, 1.0, 0, bad)

@@ -144,3 +144,26 @@ def test_collision_invariants(orc):
     assert np.allclose(fout @ e, fin @ e + F, rtol=0, atol=1e-16)
     assert mom[0] == pytest.approx(fin.sum(), abs=1e-15)
     assert np.allclose(mom[1:], fin @ e + F / 2, rtol=0, atol=1e-16)
+
+
+def test_init_equilibrium_moments(orc):
+    # the D3Q19 equilibrium (Eq. 3) has density rho, momentum rho u and momentum flux
+    # rho (I/3 + u u) exactly; the initial state must carry those moments at every node
+    rng = np.random.default_rng(5)
+    m = W.blob_mask((6, 7, 8), 0.6, 2)
+    u = 0.05 * rng.standard_normal((3,) + m.shape)
+    dr = 0.02 * rng.standard_normal(m.shape)
+    f = orc.flow_init(m, u, dr)
+    e = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                  [1, 1, 0], [-1, 1, 0], [1, -1, 0], [-1, -1, 0], [1, 0, 1], [-1, 0, 1],
+                  [1, 0, -1], [-1, 0, -1], [0, 1, 1], [0, -1, 1], [0, 1, -1], [0, -1, -1]], float)
+    fl = m.astype(bool)
+    rho = f.sum(-1)
+    j = np.einsum("zyxi,ia->azyx", f, e)
+    pi = np.einsum("zyxi,ia,ib->abzyx", f, e, e)
+    r_ref = 1.0 + dr
+    assert np.allclose(rho[fl], r_ref[fl], rtol=0, atol=1e-14)
+    assert np.allclose(j[:, fl], (r_ref * u)[:, fl], rtol=0, atol=1e-14)
+    want = r_ref * (np.eye(3)[:, :, None, None, None] / 3 + u[:, None] * u[None, :])
+    assert np.allclose(pi[:, :, fl], want[:, :, fl], rtol=0, atol=1e-14)
+    assert (f[~fl] == 0).all()
