@@ -24,5 +24,8 @@ Parity status of each function (what pins it, in ``tests/test_oracle_*.py``):
   columns with different tau, mass conservation, swap and linearity.
 * ``knudsen_diffusivity`` / ``fc`` -- the paper's printed D_K(60 nm, 323 K) and the
   coefficient 64/(3 pi) of Eq. 28.
+* ``nn_oracle`` (the learned warm start, not part of the paper's method) --
+  ``conv3d`` against ``scipy.ndimage.correlate``, every backward against central finite
+  differences, pooling / upsampling adjointness.
 """
 from .oracle import *  # noqa: F401,F403
