@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
 
-SOURCES = ["common.hip", "flow.hip", "knudsen.hip", "geom.hip", "recon.hip", "api.hip"]
+SOURCES = ["common.hip", "flow.hip", "knudsen.hip", "geom.hip", "recon.hip", "api.hip", "unet.hip"]
 # translation units whose FP64 results must equal their plain definitions bit for bit
 NO_CONTRACT = {"geom.hip", "recon.hip"}
 

@@ -123,6 +123,27 @@ _SIGS = {
     "lbm_version": ([], C.c_char_p),
     "lbm_sizeof": ([C.c_int32], C.c_size_t),
     "lbm_copy_probe": ([_P, _P, C.c_size_t, _P], C.c_int32),
+    # lbm_nn.h: layers of the warm-start network (wrapped in paper_1410_1921_amd.nn)
+    "lbm_nn_conv3d": ([_P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, C.c_int32,
+                       C.c_int32, _P], C.c_int32),
+    "lbm_nn_wgrad_workspace": ([_P, C.c_int32, C.c_int32], C.c_size_t),
+    "lbm_nn_conv3d_wgrad": ([_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int32, _P, _P,
+                             C.c_int32, _P, C.c_size_t, _P], C.c_int32),
+    "lbm_nn_transpose_weights": ([_P, C.c_int32, C.c_int32, _P, _P], C.c_int32),
+    "lbm_nn_pool2": ([_P, C.c_int32, _P, C.c_int32, _P, C.c_int32, C.c_int32, _P], C.c_int32),
+    "lbm_nn_pool2_bwd": ([_P, C.c_int32, _P, C.c_int32, _P, C.c_int32, C.c_int32, _P], C.c_int32),
+    "lbm_nn_up2": ([_P, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P], C.c_int32),
+    "lbm_nn_up2_bwd": ([_P, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P], C.c_int32),
+    "lbm_nn_relu_bwd": ([C.c_int64, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P, C.c_int32, _P],
+                        C.c_int32),
+    "lbm_nn_head_workspace": ([C.c_int64, C.c_int32], C.c_size_t),
+    "lbm_nn_head": ([C.c_int64, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P, C.c_double, _P,
+                     C.c_int32, _P, _P, C.POINTER(C.c_double), _P, C.c_size_t, _P], C.c_int32),
+    "lbm_nn_adam": ([C.c_int64, _P, _P, _P, _P, _P, C.c_float, C.c_float, C.c_float, C.c_float,
+                     C.c_int64, _P], C.c_int32),
+    "lbm_nn_to_bf16": ([C.c_int64, _P, _P, _P], C.c_int32),
+    "lbm_nn_make_input": ([C.c_int64, _P, _P, C.c_double, _P, C.c_int32, _P], C.c_int32),
+    "lbm_nn_to_fields": ([C.c_int64, C.c_int32, _P, _P, _P, _P, _P], C.c_int32),
 }
 
 _lib = None
