@@ -62,6 +62,27 @@ def batch_params(count=150, seed=4):
     return out
 
 
+# The learned warm start: 96^3 reconstructions drawn with the batch's parameter laws
+# (porosity U[0.2, 0.5], mean diameter U[6, 20] voxels with std = mean/4, overlap
+# tolerance U[0, 1]); training seeds 5000-5399, held-out seeds 6000-6049.  Flow and
+# Knudsen settings as in the 128^3 methane workload (2 nm voxels, CH4 at 400 K).
+WARMSTART = dict(
+    edge=96, train_seeds=range(5000, 5400), test_seeds=range(6000, 6050), voxel_nm=2.0,
+    flow=dict(tau=0.8, force=(1e-6, 0.0, 0.0), check_every=100, max_steps=400_000),
+    knudsen=dict(tau_ref=1.0, d_ref_nm=60.0, c_in=1.0, c_out=0.0, T=400.0, check_every=100,
+                 max_steps=4_000_000),
+)
+
+
+def warmstart_params(seed, edge=96):
+    """Reconstruction parameters of warm-start sample `seed`."""
+    rng = np.random.default_rng(seed)
+    dm = float(rng.uniform(6.0, 20.0))
+    return dict(n=(edge, edge, edge), porosity=float(rng.uniform(0.2, 0.5)), d_mean=dm,
+                d_std=dm / 4.0, d_min=1.0, overlap_tol=float(rng.uniform(0.0, 1.0)),
+                p_overlap=0.5, seed=int(seed), psd="mis")
+
+
 # --------------------------------------------------------------------------- geometries
 def slit(nx, ny, nz, h, axis=1):
     """Fluid slab of width h centred across `axis` (1 = y, 2 = z), solid elsewhere."""
