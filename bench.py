@@ -114,7 +114,7 @@ def roofline_512(lbm, W, steps):
     ms16 = e0.elapsed_time(e1) / steps
     del r, pore
     torch.cuda.empty_cache()
-    return {"kernel": "k_sweep19<false>", "workload": w["name"], "n_fluid": nf,
+    return {"kernel": "k_sweep19<StoreF32, false, true>", "workload": w["name"], "n_fluid": nf,
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": ms,
             "mlups": nf / (ms * 1e3),
@@ -254,9 +254,9 @@ def main():
     fl_n = sum(r["flow"]["steps"] for r in runs)
     kn_n = sum(r["knudsen"]["steps"] for r in runs)
     if kn_ms >= fl_ms:
-        name, per, bpu, ms = "k_sweep7", kn_ms / kn_n, BYTES_D3Q7, kn_ms
+        name, per, bpu, ms = "k_sweep7<false, false>", kn_ms / kn_n, BYTES_D3Q7, kn_ms
     else:
-        name, per, bpu, ms = "k_sweep19", fl_ms / fl_n, BYTES_D3Q19, fl_ms
+        name, per, bpu, ms = "k_sweep19<StoreF32, false, false>", fl_ms / fl_n, BYTES_D3Q19, fl_ms
     achieved = nf * bpu / (per * 1e-3) / 1e9
     roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
