@@ -24,6 +24,10 @@ Parity status of each function (what pins it, in ``tests/test_oracle_*.py``):
   columns with different tau, mass conservation, swap and linearity.
 * ``knudsen_diffusivity`` / ``fc`` -- the paper's printed D_K(60 nm, 323 K) and the
   coefficient 64/(3 pi) of Eq. 28.
+* ``collide19_mrt`` / ``flow_solve(collision=MRT)`` -- the inverse of Q against the
+  paper's printed Appendix A table (golden file; its misprinted row 6 noted), mass and
+  momentum conservation, equal rates reducing to BGK, and the tau-independent slit
+  permeability (H^2 + 1/2)/12 that the rates of Eq. 7 imply.
 * ``nn_oracle`` (the learned warm start, not part of the paper's method) --
   ``conv3d`` against ``scipy.ndimage.correlate``, every backward against central finite
   differences, pooling / upsampling adjointness.

@@ -452,6 +452,119 @@ void orc_collide19(const double *fin, double tau, const double *F, double *fout,
 }
 
 /*
+ * Section 3.1, Eqs. 4-7 and Appendix A: the MRT collision.  Q is the
+ * transformation matrix of Appendix A (rows: the 19 moments; columns: the
+ * velocities in the order of E19).  Its inverse is not taken from the printed
+ * table (row 6 of the printed inverse is garbled) but from the orthogonality of
+ * Q's rows: Q^{-1}[i][k] = Q[k][i] / |Q_k|^2.
+ */
+static const double Q19[19][19] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-30, -11, -11, -11, -11, -11, -11, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8},
+    {12, -4, -4, -4, -4, -4, -4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, -4, 4, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {0, 0, 0, 0, 0, -4, 4, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},
+    {0, 2, 2, -1, -1, -1, -1, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},
+    {0, -4, -4, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},
+    {0, 0, 0, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},
+    {0, 0, 0, -2, -2, 2, 2, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, 1, -1, 1, -1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1}};
+
+/* q (19x19, row-major) and its inverse */
+void orc_mrt_matrices(double *q, double *qinv) {
+    for (int k = 0; k < 19; k++) {
+        double n2 = 0.0;
+        for (int i = 0; i < 19; i++) n2 += Q19[k][i] * Q19[k][i];
+        for (int i = 0; i < 19; i++) {
+            if (q) q[19 * k + i] = Q19[k][i];
+            if (qinv) qinv[19 * i + k] = Q19[k][i] / n2;
+        }
+    }
+}
+
+/* Eq. 7: the relaxation rate of each moment (0 for the conserved ones) */
+void orc_mrt_rates(double tau, double *s) {
+    double sq = 8.0 * (2.0 * tau - 1.0) / (8.0 * tau - 1.0);
+    for (int k = 0; k < 19; k++) s[k] = 1.0 / tau;
+    s[0] = s[3] = s[5] = s[7] = 0.0;
+    s[4] = s[6] = s[8] = s[16] = s[17] = s[18] = sq;
+}
+
+/*
+ * One MRT collision (Eqs. 4-7) with the body force of the BGK collision: m = Q f;
+ * equilibrium moments A1-A9 with rho0 = 1 (reading: the mean density of the
+ * fluid at rest) and j = sum f e + F/2; m* = m - S (m - m_eq) + (I - S/2) Q F_src
+ * with Guo's source F_src,i = w_i [3 (e_i - u) + 9 (e_i.u) e_i] . F, u = j / rho;
+ * f* = Q^{-1} m*.  rates (nullable): the 19 relaxation rates, else Eq. 7.
+ * mom (out, nullable): rho, then j (= rho u).
+ */
+void orc_collide19_mrt(const double *fin, double tau, const double *rates, const double *F,
+                       double *fout, double *mom) {
+    double q[361], qinv[361], s[19];
+    orc_mrt_matrices(q, qinv);
+    if (rates) memcpy(s, rates, sizeof(s));
+    else orc_mrt_rates(tau, s);
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; i++) {
+        rho += fin[i];
+        for (int a = 0; a < 3; a++) j[a] += fin[i] * E19[i][a];
+    }
+    for (int a = 0; a < 3; a++) j[a] += 0.5 * F[a];
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    const double rho0 = 1.0;
+    double jj = (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho0;
+    double meq[19];
+    meq[0] = rho;
+    meq[1] = -11.0 * rho + 19.0 * jj;
+    meq[2] = 3.0 * rho - 5.5 * jj;
+    meq[3] = j[0]; meq[4] = -2.0 / 3.0 * j[0];
+    meq[5] = j[1]; meq[6] = -2.0 / 3.0 * j[1];
+    meq[7] = j[2]; meq[8] = -2.0 / 3.0 * j[2];
+    meq[9] = (3.0 * j[0] * j[0] / rho0 - jj);
+    meq[10] = -0.5 * meq[9];
+    meq[11] = (j[1] * j[1] - j[2] * j[2]) / rho0;
+    meq[12] = -0.5 * meq[11];
+    meq[13] = j[0] * j[1] / rho0;
+    meq[14] = j[1] * j[2] / rho0;
+    meq[15] = j[0] * j[2] / rho0;
+    meq[16] = meq[17] = meq[18] = 0.0;
+    double src[19];
+    double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    for (int i = 0; i < 19; i++) {
+        double eu = E19[i][0] * u[0] + E19[i][1] * u[1] + E19[i][2] * u[2];
+        double eF = E19[i][0] * F[0] + E19[i][1] * F[1] + E19[i][2] * F[2];
+        src[i] = w19(i) * (3.0 * (eF - uF) + 9.0 * eu * eF);
+    }
+    double mstar[19];
+    for (int k = 0; k < 19; k++) {
+        double m = 0.0, fm = 0.0;
+        for (int i = 0; i < 19; i++) {
+            m += q[19 * k + i] * fin[i];
+            fm += q[19 * k + i] * src[i];
+        }
+        mstar[k] = m - s[k] * (m - meq[k]) + (1.0 - 0.5 * s[k]) * fm;
+    }
+    for (int i = 0; i < 19; i++) {
+        double v = 0.0;
+        for (int k = 0; k < 19; k++) v += qinv[19 * i + k] * mstar[k];
+        fout[i] = v;
+    }
+    if (mom) {
+        mom[0] = rho;
+        for (int a = 0; a < 3; a++) mom[1 + a] = j[a];
+    }
+}
+
+/*
  * Streaming (pull form) for one node: f_i arrives from x - e_i (periodic in
  * x, y and z); when that neighbour is solid, half-way bounce-back returns the
  * node's own post-collision f of the opposite direction (Section 3.3).
@@ -485,7 +598,8 @@ void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u
 }
 
 /*
- * The flow solve: iterate stream + collide from the state in f (node-major
+ * The flow solve: iterate stream + collide (collision 0: BGK, orc_collide19;
+ * 1: MRT, orc_collide19_mrt) from the state in f (node-major
  * 19*N^3, in/out).  Every check_every steps (and at the last step) the
  * moments of the incoming populations give u = rho*u / rho; the residual is
  * ||u(t) - u(t - n_c)||_2 / (n_c ||u(t)||_2) over fluid nodes (reading: the
@@ -499,9 +613,9 @@ void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u
  *      [6]=sum of rho - n_fluid [7]=converged.
  * u_out (nullable): planar [3][N^3] velocity of the last step (0 at solids).
  */
-int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, const double *F,
-                   int64_t max_steps, int64_t fixed_steps, int check_every, double tol,
-                   const double *u_prev0, double *f, double *u_out, double *out) {
+int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int collision,
+                   const double *F, int64_t max_steps, int64_t fixed_steps, int check_every,
+                   double tol, const double *u_prev0, double *f, double *u_out, double *out) {
     if (!(tau > 0.5) || check_every < 1) return ORC_E_INVAL;
     int64_t nvox = (int64_t)nx * ny * nz;
     double *f0 = f; /* the caller's buffer: holds the final state on return */
@@ -533,7 +647,8 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, con
                     }
                     double fin[19], mom[4];
                     gather19(nx, ny, nz, fluid, f, x, y, z, fin);
-                    orc_collide19(fin, tau, F, g + 19 * v, mom);
+                    if (collision == 1) orc_collide19_mrt(fin, tau, NULL, F, g + 19 * v, mom);
+                    else orc_collide19(fin, tau, F, g + 19 * v, mom);
                     if (check) {
                         double du2 = 0.0, u2 = 0.0;
                         for (int a = 0; a < 3; a++) {
@@ -590,11 +705,12 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, con
  * that neighbour (row 0 is the node itself).  Gives the node's new
  * post-collision populations (same streaming and collision as the solve).
  */
-void orc_flow_update_node(const uint8_t *nb_fluid, const double *nb_f, double tau, const double *F,
-                          double *fout, double *mom) {
+void orc_flow_update_node(const uint8_t *nb_fluid, const double *nb_f, double tau, int collision,
+                          const double *F, double *fout, double *mom) {
     double fin[19];
     for (int i = 0; i < 19; i++) fin[i] = nb_fluid[i] ? nb_f[19 * i + i] : nb_f[opp19(i)];
-    orc_collide19(fin, tau, F, fout, mom);
+    if (collision == 1) orc_collide19_mrt(fin, tau, NULL, F, fout, mom);
+    else orc_collide19(fin, tau, F, fout, mom);
 }
 
 /* ======================================================================

@@ -78,12 +78,20 @@ def lib():
     L.orc_flow_init.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, _nullable(_f64p), _nullable(_f64p),
                                 _f64p]
     L.orc_flow_init.restype = None
-    L.orc_flow_solve.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, C.c_double, _f64p, C.c_int64,
-                                 C.c_int64, C.c_int, C.c_double, _nullable(_f64p), _f64p,
-                                 _nullable(_f64p), _f64p]
+    L.orc_flow_solve.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, C.c_double, C.c_int, _f64p,
+                                 C.c_int64, C.c_int64, C.c_int, C.c_double, _nullable(_f64p),
+                                 _f64p, _nullable(_f64p), _f64p]
     L.orc_flow_solve.restype = C.c_int
-    L.orc_flow_update_node.argtypes = [_u8p, _f64p, C.c_double, _f64p, _f64p, _nullable(_f64p)]
+    L.orc_flow_update_node.argtypes = [_u8p, _f64p, C.c_double, C.c_int, _f64p, _f64p,
+                                       _nullable(_f64p)]
     L.orc_flow_update_node.restype = None
+    L.orc_collide19_mrt.argtypes = [_f64p, C.c_double, _nullable(_f64p), _f64p, _f64p,
+                                    _nullable(_f64p)]
+    L.orc_collide19_mrt.restype = None
+    L.orc_mrt_matrices.argtypes = [_nullable(_f64p), _nullable(_f64p)]
+    L.orc_mrt_matrices.restype = None
+    L.orc_mrt_rates.argtypes = [C.c_double, _f64p]
+    L.orc_mrt_rates.restype = None
     L.orc_collide7.argtypes = [_f64p, C.c_double, _f64p, C.POINTER(C.c_double)]
     L.orc_collide7.restype = None
     L.orc_knudsen_init.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, _nullable(_f64p), _f64p]
@@ -224,10 +232,13 @@ def flow_init(fluid, u_init=None, drho_init=None):
     return f
 
 
+BGK, MRT = 0, 1
+
+
 def flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
-               check_every=100, tol=1e-7, f=None, u_prev0=None, want_u=True):
-    """Iterate the D3Q19 flow (see ``orc_flow_solve``).  ``f`` (node-major state) is
-    updated in place when given, else it starts from rest."""
+               check_every=100, tol=1e-7, f=None, u_prev0=None, want_u=True, collision=BGK):
+    """Iterate the D3Q19 flow (see ``orc_flow_solve``) with the BGK or the MRT collision.
+    ``f`` (node-major state) is updated in place when given, else it starts from rest."""
     fluid = np.ascontiguousarray(fluid, np.uint8)
     nz, ny, nx = fluid.shape
     if f is None:
@@ -236,8 +247,8 @@ def flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixe
     u = np.zeros((3,) + fluid.shape, np.float64) if want_u else None
     out = np.zeros(8, np.float64)
     up = None if u_prev0 is None else np.ascontiguousarray(u_prev0, np.float64)
-    st = lib().orc_flow_solve(nx, ny, nz, fluid, tau, F, max_steps, fixed_steps, check_every, tol,
-                              up, f, u, out)
+    st = lib().orc_flow_solve(nx, ny, nz, fluid, tau, int(collision), F, max_steps, fixed_steps,
+                              check_every, tol, up, f, u, out)
     if st < 0:
         raise OracleError(st, "flow_solve")
     return {"status": st, "steps": int(out[0]), "k_lattice": out[1], "residual": out[2],
@@ -253,13 +264,36 @@ def collide19(fin, tau, force):
     return fout, mom
 
 
-def flow_update_node(nb_fluid, nb_f, tau, force):
+def flow_update_node(nb_fluid, nb_f, tau, force, collision=BGK):
     fout = np.zeros(19)
     mom = np.zeros(4)
     lib().orc_flow_update_node(np.ascontiguousarray(nb_fluid, np.uint8),
-                               np.ascontiguousarray(nb_f, np.float64), tau,
+                               np.ascontiguousarray(nb_f, np.float64), tau, int(collision),
                                np.ascontiguousarray(force, np.float64), fout, mom)
     return fout, mom
+
+
+def collide19_mrt(fin, tau, force, rates=None):
+    """One MRT collision (see ``orc_collide19_mrt``); rates overrides Eq. 7."""
+    fout = np.zeros(19)
+    mom = np.zeros(4)
+    r = None if rates is None else np.ascontiguousarray(rates, np.float64)
+    lib().orc_collide19_mrt(np.ascontiguousarray(fin, np.float64), tau, r,
+                            np.ascontiguousarray(force, np.float64), fout, mom)
+    return fout, mom
+
+
+def mrt_matrices():
+    q = np.zeros((19, 19))
+    qi = np.zeros((19, 19))
+    lib().orc_mrt_matrices(q, qi)
+    return q, qi
+
+
+def mrt_rates(tau):
+    s = np.zeros(19)
+    lib().orc_mrt_rates(tau, s)
+    return s
 
 
 # ---------------------------------------------------------------- Knudsen (D3Q7)
