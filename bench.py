@@ -112,6 +112,19 @@ def roofline_512(lbm, W, steps):
     e1.record(s)
     torch.cuda.synchronize()
     ms16 = e0.elapsed_time(e1) / steps
+    del r
+    torch.cuda.empty_cache()
+    # and with the paper's MRT collision (binary32)
+    r = lbm.lbm_flow_solve(pore, tau=fp["tau"], force=fp["force"], fixed_steps=20,
+                           check_every=fp["check_every"], voxel_nm=w["voxel_nm"], n_fluid=nf,
+                           collision=lbm.LBM_COLLIDE_MRT)
+    lbm.lbm_flow_step(r.workspace, 10)
+    torch.cuda.synchronize()
+    e0.record(s)
+    lbm.lbm_flow_step(r.workspace, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms_mrt = e0.elapsed_time(e1) / steps
     del r, pore
     torch.cuda.empty_cache()
     return {"kernel": "k_sweep19<StoreF32, false, true>", "workload": w["name"], "n_fluid": nf,
@@ -119,7 +132,9 @@ def roofline_512(lbm, W, steps):
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": ms,
             "mlups": nf / (ms * 1e3),
             "fp16": {"ms_per_launch": ms16, "mlups": nf / (ms16 * 1e3),
-                     "achieved": round(nf * 84 / (ms16 * 1e-3) / 1e9, 1)}}
+                     "achieved": round(nf * 84 / (ms16 * 1e-3) / 1e9, 1)},
+            "mrt": {"ms_per_launch": ms_mrt, "mlups": nf / (ms_mrt * 1e3),
+                    "achieved": round(nf * BYTES_D3Q19 / (ms_mrt * 1e-3) / 1e9, 1)}}
 
 
 def knudsen_sweeps(lbm, w, steps):

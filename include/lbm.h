@@ -69,6 +69,14 @@ typedef int32_t lbm_status;
                             S max|F| in [1, 2) (1 when F = 0); collision in binary32 */
 #define LBM_STORE_FP64 2 /* binary64, collision in binary64 */
 
+/* collision operator of the flow solve */
+#define LBM_COLLIDE_BGK 0 /* single relaxation time 1/tau (Eq. 1) */
+#define LBM_COLLIDE_MRT 1 /* the paper's MRT (Eqs. 4-7, Appendix A): moments under its Q, rates
+                             0 (conserved), 1/tau (m1, m2, m9-m15) and
+                             s_q = 8 (2 tau - 1)/(8 tau - 1) (m4, m6, m8, m16-m18), equilibrium
+                             moments A1-A9 with rho0 = 1; the body force as Guo's source in
+                             moment space scaled by (1 - s_k/2) */
+
 /* sweep kernel variant (the `variant` field of the solve parameters): 0 lets the library
  * choose from the working-set size; otherwise LBM_VARIANT_EXPLICIT plus any of
  *   LBM_VARIANT_REMAP   workgroups ordered so that each XCD walks one contiguous region
@@ -198,7 +206,7 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  * formed from the collision arithmetic and kept in binary32 (sums in binary64) for
  * every storage.
  * Errors: LBM_E_INVAL (tau <= 1/2, check_every < 1, no fluid node, N > 1024, unknown
- * storage or variant bits), LBM_E_NOMEM, LBM_E_DIVERGED, LBM_E_DEVICE.
+ * storage, collision or variant bits), LBM_E_NOMEM, LBM_E_DIVERGED, LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
     double tau;
@@ -212,7 +220,7 @@ typedef struct {
     int32_t resume;       /* 1: continue from the state in the workspace */
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
     int32_t with_rho;     /* 1: u_init / u_out carry rho - 1 as a fourth plane */
-    int32_t reserved;     /* 0 */
+    int32_t collision;    /* LBM_COLLIDE_BGK or LBM_COLLIDE_MRT */
 } lbm_flow_params;
 
 typedef struct {

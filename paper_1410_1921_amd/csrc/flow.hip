@@ -40,7 +40,7 @@ namespace lbm {
     [[maybe_unused]] constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8,                  \
                                               7, 14, 13, 12, 11, 18, 17, 16, 15};
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5732ull;  // "LBMFLOW2"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5733ull;  // "LBMFLOW3"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -51,6 +51,7 @@ struct FlowHeader {
     double tau, force[3];
     int32_t variant, storage;
     double scale;  // binary16 storage: stored = scale * (f_i - w_i)
+    int32_t collision, reserved;
 };
 
 // Storage policies: T is the stored type, R the collision arithmetic.
@@ -159,8 +160,8 @@ struct Sweep19 {
     void *__restrict__ dst;
     const float *__restrict__ drho_src;  // binary16 storage only
     float *__restrict__ drho_dst;
-    float omega, fpre, Fx, Fy, Fz;     // collision parameters for binary32 arithmetic
-    double omega_d, fpre_d, Fd[3];     // and for binary64
+    float omega, fpre, Fx, Fy, Fz, sq; // collision parameters for binary32 arithmetic
+    double omega_d, fpre_d, Fd[3], sq_d;  // and for binary64 (sq: the MRT rate s_q)
     float scale, inv_scale;            // binary16 storage scale
     int64_t chunk;                     // XCD remap run length in blocks (0: none)
     // check variant
@@ -176,9 +177,97 @@ struct Sweep19 {
 //   NT: populations are written with streaming (non-temporal) stores; right when the
 //     arrays far exceed the 256 MB Infinity Cache, wrong when they fit in it.
 
+// The MRT collision (Section 3.1, Eqs. 4-7, Appendix A) on the offsets f_i - w_i: their
+// moments under the transformation matrix Q of Appendix A (rows: moments, columns: the
+// velocities in the order above), relaxed towards the equilibrium moments A1-A9 (rho0 = 1,
+// j including F/2; written as offsets from those of rest) at the rates of Eq. 7, plus
+// Guo's source in moment space scaled by (1 - s_k/2); back through Q^-1 = Q^T / |Q_k|^2
+// (Q's rows are orthogonal).
+#define LBM_MRT_Q                                                                                  \
+    constexpr int MQ[19][19] = {                                                                   \
+        {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},                                 \
+        {-30, -11, -11, -11, -11, -11, -11, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8},                   \
+        {12, -4, -4, -4, -4, -4, -4, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1},                          \
+        {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},                            \
+        {0, -4, 4, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0},                            \
+        {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},                            \
+        {0, 0, 0, -4, 4, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1},                            \
+        {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},                            \
+        {0, 0, 0, 0, 0, -4, 4, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1},                            \
+        {0, 2, 2, -1, -1, -1, -1, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},                         \
+        {0, -4, -4, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, -2, -2, -2, -2},                           \
+        {0, 0, 0, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},                           \
+        {0, 0, 0, -2, -2, 2, 2, 1, 1, 1, 1, -1, -1, -1, -1, 0, 0, 0, 0},                           \
+        {0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 0, 0},                               \
+        {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1},                               \
+        {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0},                               \
+        {0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1, 0, 0, 0, 0},                             \
+        {0, 0, 0, 0, 0, 0, 0, -1, -1, 1, 1, 0, 0, 0, 0, 1, -1, 1, -1},                             \
+        {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, -1, -1, -1, -1, 1, 1}};
+
+constexpr int mrt_norm2(int k) {
+    LBM_MRT_Q
+    int s = 0;
+    for (int i = 0; i < 19; i++) s += MQ[k][i] * MQ[k][i];
+    return s;
+}
+
+// Relaxation class of moment k under Eq. 7: 0 conserved, 1 rate 1/tau, 2 rate s_q.
+constexpr int mrt_class(int k) {
+    return (k == 0 || k == 3 || k == 5 || k == 7) ? 0
+           : (k == 4 || k == 6 || k == 8 || k >= 16) ? 2
+                                                       : 1;
+}
+
+template <class R>
+__device__ inline void mrt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R ux, R uy, R uz,
+                                   R Fx, R Fy, R Fz, R s_nu, R s_q, R (&out)[19]) {
+    LBM_D3Q19_TABLES
+    LBM_MRT_Q
+    const R W0 = R(1) / R(3), W1 = R(1) / R(18), W2 = R(1) / R(36);
+    R srcv[19];
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
+        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
+        srcv[i] = w * (R(3) * (eF - uF) + R(9) * eu * eF);
+    }
+    const R jj = jx * jx + jy * jy + jz * jz;
+    const R t9 = R(3) * jx * jx - jj, t11 = jy * jy - jz * jz;
+    const R meq[19] = {drho, R(-11) * drho + R(19) * jj, R(3) * drho - R(5.5) * jj,
+                       jx, R(-2) / R(3) * jx, jy, R(-2) / R(3) * jy, jz, R(-2) / R(3) * jz,
+                       t9, R(-0.5) * t9, t11, R(-0.5) * t11, jx * jy, jy * jz, jx * jz,
+                       R(0), R(0), R(0)};
+    R ms[19];
+#pragma unroll
+    for (int k = 0; k < 19; k++) {
+        R m = 0, fm = 0;
+#pragma unroll
+        for (int i = 0; i < 19; i++) {
+            if (MQ[k][i] == 0) continue;
+            m += R(MQ[k][i]) * f[i];
+            fm += R(MQ[k][i]) * srcv[i];
+        }
+        const R sk = mrt_class(k) == 0 ? R(0) : (mrt_class(k) == 1 ? s_nu : s_q);
+        ms[k] = (m - sk * (m - meq[k]) + (R(1) - R(0.5) * sk) * fm) / R(mrt_norm2(k));
+    }
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        R v = 0;
+#pragma unroll
+        for (int k = 0; k < 19; k++) {
+            if (MQ[k][i] == 0) continue;
+            v += R(MQ[k][i]) * ms[k];
+        }
+        out[i] = v;
+    }
+}
+
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
-template <class P, bool CHECK, bool NT>
+template <class P, bool CHECK, bool NT, bool MRT>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
                               const int (&ids)[19], double (&acc)[kFlowSums]) {
     using T = typename P::T;
@@ -220,16 +309,27 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     const R inv = R(1) / rho;
     const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
     const R ux = mx * inv, uy = my * inv, uz = mz * inv;
-    const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
-    const R uF = ux * Fx + uy * Fy + uz * Fz;
+    R posts[19];
+    if constexpr (MRT) {
+        mrt_collide<R>(f, drho, mx, my, mz, ux, uy, uz, Fx, Fy, Fz, omega, par<R>(a.sq, a.sq_d),
+                       posts);
+    } else {
+        const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+        const R uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+        for (int i = 0; i < 19; i++) {
+            const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
+            const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+            const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
+            const R feq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - uu15));
+            const R srcf = fpre * w * (R(3) * (eF - uF) + R(9) * eu * eF);
+            posts[i] = f[i] - omega * (f[i] - feq) + srcf;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
-        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-        const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
-        const R feq = w * (drho + rho * (R(3) * eu + R(4.5) * eu * eu - uu15));
-        const R srcf = fpre * w * (R(3) * (eF - uF) + R(9) * eu * eF);
-        R post = f[i] - omega * (f[i] - feq) + srcf;
+        R post = posts[i];
         if constexpr (std::is_same<T, _Float16>::value) post -= w * drho;
         const T out = to_store<P>(post, a.scale);
         if (NT)
@@ -276,7 +376,7 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
 // One stream-collide step, one fluid node per thread, neighbour ids gathered from the
 // global id map.  CHECK also forms the FP64 partial sums of the convergence check and
 // writes the velocity snapshot / field.
-template <class P, bool CHECK, bool NT>
+template <class P, bool CHECK, bool NT, bool MRT>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
     LBM_D3Q19_TABLES
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
@@ -307,7 +407,7 @@ __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
         ids[0] = 0;
 #pragma unroll
         for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
-        node19<P, CHECK, NT>(a, n, x, y, z, ids, acc);
+        node19<P, CHECK, NT, MRT>(a, n, x, y, z, ids, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
@@ -388,18 +488,25 @@ static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
     return m;
 }
 
-template <class P, bool CHECK>
+template <class P, bool CHECK, bool MRT>
 static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep19<P, CHECK, true><<<grid, 256, 0, s>>>(a);
-    else k_sweep19<P, CHECK, false><<<grid, 256, 0, s>>>(a);
+    if (m.nt) k_sweep19<P, CHECK, true, MRT><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<P, CHECK, false, MRT><<<grid, 256, 0, s>>>(a);
+}
+
+template <bool CHECK, bool MRT>
+static void launch19c(const Sweep19 &a, const Variant19 &m, int32_t storage, hipStream_t s) {
+    if (storage == LBM_STORE_FP16) launch19p<StoreF16, CHECK, MRT>(a, m, s);
+    else if (storage == LBM_STORE_FP64) launch19p<StoreF64, CHECK, MRT>(a, m, s);
+    else launch19p<StoreF32, CHECK, MRT>(a, m, s);
 }
 
 template <bool CHECK>
-static void launch19(const Sweep19 &a, const Variant19 &m, int32_t storage, hipStream_t s) {
-    if (storage == LBM_STORE_FP16) launch19p<StoreF16, CHECK>(a, m, s);
-    else if (storage == LBM_STORE_FP64) launch19p<StoreF64, CHECK>(a, m, s);
-    else launch19p<StoreF32, CHECK>(a, m, s);
+static void launch19(const Sweep19 &a, const Variant19 &m, int32_t storage, int32_t collision,
+                     hipStream_t s) {
+    if (collision == LBM_COLLIDE_MRT) launch19c<CHECK, true>(a, m, storage, s);
+    else launch19c<CHECK, false>(a, m, storage, s);
 }
 
 static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, const FlowHeader &h,
@@ -420,6 +527,8 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
     a.Fz = (float)h.force[2];
     a.omega_d = 1.0 / h.tau;
     a.fpre_d = 1.0 - 0.5 / h.tau;
+    a.sq_d = 8.0 * (2.0 * h.tau - 1.0) / (8.0 * h.tau - 1.0);  // Eq. 7
+    a.sq = (float)a.sq_d;
     for (int k = 0; k < 3; k++) a.Fd[k] = h.force[k];
     a.scale = (float)h.scale;
     a.inv_scale = (float)(1.0 / h.scale);
@@ -434,9 +543,9 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
         a.drho_src = w.drho[cur];
         a.drho_dst = w.drho[cur ^ 1];
         if (check_last && t == steps - 1)
-            launch19<true>(a, m, h.storage, s);
+            launch19<true>(a, m, h.storage, h.collision, s);
         else
-            launch19<false>(a, m, h.storage, s);
+            launch19<false>(a, m, h.storage, h.collision, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
@@ -478,6 +587,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
     LBM_REQUIRE(p->with_rho == 0 || p->with_rho == 1, LBM_E_INVAL, "with_rho must be 0 or 1");
+    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT, LBM_E_INVAL,
+                "unknown collision %d", p->collision);
     st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -505,7 +616,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         LBM_REQUIRE(h.magic == kFlowMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
-                        h.n_fluid == nf && h.storage == p->storage,
+                        h.n_fluid == nf && h.storage == p->storage && h.collision == p->collision,
                     LBM_E_INVAL,
                     "resume: the workspace holds no state for this geometry and storage");
         t0 = h.steps_done;
@@ -519,6 +630,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     h.tau = p->tau;
     h.variant = p->variant;
     h.storage = p->storage;
+    h.collision = p->collision;
+    h.reserved = 0;
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
         // binary16: a power of two S with S max|F| in [1, 2) (1 without a force)

@@ -21,6 +21,7 @@ LBM_PSD_CHORD13, LBM_PSD_MIS = 0, 1
 LBM_WS_LABEL, LBM_WS_PORE_DIAM, LBM_WS_FLOW, LBM_WS_KNUDSEN = 0, 1, 2, 3
 LBM_WS_FLOW_FP16, LBM_WS_FLOW_FP64 = 4, 5
 LBM_STORE_FP32, LBM_STORE_FP16, LBM_STORE_FP64 = 0, 1, 2
+LBM_COLLIDE_BGK, LBM_COLLIDE_MRT = 0, 1
 _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
                  LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
@@ -56,7 +57,7 @@ class lbm_flow_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("force", C.c_double * 3), ("max_steps", C.c_int64),
                 ("fixed_steps", C.c_int64), ("check_every", C.c_int32), ("storage", C.c_int32),
                 ("tol", C.c_double), ("voxel_nm", C.c_double), ("resume", C.c_int32),
-                ("variant", C.c_int32), ("with_rho", C.c_int32), ("reserved", C.c_int32)]
+                ("variant", C.c_int32), ("with_rho", C.c_int32), ("collision", C.c_int32)]
 
 
 class lbm_flow_result(C.Structure):
@@ -301,7 +302,7 @@ class Solve:
 def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
                    check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False, u_init=None,
                    workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
-                   storage=LBM_STORE_FP32, with_rho=False):
+                   storage=LBM_STORE_FP32, with_rho=False, collision=LBM_COLLIDE_BGK):
     """D3Q19 flow solve.  With with_rho the velocity field (want_u) and u_init carry a
     fourth plane, rho - 1."""
     _vol(fluid, torch.uint8, "fluid")
@@ -313,7 +314,7 @@ def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, 
     planes = 4 if with_rho else 3
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
                         int(storage), tol, voxel_nm, int(bool(resume)), int(variant),
-                        int(bool(with_rho)), 0)
+                        int(bool(with_rho)), int(collision))
     r = lbm_flow_result()
     u = torch.empty((planes,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
         if want_u else None

@@ -96,10 +96,10 @@ def test_argument_checks_before_device(lib):
     assert L.lbm_pore_diameter(n, dummy, 5, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
     nbad = (C.c_int32 * 3)(0, 8, 8)
     assert L.lbm_pore_diameter(nbad, dummy, 0, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
-    # unknown storage and with_rho values are rejected
-    for storage, wr in ((3, 0), (-1, 0), (0, 2)):
+    # unknown storage, with_rho and collision values are rejected
+    for storage, wr, col in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 2), (0, 0, -1)):
         p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, storage, 1e-7, 1.0,
-                                0, 0, wr, 0)
+                                0, 0, wr, col)
         assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
                                 None) == lib.LBM_E_INVAL
     # variant bits other than EXPLICIT | REMAP | NTSTORE are rejected by both solves

@@ -1,0 +1,99 @@
+"""The paper's MRT collision on the GPU against the FP64 oracle (same bars as the BGK
+parity tests), and its tau-independent slit permeability."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1410_1921_amd import lbm
+from paper_1410_1921_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+MRT = lbm.LBM_COLLIDE_MRT
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def say(*a):
+    print("[gpu-mrt]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_mrt_parity_32(orc):
+    rp = W.SMALL_32["recon"]
+    pore_g, _, _ = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                       rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    pore = pore_g.cpu().numpy()
+    say("mrt 32^3")
+    r = lbm.lbm_flow_solve(pore_g, tau=0.8, force=(1e-6, 0, 0), fixed_steps=2000, check_every=100,
+                           want_u=True, collision=MRT)
+    o = orc.flow_solve(pore, tau=0.8, force=(1e-6, 0, 0), fixed_steps=2000, check_every=100,
+                       collision=orc.MRT)
+    assert r["steps"] == o["steps"] == 2000
+    assert r["k_lattice"] == pytest.approx(o["k_lattice"], rel=1e-4)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= 1e-5 * np.abs(o["u"]).max()
+    say("k", r["k_lattice"], o["k_lattice"])
+
+
+@pytest.mark.parametrize("shape,seed,force", [((13, 21, 10), 3, (1e-5, 2e-6, -3e-6)),
+                                              ((1, 12, 12), 5, (1e-5, 0.0, 0.0))])
+def test_mrt_parity_ragged(orc, shape, seed, force):
+    m = W.blob_mask(shape, 0.55, seed)
+    r = lbm.lbm_flow_solve(dev(m), tau=0.7, force=force, fixed_steps=300, check_every=50,
+                           want_u=True, collision=MRT)
+    o = orc.flow_solve(m, tau=0.7, force=force, fixed_steps=300, check_every=50, collision=orc.MRT)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= 1e-5 * np.abs(o["u"]).max()
+    assert np.allclose(r["mean_rho_u"], o["mean_rho_u"], rtol=1e-4, atol=1e-4 * np.abs(force).max())
+
+
+def test_mrt_binary64_populations(orc):
+    shape = (12, 10, 14)
+    m = W.blob_mask(shape, 0.5, 7)
+    tau, force = 0.9, (1e-5, -2e-6, 3e-6)
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=force, fixed_steps=200, check_every=100,
+                           storage=lbm.LBM_STORE_FP64, collision=MRT)
+    o = orc.flow_solve(m, tau=tau, force=force, fixed_steps=200, check_every=100, collision=orc.MRT,
+                       want_u=False)
+    vox = np.flatnonzero(m.reshape(-1))
+    f, flag = lbm.lbm_flow_sample(r.workspace, vox)
+    assert flag.all()
+    ref = o["f"].reshape(-1, 19)[vox] - W19
+    err = np.abs(f - ref).max()
+    say("binary64 populations worst", err)
+    assert err <= 1e-12
+    assert r["k_lattice"] == pytest.approx(o["k_lattice"], rel=1e-9)
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.2])
+def test_mrt_slit_is_viscosity_independent(tau):
+    h = 9
+    m = W.slit(4, h + 2, 4, h, axis=1)
+    # a fixed 40 000 steps: at tau = 0.6 the binary32 residual levels off near 1e-10
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=(1e-6, 0, 0), fixed_steps=40_000, collision=MRT)
+    k = h / (h + 2) * (h * h + 0.5) / 12
+    say("mrt slit tau", tau, r["k_lattice"], k)
+    assert r["k_lattice"] == pytest.approx(k, rel=1e-5)
+
+
+def test_mrt_variants_identical():
+    g = dev(W.blob_mask((13, 21, 10), 0.55, 3))
+    E = lbm.LBM_VARIANT_EXPLICIT
+    runs = [lbm.lbm_flow_solve(g, tau=0.7, force=(1e-5, 2e-6, -1e-6), fixed_steps=250,
+                               check_every=50, want_u=True, collision=MRT, variant=v)
+            for v in (0, E, E | lbm.LBM_VARIANT_REMAP, E | lbm.LBM_VARIANT_NTSTORE)]
+    for r in runs[1:]:
+        assert torch.equal(r.field, runs[0].field)
+
+
+def test_mrt_resume_needs_the_same_collision():
+    g = dev(W.blob_mask((12, 12, 12), 0.6, 4))
+    a = lbm.lbm_flow_solve(g, fixed_steps=20, collision=MRT)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_flow_solve(g, fixed_steps=20, workspace=a.workspace, resume=True)
+    lbm.lbm_flow_solve(g, fixed_steps=20, workspace=a.workspace, resume=True, collision=MRT)
