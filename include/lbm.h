@@ -82,11 +82,14 @@ typedef int32_t lbm_status;
  *   LBM_VARIANT_REMAP   workgroups ordered so that each XCD walks one contiguous region
  *   LBM_VARIANT_NTSTORE non-temporal (streaming) population stores
  * All variants compute identical results; they differ only in speed.  Any other bit
- * (2 included) is rejected with LBM_E_INVAL. */
+ * (2 included) is rejected with LBM_E_INVAL.  A batched solve with no explicit variant
+ * times the candidates on its first steps and keeps the fastest. */
 #define LBM_VARIANT_AUTO 0
 #define LBM_VARIANT_EXPLICIT 1
 #define LBM_VARIANT_REMAP 4
 #define LBM_VARIANT_NTSTORE 8
+#define LBM_VARIANT_NOGRAPH 16 /* batched solves only: launch each step from the host
+                                  instead of replaying a captured check interval */
 
 /* ------------------------------------------------------------------------------
  * Reconstruction (Section 2, Steps 1-3): pore spheres with random centres and
@@ -252,6 +255,44 @@ lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t steps, void *
  * count <= 65536. */
 lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_h, int64_t count,
                            double *f_h, uint8_t *fluid_h, void *stream);
+
+/* ------------------------------------------------------------------------------
+ * Batched flow solves: `count` independent lattices (Section 3.1, as lbm_flow_solve,
+ * with one parameter set for all of them), advanced together so that small lattices
+ * fill the device.  Each lattice's fluid list starts on a 256-node block of one
+ * concatenated list; every launch runs the blocks of the lattices still iterating,
+ * and the per-lattice sums of a check are reduced in a fixed order.  A lattice stops
+ * at its first check with residual < tol (its result is then frozen); the others go
+ * on.  A check interval is one captured HIP graph (re-captured when a lattice
+ * retires) unless variant has LBM_VARIANT_NOGRAPH.  Without LBM_VARIANT_EXPLICIT the
+ * first steps time the four kernel variants on this batch and keep the fastest (every
+ * variant computes the same state).  The populations, residuals and k of each lattice
+ * are those lbm_flow_solve gives it alone (the sums of a check may differ in the last
+ * bits through their order).
+ *
+ * n_h      : host int32[count][3] lattice sizes (nx, ny, nz), each <= 1024.
+ * fluid    : host array of count device pointers, each uint8[nz][ny][nx] (1 = fluid).
+ * nf_h     : host int64[count] fluid-node counts (each >= 1; checked against the masks).
+ * p        : one parameter set; storage must be LBM_STORE_FP32, resume and with_rho 0,
+ *            force[0] != 0 (k is reported along x).
+ * r_h      : host lbm_flow_result[count] out; sweep_ms, mlups and gbps are those of
+ *            the whole batch in every entry.
+ * u_out    : host array of count device pointers (or null; entries may be null), each
+ *            float[3][nz][ny][nx] out: the lattice's velocity at its last check.
+ * variant_h: host int32 out, nullable: the variant bits the solve ran.
+ * workspace: lbm_flow_batch_workspace(count, n_h, nf_h) bytes of device memory.
+ * The work runs on an internal stream ordered after `stream` and before later work
+ * on it; the call returns when the solve is finished.
+ * Errors: LBM_E_INVAL (as lbm_flow_solve; a mask whose count is not nf_h, binary16 or
+ * binary64 storage, resume, with_rho), LBM_E_NOMEM (workspace too small),
+ * LBM_E_DIVERGED, LBM_W_NOT_CONVERGED (some lattice reached max_steps), LBM_E_DEVICE.
+ * ---------------------------------------------------------------------------- */
+size_t lbm_flow_batch_workspace(int32_t count, const int32_t *n_h, const int64_t *nf_h);
+
+lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t *const *fluid,
+                                const int64_t *nf_h, const lbm_flow_params *p,
+                                lbm_flow_result *r_h, float *const *u_out, int32_t *variant_h,
+                                void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------
  * Knudsen mass-transport solve (Section 3.2, Eq. 10, on the D3Q7 lattice with rest

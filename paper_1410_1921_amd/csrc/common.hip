@@ -111,10 +111,11 @@ __device__ inline bool column_row(const Grid &g, int64_t r, int &y, int &z) {
     return y < g.ny && z < g.nz;
 }
 
-// Exclusive scan, in list order, of the segment counts held in rank[].base, in place;
-// the total goes to *total.  One block of 1024 threads, each over a run of rows.
+// Exclusive scan, in list order, of the segment counts held in rank[].base, in place,
+// offset by id_base (the id of the lattice's first node); the count goes to *total.
+// One block of 1024 threads, each over a run of rows.
 __global__ __launch_bounds__(1024) void k_seg_scan(RankWord *__restrict__ rank, Grid g,
-                                                   int32_t *__restrict__ total) {
+                                                   int32_t *__restrict__ total, uint32_t id_base) {
     __shared__ int64_t part[1024];
     const int64_t nrows = (int64_t)g.ncz * g.ncy * kCol * kCol;
     const int64_t per = (nrows + 1023) / 1024;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(1024) void k_seg_scan(RankWord *__restrict__ rank, 
         *total = (int32_t)run;
     }
     __syncthreads();
-    int64_t run = part[threadIdx.x];
+    int64_t run = part[threadIdx.x] + id_base;
     for (int64_t r = lo; r < hi; r++) {
         if (!column_row(g, r, y, z)) continue;
         const int64_t s0 = g.seg(0, y, z);
@@ -166,11 +167,11 @@ __global__ __launch_bounds__(256) void k_seg_fill(Grid g, const RankWord *__rest
 }
 
 lbm_status layout_count(const Grid &g, const uint8_t *fluid, RankWord *rank, int32_t *total_d,
-                        int64_t *nf_h, hipStream_t s) {
+                        int64_t *nf_h, hipStream_t s, uint32_t id_base) {
     const int64_t blocks = (g.nsegs() + 3) / 4;
     k_seg_count<<<(unsigned)blocks, 256, 0, s>>>(g, fluid, rank);
     LBM_CHECK_LAUNCH();
-    k_seg_scan<<<1, 1024, 0, s>>>(rank, g, total_d);
+    k_seg_scan<<<1, 1024, 0, s>>>(rank, g, total_d, id_base);
     LBM_CHECK_LAUNCH();
     int32_t total = 0;
     LBM_TRY_HIP(hipMemcpyAsync(&total, total_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));

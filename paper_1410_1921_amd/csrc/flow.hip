@@ -21,6 +21,7 @@
 // populations of 2 bytes, one drho store and 19 drho gathers (cache resident, one value
 // per node).
 #include <algorithm>
+#include <vector>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -154,6 +155,7 @@ size_t flow_ws_bytes(const Grid &g, int64_t nf, int32_t storage) {
 struct Sweep19 {
     Grid g;
     int64_t nf, stride, launched;
+    int64_t launched_live;             // batched solves: blocks of the launch with work
     const uint32_t *__restrict__ coords;
     const RankWord *__restrict__ rank;
     const void *__restrict__ src;
@@ -373,43 +375,111 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
         for (int k = 0; k < NV; k++) part[row * NV + k] = out[k];
 }
 
-// One stream-collide step, one fluid node per thread, neighbour ids gathered from the
-// global id map.  CHECK also forms the FP64 partial sums of the convergence check and
-// writes the velocity snapshot / field.
+// The update of fluid node n (n < a.nf): its coordinates, the 18 pull sources from the
+// rank map (one batch of loads), then node19.
+template <class P, bool CHECK, bool NT, bool MRT>
+__device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[kFlowSums]) {
+    LBM_D3Q19_TABLES
+    const uint32_t c = a.coords[n];
+    const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
+    const Grid &g = a.g;
+    // per-axis pieces of the rank word and bit of x-1, x, x+1 (periodic), etc.
+    int xs[3], ys[3], zs[3];
+    xs[0] = x == 0 ? g.nx - 1 : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    ys[0] = y == 0 ? g.ny - 1 : y - 1; ys[1] = y; ys[2] = y == g.ny - 1 ? 0 : y + 1;
+    zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
+    int wx[3], wy[3], wz[3], bx[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        wx[k] = xs[k] >> kSegLog;
+        wy[k] = ys[k] * g.nseg;
+        wz[k] = zs[k] * (g.ny * g.nseg);
+        bx[k] = xs[k] & (kSeg - 1);
+    }
+    // the 18 rank words are loaded as one batch, then the 19 populations as another
+    RankWord rw[19];
+#pragma unroll
+    for (int i = 1; i < 19; i++) rw[i] = a.rank[wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]]];
+    int ids[19];
+    ids[0] = 0;
+#pragma unroll
+    for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
+    node19<P, CHECK, NT, MRT>(a, n, x, y, z, ids, acc);
+}
+
+// One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
+// sums of the convergence check and writes the velocity snapshot / field.
 template <class P, bool CHECK, bool NT, bool MRT>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
-    LBM_D3Q19_TABLES
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
-    if (n < a.nf) {
-        const uint32_t c = a.coords[n];
-        const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
-        const Grid &g = a.g;
-        // per-axis pieces of the rank word and bit of x-1, x, x+1 (periodic), etc.
-        int xs[3], ys[3], zs[3];
-        xs[0] = x == 0 ? g.nx - 1 : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? 0 : x + 1;
-        ys[0] = y == 0 ? g.ny - 1 : y - 1; ys[1] = y; ys[2] = y == g.ny - 1 ? 0 : y + 1;
-        zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
-        int wx[3], wy[3], wz[3], bx[3];
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            wx[k] = xs[k] >> kSegLog;
-            wy[k] = ys[k] * g.nseg;
-            wz[k] = zs[k] * (g.ny * g.nseg);
-            bx[k] = xs[k] & (kSeg - 1);
-        }
-        // the 18 rank words are loaded as one batch, then the 19 populations as another
-        RankWord rw[19];
-#pragma unroll
-        for (int i = 1; i < 19; i++) rw[i] = a.rank[wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]]];
-        int ids[19];
-        ids[0] = 0;
-#pragma unroll
-        for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
-        node19<P, CHECK, NT, MRT>(a, n, x, y, z, ids, acc);
-    }
+    if (n < a.nf) sweep19_node<P, CHECK, NT, MRT>(a, n, acc);
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
+}
+
+// ---------------------------------------------------------------- batched solves
+// Many lattices in one launch: their fluid lists are concatenated, each starting on a
+// 256-node block, with rank maps whose bases are global node ids.  Block b of the launch
+// runs physical block blocks[b] of the lattice blk_lat says; each lattice brings its own
+// grid, rank map and collision parameters.
+struct LatDesc {
+    Grid g;
+    int64_t n_end;          // one past the lattice's last node (global id)
+    int64_t rk0;            // first rank word of the lattice
+    int64_t b0, b1;         // its physical blocks
+    float omega, fpre, Fx, Fy, Fz, sq;
+    double nvox;
+    float *u_out;           // the lattice's velocity field, written at checks (nullable)
+};
+
+template <bool CHECK, bool NT, bool MRT>
+__global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const LatDesc *__restrict__ lats,
+                                                  const int32_t *__restrict__ blocks,
+                                                  const int32_t *__restrict__ blk_lat) {
+    const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
+    double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
+    const bool live = lb < a.launched_live;
+    const int64_t pb = live ? blocks[lb] : 0;
+    if (live) {
+        const LatDesc L = lats[blk_lat[pb]];
+        Sweep19 b = a;
+        b.g = L.g;
+        b.nf = L.n_end;
+        b.rank = a.rank + L.rk0;
+        b.omega = L.omega;
+        b.fpre = L.fpre;
+        b.Fx = L.Fx;
+        b.Fy = L.Fy;
+        b.Fz = L.Fz;
+        b.sq = L.sq;
+        b.u_out = L.u_out;
+        const int64_t n = pb * 256 + threadIdx.x;
+        if (n < L.n_end) sweep19_node<StoreF32, CHECK, NT, MRT>(b, n, acc);
+    }
+    if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
+}
+
+// res[l][k] = sum of the partial rows of lattice lat_ids[l] in block order (fixed order).
+__global__ __launch_bounds__(256) void k_lat_reduce(const double *__restrict__ partials,
+                                                    const LatDesc *__restrict__ lats,
+                                                    const int32_t *__restrict__ lat_ids,
+                                                    double *__restrict__ res) {
+    __shared__ double lds[256];
+    const int lat = lat_ids[blockIdx.x];
+    const LatDesc L = lats[lat];
+    for (int k = 0; k < kFlowSums; k++) {
+        double s = 0.0;
+        for (int64_t b = L.b0 + threadIdx.x; b < L.b1; b += 256) s += partials[b * kFlowSums + k];
+        lds[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) res[lat * kFlowSums + k] = lds[0];
+        __syncthreads();
+    }
 }
 
 // f - w_i at the equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x,
@@ -815,5 +885,376 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     LBM_TRY_HIP(hipMemcpyAsync(f_h, w.samp_out, sizeof(double) * 19 * count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(fluid_h, w.samp_flag, count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+// ============================================================== batched flow solves
+namespace lbm {
+
+struct BatchWs {
+    LatDesc *lats;
+    int32_t *blocks, *blk_lat, *lat_ids, *total;
+    double *res;
+    RankWord *rank;
+    uint32_t *coords;
+    float *f[2];
+    float *usnap;
+    double *partials;
+    int64_t stride, nblk, nrank;
+    size_t bytes;
+};
+
+static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int64_t *nf_h) {
+    BatchWs w;
+    w.nblk = 0;
+    w.nrank = 0;
+    for (int l = 0; l < count; l++) {
+        const Grid g = make_grid(n_h + 3 * l);
+        w.nblk += blocks_for(nf_h[l] < 1 ? 1 : nf_h[l]);
+        w.nrank += g.nsegs();
+    }
+    w.stride = w.nblk * 256;
+    Carver c(base);
+    w.lats = c.take<LatDesc>(count);
+    w.blocks = c.take<int32_t>(w.nblk);
+    w.blk_lat = c.take<int32_t>(w.nblk);
+    w.lat_ids = c.take<int32_t>(count);
+    w.total = c.take<int32_t>(count);
+    w.res = c.take<double>((size_t)count * kFlowSums);
+    w.rank = c.take<RankWord>(w.nrank);
+    w.coords = c.take<uint32_t>(w.stride);
+    w.f[0] = c.take<float>((size_t)19 * w.stride);
+    w.f[1] = c.take<float>((size_t)19 * w.stride);
+    w.usnap = c.take<float>((size_t)3 * w.stride);
+    w.partials = c.take<double>((size_t)w.nblk * kFlowSums);
+    w.bytes = c.off;
+    return w;
+}
+
+// Owns the batch's internal stream, events and captured graphs.
+struct BatchRes {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, join = nullptr;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    void drop_graphs() {
+        for (int k = 0; k < 2; k++) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            exec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+    }
+    ~BatchRes() {
+        drop_graphs();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+template <bool CHECK>
+static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision, const BatchWs &w,
+                      hipStream_t s) {
+    const unsigned grid = (unsigned)a.launched;
+    if (collision == LBM_COLLIDE_MRT) {
+        if (m.nt) k_sweep19b<CHECK, true, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+        else k_sweep19b<CHECK, false, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+    } else {
+        if (m.nt) k_sweep19b<CHECK, true, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+        else k_sweep19b<CHECK, false, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+    }
+}
+
+// `steps` sweeps of every active lattice from buffer cur; the last one checks, then the
+// per-lattice sums of the n_act active lattices go to w.res.
+static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, int32_t collision,
+                              int64_t n_live, int n_act, int cur, int64_t steps, bool check_last,
+                              hipStream_t s) {
+    a.launched_live = n_live;
+    a.chunk = m.remap ? (n_live + kXcd - 1) / kXcd : 0;
+    a.launched = a.chunk ? xcd_launch(n_live, a.chunk) : n_live;
+    for (int64_t t = 0; t < steps; t++) {
+        a.src = w.f[cur];
+        a.dst = w.f[cur ^ 1];
+        if (check_last && t == steps - 1) launch19b<true>(a, m, collision, w, s);
+        else launch19b<false>(a, m, collision, w, s);
+        LBM_CHECK_LAUNCH();
+        cur ^= 1;
+    }
+    if (check_last) {
+        k_lat_reduce<<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
+        LBM_CHECK_LAUNCH();
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+extern "C" size_t lbm_flow_batch_workspace(int32_t count, const int32_t *n_h, const int64_t *nf_h) {
+    if (count < 1 || !n_h || !nf_h) return 0;
+    for (int l = 0; l < count; l++)
+        if (n_h[3 * l] < 1 || n_h[3 * l + 1] < 1 || n_h[3 * l + 2] < 1 || n_h[3 * l] > kMaxEdge ||
+            n_h[3 * l + 1] > kMaxEdge || n_h[3 * l + 2] > kMaxEdge || nf_h[l] < 0)
+            return 0;
+    return carve_batch(nullptr, count, n_h, nf_h).bytes;
+}
+
+extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
+                                           const uint8_t *const *fluid, const int64_t *nf_h,
+                                           const lbm_flow_params *p, lbm_flow_result *r_h,
+                                           float *const *u_out, int32_t *variant_h,
+                                           void *workspace, size_t ws_bytes, void *stream) {
+    LBM_REQUIRE(count >= 1 && n_h && fluid && nf_h && p && r_h && workspace, LBM_E_INVAL,
+                "lbm_flow_solve_batch: null argument or empty batch");
+    for (int l = 0; l < count; l++) {
+        lbm_status st = validate_n(n_h + 3 * l);
+        if (st != LBM_OK) return st;
+        LBM_REQUIRE(fluid[l] && nf_h[l] >= 1, LBM_E_INVAL, "lattice %d: no fluid mask or node", l);
+    }
+    LBM_REQUIRE(p->tau > 0.5 && std::isfinite(p->tau), LBM_E_INVAL, "tau must exceed 1/2");
+    LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
+    LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->storage == LBM_STORE_FP32 && !p->resume && !p->with_rho, LBM_E_INVAL,
+                "batched solves take binary32 storage, no resume, no density fields");
+    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT, LBM_E_INVAL,
+                "unknown collision %d", p->collision);
+    LBM_REQUIRE((p->variant & ~(kVariantBits | LBM_VARIANT_NOGRAPH)) == 0, LBM_E_INVAL,
+                "unknown variant bits 0x%x", p->variant);
+    LBM_REQUIRE(p->force[0] != 0.0, LBM_E_INVAL, "batched solves report k along x: F_x must be nonzero");
+    lbm_status st = check_device();
+    if (st != LBM_OK) return st;
+    const BatchWs w = carve_batch(workspace, count, n_h, nf_h);
+    LBM_REQUIRE(19 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                "%lld nodes exceed the 32-bit population offsets", (long long)w.stride);
+    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace of %zu bytes; %zu needed", ws_bytes,
+                w.bytes);
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+
+    BatchRes R;
+    LBM_TRY_HIP(hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
+    LBM_TRY_HIP(hipEventCreate(&R.e0));
+    LBM_TRY_HIP(hipEventCreate(&R.e1));
+    LBM_TRY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
+    LBM_TRY_HIP(hipEventRecord(R.join, caller));
+    LBM_TRY_HIP(hipStreamWaitEvent(R.s, R.join, 0));
+    hipStream_t s = R.s;
+
+    // layout, lattice table, initial state
+    std::vector<LatDesc> lats(count);
+    std::vector<int32_t> blk_lat(w.nblk);
+    int64_t n0 = 0, rk0 = 0, b0 = 0;
+    for (int l = 0; l < count; l++) {
+        const Grid g = make_grid(n_h + 3 * l);
+        int64_t nf = 0;
+        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s, (uint32_t)n0);
+        if (st != LBM_OK) return st;
+        LBM_REQUIRE(nf == nf_h[l], LBM_E_INVAL, "lattice %d has %lld fluid nodes, not %lld", l,
+                    (long long)nf, (long long)nf_h[l]);
+        st = layout_fill(g, w.rank + rk0, w.coords, s);
+        if (st != LBM_OK) return st;
+        k_flow_init<StoreF32><<<(unsigned)blocks_for(nf), 256, 0, s>>>(
+            g, nf, w.stride, w.coords + n0, nullptr, 0, w.f[0] + n0, 1.f, nullptr, w.usnap + n0);
+        LBM_CHECK_LAUNCH();
+        LatDesc &L = lats[l];
+        L.g = g;
+        L.n_end = n0 + nf;
+        L.rk0 = rk0;
+        L.b0 = b0;
+        L.b1 = b0 + blocks_for(nf);
+        L.omega = (float)(1.0 / p->tau);
+        L.fpre = (float)(1.0 - 0.5 / p->tau);
+        L.Fx = (float)p->force[0];
+        L.Fy = (float)p->force[1];
+        L.Fz = (float)p->force[2];
+        L.sq = (float)(8.0 * (2.0 * p->tau - 1.0) / (8.0 * p->tau - 1.0));
+        L.nvox = (double)g.nvox();
+        L.u_out = u_out ? u_out[l] : nullptr;
+        if (L.u_out) LBM_TRY_HIP(hipMemsetAsync(L.u_out, 0, sizeof(float) * 3 * g.nvox(), s));
+        for (int64_t b = L.b0; b < L.b1; b++) blk_lat[b] = l;
+        n0 = L.b1 * 256;
+        rk0 += g.nsegs();
+        b0 = L.b1;
+    }
+    LBM_TRY_HIP(hipMemcpyAsync(w.lats, lats.data(), sizeof(LatDesc) * count, hipMemcpyHostToDevice, s));
+    LBM_TRY_HIP(hipMemcpyAsync(w.blk_lat, blk_lat.data(), sizeof(int32_t) * w.nblk, hipMemcpyHostToDevice, s));
+
+    // the active set: lattices not yet converged, and their blocks
+    std::vector<int32_t> act(count), act_blocks;
+    for (int l = 0; l < count; l++) act[l] = l;
+    double live_nodes = 0.0;  // fluid nodes of the active lattices
+    auto upload_active = [&]() -> lbm_status {
+        act_blocks.clear();
+        live_nodes = 0.0;
+        for (int l : act) {
+            for (int64_t b = lats[l].b0; b < lats[l].b1; b++) act_blocks.push_back((int32_t)b);
+            live_nodes += (double)nf_h[l];
+        }
+        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, act.data(), sizeof(int32_t) * act.size(),
+                                   hipMemcpyHostToDevice, s));
+        LBM_TRY_HIP(hipMemcpyAsync(w.blocks, act_blocks.data(), sizeof(int32_t) * act_blocks.size(),
+                                   hipMemcpyHostToDevice, s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));  // the host vectors are reused
+        return LBM_OK;
+    };
+    st = upload_active();
+    if (st != LBM_OK) return st;
+
+    Sweep19 a{};
+    a.stride = w.stride;
+    a.coords = w.coords;
+    a.rank = w.rank;
+    a.omega_d = 1.0 / p->tau;
+    a.fpre_d = 1.0 - 0.5 / p->tau;
+    a.scale = 1.f;
+    a.inv_scale = 1.f;
+    a.usnap = w.usnap;
+    a.u_out = nullptr;
+    a.partials = w.partials;
+    a.update_snap = 1;
+    a.with_rho = 0;
+
+    const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
+    const int nc = p->check_every;
+    const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
+    Variant19 mode = pick_variant(p->variant & kVariantBits, w.stride, LBM_STORE_FP32);
+    int cur = 0;
+    int64_t t = 0;
+    double sweep_ms = 0.0, updates = 0.0;
+
+    // autotuner: without an explicit variant, the first steps time each candidate on
+    // this batch (every variant computes the same state, so the steps count)
+    int32_t chosen = p->variant & kVariantBits;
+    if (!(p->variant & LBM_VARIANT_EXPLICIT)) {
+        const int32_t cand[4] = {LBM_VARIANT_EXPLICIT, LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP,
+                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_NTSTORE,
+                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE};
+        const int64_t per = 8;
+        float best = 0.f;
+        for (int k = 0; k < 4 && t + per + 1 < std::min<int64_t>(limit, nc); k++) {
+            const Variant19 m = pick_variant(cand[k], w.stride, LBM_STORE_FP32);
+            st = batch_steps(w, a, m, p->collision, (int64_t)act_blocks.size(), (int)act.size(), cur,
+                             1, false, s);  // warm the variant's code
+            if (st != LBM_OK) return st;
+            cur ^= 1;
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            st = batch_steps(w, a, m, p->collision, (int64_t)act_blocks.size(), (int)act.size(), cur,
+                             per, false, s);
+            if (st != LBM_OK) return st;
+            LBM_TRY_HIP(hipEventRecord(R.e1, s));
+            LBM_TRY_HIP(hipEventSynchronize(R.e1));
+            float ms = 0.f;
+            LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
+            cur ^= (int)(per & 1);
+            t += per + 1;
+            sweep_ms += ms;
+            updates += (double)per * live_nodes;
+            if (k == 0 || ms < best) {
+                best = ms;
+                mode = m;
+                chosen = cand[k];
+            }
+        }
+    }
+    if (variant_h) *variant_h = chosen | (p->variant & LBM_VARIANT_NOGRAPH);
+
+    std::vector<double> res((size_t)count * kFlowSums, 0.0);
+    std::vector<int64_t> steps_l(count, 0);
+    std::vector<double> resid_l(count, INFINITY);
+    std::vector<int> conv_l(count, 0), cur_l(count, 0);
+    std::vector<double> sums_l((size_t)count * kFlowSums, 0.0);
+    bool diverged = false;
+    while (t < limit && !act.empty()) {
+        const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
+        const int64_t live = (int64_t)act_blocks.size();
+        LBM_TRY_HIP(hipEventRecord(R.e0, s));
+        if (use_graph && chunk == nc) {
+            if (!R.exec[cur]) {
+                LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                st = batch_steps(w, a, mode, p->collision, live, (int)act.size(), cur, chunk, true, s);
+                hipGraph_t graph = nullptr;
+                hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (st != LBM_OK) return st;
+                LBM_TRY_HIP(ec);
+                R.graph[cur] = graph;
+                LBM_TRY_HIP(hipGraphInstantiate(&R.exec[cur], graph, nullptr, nullptr, 0));
+            }
+            LBM_TRY_HIP(hipGraphLaunch(R.exec[cur], s));
+        } else {
+            st = batch_steps(w, a, mode, p->collision, live, (int)act.size(), cur, chunk, true, s);
+            if (st != LBM_OK) return st;
+        }
+        LBM_TRY_HIP(hipEventRecord(R.e1, s));
+        LBM_TRY_HIP(hipMemcpyAsync(res.data(), w.res, sizeof(double) * count * kFlowSums,
+                                   hipMemcpyDeviceToHost, s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
+        sweep_ms += ms;
+        updates += (double)chunk * live_nodes;
+        cur ^= (int)(chunk & 1);
+        t += chunk;
+        std::vector<int32_t> keep;
+        for (int l : act) {
+            const double *sm = res.data() + (size_t)l * kFlowSums;
+            std::copy(sm, sm + kFlowSums, sums_l.begin() + (size_t)l * kFlowSums);
+            steps_l[l] = t;
+            cur_l[l] = cur;
+            if (!std::isfinite(sm[0]) || !std::isfinite(sm[1]) || !std::isfinite(sm[2])) {
+                diverged = true;
+                continue;
+            }
+            bool done = false;
+            if (t % nc == 0) {
+                resid_l[l] = std::sqrt(sm[0]) / ((double)nc * std::sqrt(sm[1]));
+                if (p->fixed_steps <= 0 && resid_l[l] < p->tol) {
+                    conv_l[l] = 1;
+                    done = true;
+                }
+            }
+            if (!done) keep.push_back(l);
+        }
+        if (diverged) break;
+        if (keep.size() != act.size()) {
+            act = keep;
+            R.drop_graphs();
+            if (!act.empty()) {
+                st = upload_active();
+                if (st != LBM_OK) return st;
+            }
+        }
+    }
+    LBM_TRY_HIP(hipEventRecord(R.join, s));
+    LBM_TRY_HIP(hipStreamWaitEvent(caller, R.join, 0));
+
+    const double nu = (p->tau - 0.5) / 3.0;
+    for (int l = 0; l < count; l++) {
+        lbm_flow_result &r = r_h[l];
+        std::memset(&r, 0, sizeof(r));
+        const double *sm = sums_l.data() + (size_t)l * kFlowSums;
+        r.steps = steps_l[l];
+        r.n_fluid = nf_h[l];
+        r.converged = conv_l[l];
+        r.residual = resid_l[l];
+        for (int k = 0; k < 3; k++) r.mean_rho_u[k] = sm[2 + k] / lats[l].nvox;
+        r.mass_dev = sm[5];
+        r.k_lattice = nu * r.mean_rho_u[0] / p->force[0];
+        const double dx = p->voxel_nm * 1e-9;
+        r.k_m2 = r.k_lattice * dx * dx;
+        r.k_mD = r.k_m2 / 9.869233e-16;
+        r.sweep_ms = sweep_ms;  // of the whole batch
+        r.mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
+        r.gbps = sweep_ms > 0 ? updates * 152.0 / (sweep_ms * 1e-3) / 1e9 : 0.0;
+    }
+    if (diverged) {
+        set_error("batched flow solve diverged (NaN/Inf) by step %lld", (long long)t);
+        return LBM_E_DIVERGED;
+    }
+    for (int l = 0; l < count; l++)
+        if (!conv_l[l] && p->fixed_steps <= 0) {
+            set_error("lattice %d not converged after %lld steps", l, (long long)steps_l[l]);
+            return LBM_W_NOT_CONVERGED;
+        }
     return LBM_OK;
 }

@@ -92,7 +92,7 @@ __host__ __device__ inline uint32_t pack_xyz(int x, int y, int z) {
     return (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
 }
 
-// Variant bits a solve accepts.
+// Variant bits a solve accepts (a batched solve also LBM_VARIANT_NOGRAPH).
 constexpr int32_t kVariantBits = LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE;
 
 // ---------------------------------------------------------------- XCD-aware mapping
@@ -163,11 +163,12 @@ __device__ inline int node_at(const RankWord *__restrict__ rank, const Grid &g, 
     return rank_lookup(rank[g.seg(x, y, z)], x & (kSeg - 1));
 }
 
-// layout_count: the rank map's occupancy bits and bases (g.nsegs() words); the number
-// of fluid nodes goes to *nf_h (host sync); total_d is one int32 of device scratch.
+// layout_count: the rank map's occupancy bits and bases (g.nsegs() words; ids start at
+// id_base); the number of fluid nodes goes to *nf_h (host sync); total_d is one int32 of
+// device scratch.
 // layout_fill: coords[id] = packed x | y<<10 | z<<20 of every fluid node.
 lbm_status layout_count(const Grid &g, const uint8_t *fluid, RankWord *rank, int32_t *total_d,
-                        int64_t *nf_h, hipStream_t s);
+                        int64_t *nf_h, hipStream_t s, uint32_t id_base = 0);
 lbm_status layout_fill(const Grid &g, const RankWord *rank, uint32_t *coords, hipStream_t s);
 
 // Counting kernel usable by several entry points.

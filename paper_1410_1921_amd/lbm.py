@@ -25,6 +25,7 @@ LBM_COLLIDE_BGK, LBM_COLLIDE_MRT = 0, 1
 _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
                  LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
+LBM_VARIANT_NOGRAPH = 16
 
 _STATUS = {0: "OK", 1: "W_NOT_CONVERGED", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE",
            -4: "E_RECON_STALL", -5: "E_DIVERGED"}
@@ -111,6 +112,10 @@ _SIGS = {
                         _P, C.c_size_t, _P], C.c_int32),
     "lbm_flow_step": ([_P, C.c_size_t, C.c_int64, _P], C.c_int32),
     "lbm_flow_sample": ([_P, C.c_size_t, _P, C.c_int64, _P, _P, _P], C.c_int32),
+    "lbm_flow_batch_workspace": ([C.c_int32, _P, _P], C.c_size_t),
+    "lbm_flow_solve_batch": ([C.c_int32, _P, _P, _P, C.POINTER(lbm_flow_params),
+                              C.POINTER(lbm_flow_result), _P, C.POINTER(C.c_int32), _P,
+                              C.c_size_t, _P], C.c_int32),
     "lbm_knudsen_solve": ([_P, _P, _P, C.POINTER(lbm_knudsen_params),
                            C.POINTER(lbm_knudsen_result), _P, _P, _P, _P, C.c_size_t, _P],
                           C.c_int32),
@@ -342,6 +347,46 @@ def lbm_flow_sample(workspace, vox):
                                   len(vox), f.ctypes.data_as(C.c_void_p),
                                   flag.ctypes.data_as(C.c_void_p), _stream()), "lbm_flow_sample")
     return f, flag
+
+
+def lbm_flow_batch_workspace(shapes, n_fluids):
+    """Workspace bytes of lbm_flow_solve_batch for lattices of these (nz, ny, nx) shapes
+    and fluid counts (0: invalid sizes)."""
+    n = np.array([[s[2], s[1], s[0]] for s in shapes], np.int32)
+    nf = np.ascontiguousarray(n_fluids, np.int64)
+    return load().lbm_flow_batch_workspace(len(n), n.ctypes.data_as(C.c_void_p),
+                                           nf.ctypes.data_as(C.c_void_p))
+
+
+def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000,
+                         fixed_steps=0, check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False,
+                         n_fluids=None, variant=LBM_VARIANT_AUTO, collision=LBM_COLLIDE_BGK,
+                         workspace=None):
+    """D3Q19 flow solves of several lattices in one batch (binary32 storage).  Returns
+    (status, list of result dicts, list of velocity fields or None, the variant run)."""
+    for m in fluids:
+        _vol(m, torch.uint8, "fluid")
+    if n_fluids is None:
+        n_fluids = [lbm_count(m) for m in fluids]
+    count = len(fluids)
+    n = np.array([[m.shape[2], m.shape[1], m.shape[0]] for m in fluids], np.int32)
+    nf = np.ascontiguousarray(n_fluids, np.int64)
+    if workspace is None:
+        workspace = Workspace(lbm_flow_batch_workspace([m.shape for m in fluids], nf),
+                              fluids[0].device)
+    p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
+                        LBM_STORE_FP32, tol, voxel_nm, 0, int(variant), 0, int(collision))
+    res = (lbm_flow_result * count)()
+    us = [torch.empty((3,) + tuple(m.shape), dtype=torch.float32, device=m.device)
+          for m in fluids] if want_u else None
+    masks = (C.c_void_p * count)(*[m.data_ptr() for m in fluids])
+    u_ptrs = (C.c_void_p * count)(*[u.data_ptr() for u in us]) if want_u else None
+    ran = C.c_int32(0)
+    st = _check(load().lbm_flow_solve_batch(count, n.ctypes.data_as(C.c_void_p), masks,
+                                            nf.ctypes.data_as(C.c_void_p), C.byref(p), res,
+                                            u_ptrs, C.byref(ran), workspace.ptr,
+                                            workspace.nbytes, _stream()), "lbm_flow_solve_batch")
+    return st, [_as_dict(r) for r in res], us, ran.value
 
 
 # ------------------------------------------------------------------ Knudsen

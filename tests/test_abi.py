@@ -27,7 +27,7 @@ def _declared(header=HEADER):
 def test_every_declared_symbol_is_exported(lib):
     L = lib.load()
     names = _declared() + _declared(os.path.join(ROOT, "include", "lbm_nn.h"))
-    assert len(names) == 16 + 15
+    assert len(names) == 18 + 15
     for name in names:
         assert hasattr(L, name), name
     # and the binding wraps each of them
@@ -135,3 +135,37 @@ def test_props_relations(lib, orc):
     assert out["bruggeman_alpha"] == pytest.approx(math.log(0.1) / math.log(0.4), rel=1e-14)
     partial = lib.lbm_props(g, None, None)
     assert math.isnan(partial["k_m2"]) and partial["porosity"] == 0.4
+
+
+def test_batch_sizes_and_checks(lib):
+    L = lib.load()
+    one = lib.lbm_flow_batch_workspace([(32, 32, 32)], [1000])
+    two = lib.lbm_flow_batch_workspace([(32, 32, 32), (16, 24, 40)], [1000, 3000])
+    # at least the two binary32 population buffers of every block-aligned list
+    assert one >= 2 * 19 * 4 * 1024
+    assert two - one >= 2 * 19 * 4 * 3072
+    assert lib.lbm_flow_batch_workspace([(8, 8, 2000)], [10]) == 0
+    assert lib.lbm_flow_batch_workspace([(8, 8, 8)], [-1]) == 0
+    n = (C.c_int32 * 6)(8, 8, 8, 8, 8, 8)
+    nf = (C.c_int64 * 2)(100, 100)
+    masks = (C.c_void_p * 2)(1, 1)
+    res = (lib.lbm_flow_result * 2)()
+    dummy = C.c_void_p(1)
+
+    def call(count=2, **kw):
+        a = dict(tau=0.8, force=(1e-6, 0, 0), max_steps=10, fixed_steps=0, check_every=10,
+                 storage=0, tol=1e-7, voxel_nm=1.0, resume=0, variant=0, with_rho=0, collision=0)
+        a.update(kw)
+        p = lib.lbm_flow_params(a["tau"], (C.c_double * 3)(*a["force"]), a["max_steps"],
+                                a["fixed_steps"], a["check_every"], a["storage"], a["tol"],
+                                a["voxel_nm"], a["resume"], a["variant"], a["with_rho"],
+                                a["collision"])
+        return L.lbm_flow_solve_batch(count, n, masks, nf, C.byref(p), res, None, None, dummy,
+                                      1 << 30, None)
+
+    # binary16 / binary64 storage, resume, density planes, F_x = 0, tau <= 1/2, unknown
+    # variant bits and an empty batch are rejected before any device work
+    for kw in (dict(storage=1), dict(storage=2), dict(resume=1), dict(with_rho=1),
+               dict(force=(0, 1e-6, 0)), dict(tau=0.5), dict(variant=2), dict(collision=2),
+               dict(count=0)):
+        assert call(**kw) == lib.LBM_E_INVAL, kw
