@@ -357,6 +357,40 @@ lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const int64_t *v
                               void *stream);
 
 /* ------------------------------------------------------------------------------
+ * Batched Knudsen solves: `count` independent lattices (Section 3.2, as
+ * lbm_knudsen_solve, one parameter set for all), advanced together as the batched flow
+ * solves are (block-aligned concatenated lists, per-lattice retirement at checks,
+ * captured check intervals unless LBM_VARIANT_NOGRAPH, variant autotuning without
+ * LBM_VARIANT_EXPLICIT).  Each lattice keeps its own reference frames; the
+ * populations, steps and D_eff of a lattice are those lbm_knudsen_solve gives it alone
+ * (check sums up to their summation order).
+ *
+ * n_h       : host int32[count][3] lattice sizes, each <= 1024.
+ * fluid     : host array of count device pointers, uint8[nz][ny][nx] each.
+ * pore_diam : host array of count device pointers, double[nz][ny][nx] each (voxels).
+ * nf_h      : host int64[count] fluid-node counts (each >= 1; checked).
+ * p         : one parameter set; resume must be 0.
+ * r_h       : host lbm_knudsen_result[count] out (sweep_ms, mlups, gbps of the batch).
+ * c_field   : host array of count device pointers or null (entries may be null),
+ *             float[nz][ny][nx] out: C at the lattice's last check.
+ * c_init    : host array of count device pointers or null (entries may be null),
+ *             float[nz][ny][nx] in: initial C (warm start).
+ * variant_h : host int32 out, nullable: the variant bits the solve ran.
+ * workspace : lbm_knudsen_batch_workspace(count, n_h, nf_h) bytes.
+ * The work runs on an internal stream ordered after `stream` and before later work on
+ * it; the call returns when the solve is finished.
+ * Errors: as lbm_knudsen_solve; LBM_E_INVAL also for resume or a count mismatch.
+ * ---------------------------------------------------------------------------- */
+size_t lbm_knudsen_batch_workspace(int32_t count, const int32_t *n_h, const int64_t *nf_h);
+
+lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h, const uint8_t *const *fluid,
+                                   const double *const *pore_diam, const int64_t *nf_h,
+                                   const lbm_knudsen_params *p, lbm_knudsen_result *r_h,
+                                   float *const *c_field, const float *const *c_init,
+                                   int32_t *variant_h, void *workspace, size_t ws_bytes,
+                                   void *stream);
+
+/* ------------------------------------------------------------------------------
  * Derived properties (host only, pure).  Eq. 15 unit conversions; D_K of Eq. 11 at
  * the mean pore diameter; Kozeny-Carman k = d^2/180 eps^3/(1-eps)^2 (Eq. 17) with
  * d = d_mean_nm; Bruggeman exponent alpha = ln(D_eff/D_K,ref)/ln(eps) (Section

@@ -460,28 +460,6 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const LatDesc *__re
     if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
 }
 
-// res[l][k] = sum of the partial rows of lattice lat_ids[l] in block order (fixed order).
-__global__ __launch_bounds__(256) void k_lat_reduce(const double *__restrict__ partials,
-                                                    const LatDesc *__restrict__ lats,
-                                                    const int32_t *__restrict__ lat_ids,
-                                                    double *__restrict__ res) {
-    __shared__ double lds[256];
-    const int lat = lat_ids[blockIdx.x];
-    const LatDesc L = lats[lat];
-    for (int k = 0; k < kFlowSums; k++) {
-        double s = 0.0;
-        for (int64_t b = L.b0 + threadIdx.x; b < L.b1; b += 256) s += partials[b * kFlowSums + k];
-        lds[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) res[lat * kFlowSums + k] = lds[0];
-        __syncthreads();
-    }
-}
-
 // f - w_i at the equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x,
 // u_y, u_z and, with with_rho, rho - 1; rest and rho = 1 without it); the snapshot
 // starts at that u.
@@ -931,29 +909,6 @@ static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int6
     return w;
 }
 
-// Owns the batch's internal stream, events and captured graphs.
-struct BatchRes {
-    hipStream_t s = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr, join = nullptr;
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    void drop_graphs() {
-        for (int k = 0; k < 2; k++) {
-            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
-            if (graph[k]) (void)hipGraphDestroy(graph[k]);
-            exec[k] = nullptr;
-            graph[k] = nullptr;
-        }
-    }
-    ~BatchRes() {
-        drop_graphs();
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        if (join) (void)hipEventDestroy(join);
-        if (s) (void)hipStreamDestroy(s);
-    }
-};
-
 template <bool CHECK>
 static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision, const BatchWs &w,
                       hipStream_t s) {
@@ -984,7 +939,7 @@ static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, i
         cur ^= 1;
     }
     if (check_last) {
-        k_lat_reduce<<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
+        k_lat_reduce<kFlowSums><<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
         LBM_CHECK_LAUNCH();
     }
     return LBM_OK;

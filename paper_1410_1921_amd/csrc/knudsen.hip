@@ -110,6 +110,7 @@ size_t knudsen_ws_bytes_n(const int32_t n[3], int64_t nf) {
 struct Sweep7 {
     Grid g;
     int64_t nf, stride, launched;
+    int64_t launched_live;             // batched solves: blocks of the launch with work
     const uint32_t *__restrict__ coords;
     const RankWord *__restrict__ rank;
     const float *__restrict__ omega;
@@ -189,37 +190,78 @@ __device__ inline void write_partials7(double (&acc)[NV], int64_t row, bool vali
         for (int k = 0; k < NV; k++) part[row * NV + k] = out[k];
 }
 
-// One step, one fluid node per thread, neighbour ids found through the rank map.
+// The update of fluid node n: its 6 pull sources through the rank map.
+template <bool CHECK, bool NT>
+__device__ inline void sweep7_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
+    const uint32_t c = a.coords[n];
+    const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
+    const Grid &g = a.g;
+    const int xm = x - 1, xp = x + 1;  // ghost planes beyond the x faces
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    // neighbour voxels in direction order 1..6 (source x - e_i); beyond an x face the
+    // node itself stands in, its id is replaced by -2 (ghost plane)
+    const int x1 = xm >= 0 ? xm : x, x2 = xp < g.nx ? xp : x;
+    const int nxs[7] = {x, x1, x2, x, x, x, x};
+    const int nys[7] = {y, y, y, ym, yp, y, y};
+    const int nzs[7] = {z, z, z, z, z, zm, zp};
+    RankWord rw[7];
+#pragma unroll
+    for (int i = 1; i < 7; i++) rw[i] = a.rank[g.seg(nxs[i], nys[i], nzs[i])];
+    int ids[7];
+    ids[0] = 0;
+#pragma unroll
+    for (int i = 1; i < 7; i++) ids[i] = rank_lookup(rw[i], nxs[i] & (kSeg - 1));
+    if (xm < 0) ids[1] = -2;
+    if (xp >= g.nx) ids[2] = -2;
+    node7<CHECK, NT>(a, n, x, y, z, ids, acc);
+}
+
+// One step, one fluid node per thread.
 template <bool CHECK, bool NT>
 __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
-    if (n < a.nf) {
-        const uint32_t c = a.coords[n];
-        const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
-        const Grid &g = a.g;
-        const int xm = x - 1, xp = x + 1;  // ghost planes beyond the x faces
-        const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
-        const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-        // neighbour voxels in direction order 1..6 (source x - e_i); beyond an x face the
-        // node itself stands in, its id is replaced by -2 (ghost plane)
-        const int x1 = xm >= 0 ? xm : x, x2 = xp < g.nx ? xp : x;
-        const int nxs[7] = {x, x1, x2, x, x, x, x};
-        const int nys[7] = {y, y, y, ym, yp, y, y};
-        const int nzs[7] = {z, z, z, z, z, zm, zp};
-        RankWord rw[7];
-#pragma unroll
-        for (int i = 1; i < 7; i++) rw[i] = a.rank[g.seg(nxs[i], nys[i], nzs[i])];
-        int ids[7];
-        ids[0] = 0;
-#pragma unroll
-        for (int i = 1; i < 7; i++) ids[i] = rank_lookup(rw[i], nxs[i] & (kSeg - 1));
-        if (xm < 0) ids[1] = -2;
-        if (xp >= g.nx) ids[2] = -2;
-        node7<CHECK, NT>(a, n, x, y, z, ids, acc);
-    }
+    if (n < a.nf) sweep7_node<CHECK, NT>(a, n, acc);
     if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
+}
+
+// ---------------------------------------------------------------- batched solves
+// As in the batched flow solve: concatenated block-aligned fluid lists, rank maps with
+// global node ids, block b of a launch runs physical block blocks[b].  Each lattice has
+// its own per-x frame tables (nx + 2 entries from sh0) and nx plane-mean rows (from pl0).
+struct KnLat {
+    Grid g;
+    int64_t n_end;  // one past the lattice's last node (global id)
+    int64_t rk0;    // first rank word
+    int64_t b0, b1; // physical blocks
+    int64_t sh0;    // first entry of the per-x tables
+    int64_t pl0;    // first plane row of the plane-mean partials
+    float *c_out;   // concentration field written at checks (nullable)
+};
+
+template <bool CHECK, bool NT>
+__global__ __launch_bounds__(256) void k_sweep7b(Sweep7 a, const KnLat *__restrict__ lats,
+                                                 const int32_t *__restrict__ blocks,
+                                                 const int32_t *__restrict__ blk_lat) {
+    const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
+    double acc[kKnSums] = {0, 0, 0, 0, 0};
+    const bool live = lb < a.launched_live;
+    const int64_t pb = live ? blocks[lb] : 0;
+    if (live) {
+        const KnLat L = lats[blk_lat[pb]];
+        Sweep7 b = a;
+        b.g = L.g;
+        b.nf = L.n_end;
+        b.rank = a.rank + L.rk0;
+        b.shift = a.shift + L.sh0;
+        b.ref_out = a.ref_out + L.sh0;
+        b.c_out = L.c_out;
+        const int64_t n = pb * 256 + threadIdx.x;
+        if (n < L.n_end) sweep7_node<CHECK, NT>(b, n, acc);
+    }
+    if (CHECK) write_partials7<kKnSums>(acc, pb, live, a.partials);
 }
 
 // 1/tau_g per node from the pore diameter (Eq. 12); counts nodes with tau_g <= 1/2 and
@@ -273,11 +315,11 @@ __global__ __launch_bounds__(1024) void k_frame0(int nx, double c_in, double c_o
     }
 }
 
-// Plane sums of the checked concentration, kPlaneParts workgroups per plane.
-__global__ __launch_bounds__(256) void k_plane_mean(Grid g, const RankWord *__restrict__ rank,
-                                                    const float *__restrict__ csnap,
-                                                    double *__restrict__ part) {
-    const int p = blockIdx.x, x = blockIdx.y;
+// Plane sums of the checked concentration, kPlaneParts workgroups per plane: workgroup
+// p of plane x writes its (sum, count) to row[0], row[1].
+__device__ inline void plane_mean_part(const Grid &g, const RankWord *__restrict__ rank,
+                                       const float *__restrict__ csnap, int x, int p,
+                                       double *__restrict__ row) {
     double acc[2] = {0.0, 0.0};
     const int64_t m = (int64_t)g.ny * g.nz;
     for (int64_t k = (int64_t)p * 256 + threadIdx.x; k < m; k += kPlaneParts * 256) {
@@ -291,19 +333,38 @@ __global__ __launch_bounds__(256) void k_plane_mean(Grid g, const RankWord *__re
     double out[2];
     block_sum<2>(acc, lds, out);
     if (threadIdx.x == 0) {
-        part[2 * (x * kPlaneParts + p)] = out[0];
-        part[2 * (x * kPlaneParts + p) + 1] = out[1];
+        row[0] = out[0];
+        row[1] = out[1];
     }
+}
+
+__global__ __launch_bounds__(256) void k_plane_mean(Grid g, const RankWord *__restrict__ rank,
+                                                    const float *__restrict__ csnap,
+                                                    double *__restrict__ part) {
+    const int p = blockIdx.x, x = blockIdx.y;
+    plane_mean_part(g, rank, csnap, x, p, part + 2 * (x * kPlaneParts + p));
+}
+
+// Batched: planes[q] = (lattice, x) of the q-th plane of the active lattices, workgroup
+// q * kPlaneParts + p.
+__global__ __launch_bounds__(256) void k_plane_mean_b(const int32_t *__restrict__ planes,
+                                                      const KnLat *__restrict__ lats,
+                                                      const RankWord *__restrict__ rank,
+                                                      const float *__restrict__ csnap,
+                                                      double *__restrict__ part) {
+    const int64_t q = blockIdx.x / kPlaneParts;
+    const int p = (int)(blockIdx.x % kPlaneParts);
+    const int x = planes[2 * q + 1];
+    const KnLat L = lats[planes[2 * q]];
+    plane_mean_part(L.g, rank + L.rk0, csnap, x, p, part + 2 * ((L.pl0 + x) * kPlaneParts + p));
 }
 
 // The next frame: plane means (planes without fluid keep the current value), its steady
 // shifts, and the shifts from the current frame into it.  Sums in fixed order.
-__global__ __launch_bounds__(1024) void k_frame_next(int nx, double c_in, double c_out,
-                                                     const double *__restrict__ part,
-                                                     const double *__restrict__ ref_cur,
-                                                     double *__restrict__ ref_next,
-                                                     Shift *__restrict__ steady_next,
-                                                     Shift *__restrict__ trans) {
+__device__ inline void frame_next(int nx, double c_in, double c_out,
+                                  const double *__restrict__ part,
+                                  const double *__restrict__ ref_cur, double *__restrict__ ref_next,
+                                  Shift *__restrict__ steady_next, Shift *__restrict__ trans) {
     for (int k = threadIdx.x; k < nx + 2; k += 1024) {
         double v;
         if (k == 0) {
@@ -334,6 +395,29 @@ __global__ __launch_bounds__(1024) void k_frame_next(int nx, double c_in, double
         steady_next[k] = s;
         trans[k] = t;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_frame_next(int nx, double c_in, double c_out,
+                                                     const double *__restrict__ part,
+                                                     const double *__restrict__ ref_cur,
+                                                     double *__restrict__ ref_next,
+                                                     Shift *__restrict__ steady_next,
+                                                     Shift *__restrict__ trans) {
+    frame_next(nx, c_in, c_out, part, ref_cur, ref_next, steady_next, trans);
+}
+
+// Batched: workgroup l forms the next frame of lattice lat_ids[l].
+__global__ __launch_bounds__(1024) void k_frame_next_b(const int32_t *__restrict__ lat_ids,
+                                                       const KnLat *__restrict__ lats,
+                                                       double c_in, double c_out,
+                                                       const double *__restrict__ part,
+                                                       const double *__restrict__ ref_cur,
+                                                       double *__restrict__ ref_next,
+                                                       Shift *__restrict__ steady_next,
+                                                       Shift *__restrict__ trans) {
+    const KnLat L = lats[lat_ids[blockIdx.x]];
+    frame_next(L.g.nx, c_in, c_out, part + 2 * L.pl0 * kPlaneParts, ref_cur + L.sh0,
+               ref_next + L.sh0, steady_next + L.sh0, trans + L.sh0);
 }
 
 // Net +x flux through the link plane x = px - 1/2 (px = 0..nx), one block per plane,
@@ -454,6 +538,43 @@ static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, KnHeader &
         cur ^= 1;
     }
     return LBM_OK;
+}
+
+// The reported quantities of a Knudsen solve from its last check sums (Phi_out, Phi_in,
+// sum C), the sum of tau_g - 1/2 and the link-plane fluxes (Eqs. 11, 14-16).
+static void kn_result(lbm_knudsen_result *r, const lbm_knudsen_params *p, const Grid &g,
+                      int64_t nf, int64_t t, bool converged, double resid, const double *sums,
+                      double sum_tau, const double *planes, double sweep_ms, double updates) {
+    std::memset(r, 0, sizeof(*r));
+    r->steps = t;
+    r->n_fluid = nf;
+    r->converged = converged;
+    r->residual = resid;
+    r->phi_out = sums[2];
+    r->phi_in = sums[3];
+    r->sum_c = sums[4];
+    const double dc = p->c_in - p->c_out;
+    r->Deff_lattice = sums[2] / ((double)g.ny * g.nz) * (double)(g.nx + 1) / dc;
+    const double cs2 = 0.25;
+    const double d_lref = cs2 * (p->tau_ref - 0.5);
+    r->Deff_over_DKref = r->Deff_lattice / d_lref;
+    const double R = 8.314462618, PI = 3.141592653589793;
+    r->DK_ref_m2s = p->d_ref_nm * 1e-9 / 3.0 * std::sqrt(8.0 * R * p->T_K / (PI * p->M_kg_mol));
+    r->Deff_m2s = r->Deff_over_DKref * r->DK_ref_m2s;
+    const double eps = (double)nf / (double)g.nvox();
+    r->tortuosity = eps * d_lref / r->Deff_lattice;
+    r->tortuosity_local = eps * (cs2 * sum_tau / (double)nf) / r->Deff_lattice;
+    double mn = planes[0], mx = planes[0], mean = 0.0;
+    for (int k = 0; k <= g.nx; k++) {
+        mn = planes[k] < mn ? planes[k] : mn;
+        mx = planes[k] > mx ? planes[k] : mx;
+        mean += planes[k];
+    }
+    mean /= (double)(g.nx + 1);
+    r->flux_spread = mean != 0.0 ? (mx - mn) / std::fabs(mean) : INFINITY;
+    r->sweep_ms = sweep_ms;
+    r->mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
+    r->gbps = sweep_ms > 0 ? updates * 60.0 / (sweep_ms * 1e-3) / 1e9 : 0.0;
 }
 
 }  // namespace lbm
@@ -602,37 +723,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_TRY_HIP(hipStreamSynchronize(s));
     if (plane_flux_h) std::memcpy(plane_flux_h, planes, sizeof(double) * (g.nx + 1));
 
-    std::memset(r, 0, sizeof(*r));
-    r->steps = t;
-    r->n_fluid = nf;
-    r->converged = converged;
-    r->residual = resid;
-    r->phi_out = sums[2];
-    r->phi_in = sums[3];
-    r->sum_c = sums[4];
-    const double dc = p->c_in - p->c_out;
-    r->Deff_lattice = sums[2] / ((double)g.ny * g.nz) * (double)(g.nx + 1) / dc;
-    const double cs2 = 0.25;
-    const double d_lref = cs2 * (p->tau_ref - 0.5);
-    r->Deff_over_DKref = r->Deff_lattice / d_lref;
-    const double R = 8.314462618, PI = 3.141592653589793;
-    r->DK_ref_m2s = p->d_ref_nm * 1e-9 / 3.0 * std::sqrt(8.0 * R * p->T_K / (PI * p->M_kg_mol));
-    r->Deff_m2s = r->Deff_over_DKref * r->DK_ref_m2s;
-    const double eps = (double)nf / (double)g.nvox();
-    r->tortuosity = eps * d_lref / r->Deff_lattice;
-    r->tortuosity_local = eps * (cs2 * sum_tau / (double)nf) / r->Deff_lattice;
-    double mn = planes[0], mx = planes[0], mean = 0.0;
-    for (int k = 0; k <= g.nx; k++) {
-        mn = planes[k] < mn ? planes[k] : mn;
-        mx = planes[k] > mx ? planes[k] : mx;
-        mean += planes[k];
-    }
-    mean /= (double)(g.nx + 1);
-    r->flux_spread = mean != 0.0 ? (mx - mn) / std::fabs(mean) : INFINITY;
-    r->sweep_ms = sweep_ms;
-    const double updates = (double)nf * (double)t;
-    r->mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
-    r->gbps = sweep_ms > 0 ? updates * 60.0 / (sweep_ms * 1e-3) / 1e9 : 0.0;
+    kn_result(r, p, g, nf, t, converged, resid, sums, sum_tau, planes, sweep_ms,
+              (double)nf * (double)t);
     if (diverged) {
         set_error("Knudsen solve diverged (NaN/Inf) by step %lld", (long long)(t0 + t));
         return LBM_E_DIVERGED;
@@ -707,5 +799,419 @@ extern "C" lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const
         for (int k = 0; k < 7; k++) g_h[i * 7 + k] = tmp[i * 8 + k];
         tau_h[i] = tmp[i * 8 + 7];
     }
+    return LBM_OK;
+}
+
+// ============================================================== batched Knudsen solves
+namespace lbm {
+
+struct KnBatchWs {
+    KnLat *lats;
+    int32_t *blocks, *blk_lat, *lat_ids, *total, *planes;
+    unsigned long long *counter;
+    double *res, *tau_sum, *plane;
+    RankWord *rank;
+    uint32_t *coords;
+    float *g[2];
+    float *omega, *csnap;
+    double *partials;
+    double *ref[2];
+    Shift *steady[2];
+    Shift *trans;
+    double *part;
+    int64_t stride, nblk, nrank, ntab, nplane;
+    size_t bytes;
+};
+
+static KnBatchWs carve_kn_batch(void *base, int count, const int32_t *n_h, const int64_t *nf_h) {
+    KnBatchWs w;
+    w.nblk = w.nrank = w.ntab = w.nplane = 0;
+    for (int l = 0; l < count; l++) {
+        const Grid g = make_grid(n_h + 3 * l);
+        w.nblk += kn_blocks(nf_h[l] < 1 ? 1 : nf_h[l]);
+        w.nrank += g.nsegs();
+        w.ntab += g.nx + 2;
+        w.nplane += g.nx;
+    }
+    w.stride = w.nblk * 256;
+    Carver c(base);
+    w.lats = c.take<KnLat>(count);
+    w.blocks = c.take<int32_t>(w.nblk);
+    w.blk_lat = c.take<int32_t>(w.nblk);
+    w.lat_ids = c.take<int32_t>(count);
+    w.total = c.take<int32_t>(count);
+    w.planes = c.take<int32_t>(2 * w.nplane);
+    w.counter = c.take<unsigned long long>(1);
+    w.res = c.take<double>((size_t)count * kKnSums);
+    w.tau_sum = c.take<double>(count);
+    w.plane = c.take<double>(w.ntab);  // nx + 1 link planes per lattice fit its nx + 2 rows
+    w.rank = c.take<RankWord>(w.nrank);
+    w.coords = c.take<uint32_t>(w.stride);
+    w.g[0] = c.take<float>((size_t)7 * w.stride);
+    w.g[1] = c.take<float>((size_t)7 * w.stride);
+    w.omega = c.take<float>(w.stride);
+    w.csnap = c.take<float>(w.stride);
+    w.partials = c.take<double>((size_t)w.nblk * kKnSums);
+    for (int f = 0; f < 2; f++) w.ref[f] = c.take<double>(w.ntab);
+    for (int f = 0; f < 2; f++) w.steady[f] = c.take<Shift>(w.ntab);
+    w.trans = c.take<Shift>(w.ntab);
+    w.part = c.take<double>((size_t)w.nplane * kPlaneParts * 2);
+    w.bytes = c.off;
+    return w;
+}
+
+template <bool CHECK>
+static void launch7b(const Sweep7 &a, const Variant7 &m, const KnBatchWs &w, hipStream_t s) {
+    const unsigned grid = (unsigned)a.launched;
+    if (m.nt) k_sweep7b<CHECK, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+    else k_sweep7b<CHECK, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+}
+
+// The batch's position in its iteration: population buffer, frame of the stored state,
+// and whether the next sweep moves the state into the other frame.
+struct KnPos {
+    int cur = 0, frame = 0;
+    bool pending = false;
+};
+
+// The plane means of the active lattices' checked concentration become their next frames.
+static lbm_status kn_batch_frames(const KnBatchWs &w, int64_t n_planes, int n_act, int frame,
+                                  const lbm_knudsen_params *p, hipStream_t s) {
+    k_plane_mean_b<<<(unsigned)(n_planes * kPlaneParts), 256, 0, s>>>(w.planes, w.lats, w.rank,
+                                                                      w.csnap, w.part);
+    LBM_CHECK_LAUNCH();
+    k_frame_next_b<<<(unsigned)n_act, 1024, 0, s>>>(w.lat_ids, w.lats, p->c_in, p->c_out, w.part,
+                                                    w.ref[frame], w.ref[frame ^ 1],
+                                                    w.steady[frame ^ 1], w.trans);
+    LBM_CHECK_LAUNCH();
+    return LBM_OK;
+}
+
+// `steps` sweeps of the active lattices from position q; with check_last the last one
+// checks, the per-lattice sums go to w.res and the next frames are formed.
+static lbm_status kn_batch_steps(const KnBatchWs &w, Sweep7 a, const Variant7 &m, int64_t n_live,
+                                 int n_act, int64_t n_planes, KnPos &q, int64_t steps,
+                                 bool check_last, const lbm_knudsen_params *p, hipStream_t s) {
+    a.launched_live = n_live;
+    a.chunk = m.remap ? (n_live + kXcd - 1) / kXcd : 0;
+    a.launched = a.chunk ? xcd_launch(n_live, a.chunk) : n_live;
+    for (int64_t t = 0; t < steps; t++) {
+        if (q.pending) {
+            a.shift = w.trans;
+            q.frame ^= 1;
+            q.pending = false;
+        } else {
+            a.shift = w.steady[q.frame];
+        }
+        a.ref_out = w.ref[q.frame];
+        a.src = w.g[q.cur];
+        a.dst = w.g[q.cur ^ 1];
+        if (check_last && t == steps - 1) launch7b<true>(a, m, w, s);
+        else launch7b<false>(a, m, w, s);
+        LBM_CHECK_LAUNCH();
+        q.cur ^= 1;
+    }
+    if (check_last) {
+        k_lat_reduce<kKnSums><<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
+        LBM_CHECK_LAUNCH();
+        lbm_status st = kn_batch_frames(w, n_planes, n_act, q.frame, p, s);
+        if (st != LBM_OK) return st;
+        q.pending = true;
+    }
+    return LBM_OK;
+}
+
+}  // namespace lbm
+
+extern "C" size_t lbm_knudsen_batch_workspace(int32_t count, const int32_t *n_h,
+                                              const int64_t *nf_h) {
+    if (count < 1 || !n_h || !nf_h) return 0;
+    for (int l = 0; l < count; l++)
+        if (n_h[3 * l] < 1 || n_h[3 * l + 1] < 1 || n_h[3 * l + 2] < 1 || n_h[3 * l] > kMaxEdge ||
+            n_h[3 * l + 1] > kMaxEdge || n_h[3 * l + 2] > kMaxEdge || nf_h[l] < 0)
+            return 0;
+    return carve_kn_batch(nullptr, count, n_h, nf_h).bytes;
+}
+
+extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
+                                              const uint8_t *const *fluid,
+                                              const double *const *pore_diam, const int64_t *nf_h,
+                                              const lbm_knudsen_params *p, lbm_knudsen_result *r_h,
+                                              float *const *c_field, const float *const *c_init,
+                                              int32_t *variant_h, void *workspace,
+                                              size_t ws_bytes, void *stream) {
+    LBM_REQUIRE(count >= 1 && n_h && fluid && pore_diam && nf_h && p && r_h && workspace,
+                LBM_E_INVAL, "lbm_knudsen_solve_batch: null argument or empty batch");
+    for (int l = 0; l < count; l++) {
+        const int32_t *n = n_h + 3 * l;
+        LBM_REQUIRE(n[0] >= 1 && n[1] >= 1 && n[2] >= 1 && n[0] <= kMaxEdge && n[1] <= kMaxEdge &&
+                        n[2] <= kMaxEdge,
+                    LBM_E_INVAL, "lattice %d: sizes must lie in [1, %d]", l, kMaxEdge);
+        LBM_REQUIRE(fluid[l] && pore_diam[l] && nf_h[l] >= 1, LBM_E_INVAL,
+                    "lattice %d: no fluid mask, pore diameter or node", l);
+    }
+    LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
+    LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
+    LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
+                "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
+    LBM_REQUIRE(!p->resume, LBM_E_INVAL, "batched solves do not resume");
+    LBM_REQUIRE((p->variant & ~(kVariantBits | LBM_VARIANT_NOGRAPH)) == 0, LBM_E_INVAL,
+                "unknown variant bits 0x%x", p->variant);
+    lbm_status st = check_device();
+    if (st != LBM_OK) return st;
+    const KnBatchWs w = carve_kn_batch(workspace, count, n_h, nf_h);
+    LBM_REQUIRE(7 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                "%lld nodes exceed the 32-bit population offsets", (long long)w.stride);
+    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace of %zu bytes; %zu needed", ws_bytes,
+                w.bytes);
+    hipStream_t caller = static_cast<hipStream_t>(stream);
+    BatchRes R;
+    LBM_TRY_HIP(hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
+    LBM_TRY_HIP(hipEventCreate(&R.e0));
+    LBM_TRY_HIP(hipEventCreate(&R.e1));
+    LBM_TRY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
+    LBM_TRY_HIP(hipEventRecord(R.join, caller));
+    LBM_TRY_HIP(hipStreamWaitEvent(R.s, R.join, 0));
+    hipStream_t s = R.s;
+
+    // layout, lattice table, initial state, relaxation times and frame 0 of every lattice
+    const double d_ref = p->d_ref_nm / p->voxel_nm;
+    std::vector<KnLat> lats(count);
+    std::vector<int32_t> blk_lat(w.nblk);
+    LBM_TRY_HIP(hipMemsetAsync(w.counter, 0, sizeof(unsigned long long), s));
+    int64_t n0 = 0, rk0 = 0, b0 = 0, sh0 = 0, pl0 = 0;
+    for (int l = 0; l < count; l++) {
+        const Grid g = make_grid(n_h + 3 * l);
+        int64_t nf = 0;
+        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s, (uint32_t)n0);
+        if (st != LBM_OK) return st;
+        LBM_REQUIRE(nf == nf_h[l], LBM_E_INVAL, "lattice %d has %lld fluid nodes, not %lld", l,
+                    (long long)nf, (long long)nf_h[l]);
+        st = layout_fill(g, w.rank + rk0, w.coords, s);
+        if (st != LBM_OK) return st;
+        KnLat &L = lats[l];
+        L.g = g;
+        L.n_end = n0 + nf;
+        L.rk0 = rk0;
+        L.b0 = b0;
+        L.b1 = b0 + kn_blocks(nf);
+        L.sh0 = sh0;
+        L.pl0 = pl0;
+        L.c_out = c_field ? c_field[l] : nullptr;
+        if (L.c_out) LBM_TRY_HIP(hipMemsetAsync(L.c_out, 0, sizeof(float) * g.nvox(), s));
+        k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(
+            g, nf, w.stride, w.coords + n0, pore_diam[l], d_ref, p->tau_ref,
+            c_init ? c_init[l] : nullptr, w.g[0] + n0, w.omega + n0, w.csnap + n0, 1, w.counter,
+            w.partials + b0);
+        LBM_CHECK_LAUNCH();
+        st = reduce_partials(w.partials + b0, kn_blocks(nf), 1, w.tau_sum + l, s);
+        if (st != LBM_OK) return st;
+        k_frame0<<<1, 1024, 0, s>>>(g.nx, p->c_in, p->c_out, w.ref[0] + sh0, w.steady[0] + sh0);
+        LBM_CHECK_LAUNCH();
+        for (int64_t b = L.b0; b < L.b1; b++) blk_lat[b] = l;
+        n0 = L.b1 * 256;
+        rk0 += g.nsegs();
+        b0 = L.b1;
+        sh0 += g.nx + 2;
+        pl0 += g.nx;
+    }
+    unsigned long long bad = 0;
+    std::vector<double> tau_sum(count);
+    LBM_TRY_HIP(hipMemcpyAsync(&bad, w.counter, sizeof(bad), hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipMemcpyAsync(tau_sum.data(), w.tau_sum, sizeof(double) * count,
+                               hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipMemcpyAsync(w.lats, lats.data(), sizeof(KnLat) * count, hipMemcpyHostToDevice, s));
+    LBM_TRY_HIP(hipMemcpyAsync(w.blk_lat, blk_lat.data(), sizeof(int32_t) * w.nblk,
+                               hipMemcpyHostToDevice, s));
+    LBM_TRY_HIP(hipStreamSynchronize(s));
+    LBM_REQUIRE(bad == 0, LBM_E_INVAL, "%llu fluid nodes have tau_g <= 1/2 (pore diameter <= 0)", bad);
+
+    // the active set: lattices not yet converged, their blocks and their planes
+    std::vector<int32_t> act(count), act_blocks, act_planes;
+    for (int l = 0; l < count; l++) act[l] = l;
+    double live_nodes = 0.0;
+    auto upload_active = [&]() -> lbm_status {
+        act_blocks.clear();
+        act_planes.clear();
+        live_nodes = 0.0;
+        for (int l : act) {
+            for (int64_t b = lats[l].b0; b < lats[l].b1; b++) act_blocks.push_back((int32_t)b);
+            for (int x = 0; x < lats[l].g.nx; x++) {
+                act_planes.push_back(l);
+                act_planes.push_back(x);
+            }
+            live_nodes += (double)nf_h[l];
+        }
+        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, act.data(), sizeof(int32_t) * act.size(),
+                                   hipMemcpyHostToDevice, s));
+        LBM_TRY_HIP(hipMemcpyAsync(w.blocks, act_blocks.data(), sizeof(int32_t) * act_blocks.size(),
+                                   hipMemcpyHostToDevice, s));
+        LBM_TRY_HIP(hipMemcpyAsync(w.planes, act_planes.data(), sizeof(int32_t) * act_planes.size(),
+                                   hipMemcpyHostToDevice, s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));  // the host vectors are reused
+        return LBM_OK;
+    };
+    st = upload_active();
+    if (st != LBM_OK) return st;
+    auto n_live = [&]() { return (int64_t)act_blocks.size(); };
+    auto n_planes = [&]() { return (int64_t)act_planes.size() / 2; };
+
+    // frame 0 holds the initial state; its plane means become the first pending frame
+    KnPos q;
+    st = kn_batch_frames(w, n_planes(), (int)act.size(), 0, p, s);
+    if (st != LBM_OK) return st;
+    q.pending = true;
+
+    Sweep7 a{};
+    a.stride = w.stride;
+    a.coords = w.coords;
+    a.rank = w.rank;
+    a.omega = w.omega;
+    a.csnap = w.csnap;
+    a.partials = w.partials;
+
+    const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
+    const int nc = p->check_every;
+    const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
+    Variant7 mode = pick_variant7(p->variant & kVariantBits, w.stride);
+    int64_t t = 0;
+    double sweep_ms = 0.0, updates = 0.0;
+
+    // autotuner, as in the batched flow solve
+    int32_t chosen = p->variant & kVariantBits;
+    if (!(p->variant & LBM_VARIANT_EXPLICIT)) {
+        const int32_t cand[4] = {LBM_VARIANT_EXPLICIT, LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP,
+                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_NTSTORE,
+                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE};
+        const int64_t per = 8;
+        float best = 0.f;
+        for (int k = 0; k < 4 && t + per + 1 < std::min<int64_t>(limit, nc); k++) {
+            const Variant7 m = pick_variant7(cand[k], w.stride);
+            st = kn_batch_steps(w, a, m, n_live(), (int)act.size(), n_planes(), q, 1, false, p, s);
+            if (st != LBM_OK) return st;
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            st = kn_batch_steps(w, a, m, n_live(), (int)act.size(), n_planes(), q, per, false, p, s);
+            if (st != LBM_OK) return st;
+            LBM_TRY_HIP(hipEventRecord(R.e1, s));
+            LBM_TRY_HIP(hipEventSynchronize(R.e1));
+            float ms = 0.f;
+            LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
+            t += per + 1;
+            sweep_ms += ms;
+            updates += (double)per * live_nodes;
+            if (k == 0 || ms < best) {
+                best = ms;
+                mode = m;
+                chosen = cand[k];
+            }
+        }
+    }
+    if (variant_h) *variant_h = chosen | (p->variant & LBM_VARIANT_NOGRAPH);
+
+    std::vector<double> res((size_t)count * kKnSums, 0.0), sums_l((size_t)count * kKnSums, 0.0);
+    std::vector<int64_t> steps_l(count, 0);
+    std::vector<double> resid_l(count, INFINITY);
+    std::vector<int> conv_l(count, 0), cur_l(count, 0), frame_l(count, 0);
+    bool diverged = false;
+    while (t < limit && !act.empty()) {
+        const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
+        LBM_TRY_HIP(hipEventRecord(R.e0, s));
+        if (use_graph && chunk == nc && q.pending) {
+            // one graph per (buffer, frame) at the start of the interval
+            const int key = q.cur * 2 + q.frame;
+            KnPos q0 = q;
+            if (!R.exec[key]) {
+                LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                st = kn_batch_steps(w, a, mode, n_live(), (int)act.size(), n_planes(), q, chunk,
+                                    true, p, s);
+                hipGraph_t graph = nullptr;
+                hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (st != LBM_OK) return st;
+                LBM_TRY_HIP(ec);
+                R.graph[key] = graph;
+                LBM_TRY_HIP(hipGraphInstantiate(&R.exec[key], graph, nullptr, nullptr, 0));
+            }
+            LBM_TRY_HIP(hipGraphLaunch(R.exec[key], s));
+            // the position after the interval: one frame change, chunk buffer swaps
+            q = q0;
+            q.frame ^= 1;
+            q.cur ^= (int)(chunk & 1);
+            q.pending = true;
+        } else {
+            st = kn_batch_steps(w, a, mode, n_live(), (int)act.size(), n_planes(), q, chunk, true,
+                                p, s);
+            if (st != LBM_OK) return st;
+        }
+        LBM_TRY_HIP(hipEventRecord(R.e1, s));
+        LBM_TRY_HIP(hipMemcpyAsync(res.data(), w.res, sizeof(double) * count * kKnSums,
+                                   hipMemcpyDeviceToHost, s));
+        LBM_TRY_HIP(hipStreamSynchronize(s));
+        float ms = 0.f;
+        LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
+        sweep_ms += ms;
+        updates += (double)chunk * live_nodes;
+        t += chunk;
+        std::vector<int32_t> keep;
+        for (int l : act) {
+            const double *sm = res.data() + (size_t)l * kKnSums;
+            std::copy(sm, sm + kKnSums, sums_l.begin() + (size_t)l * kKnSums);
+            steps_l[l] = t;
+            cur_l[l] = q.cur;
+            frame_l[l] = q.frame;  // the pending frame is not entered by a retired lattice
+            if (!std::isfinite(sm[0]) || !std::isfinite(sm[1]) || !std::isfinite(sm[2])) {
+                diverged = true;
+                continue;
+            }
+            bool done = false;
+            if (t % nc == 0) {
+                resid_l[l] = std::sqrt(sm[0]) / ((double)nc * std::sqrt(sm[1]));
+                if (p->fixed_steps <= 0 && resid_l[l] < p->tol) {
+                    conv_l[l] = 1;
+                    done = true;
+                }
+            }
+            if (!done) keep.push_back(l);
+        }
+        if (diverged) break;
+        if (keep.size() != act.size()) {
+            act = keep;
+            R.drop_graphs();
+            if (!act.empty()) {
+                st = upload_active();
+                if (st != LBM_OK) return st;
+            }
+        }
+    }
+
+    // link-plane fluxes of each lattice's final state, then the results
+    std::vector<double> planes(w.ntab);
+    for (int l = 0; l < count; l++) {
+        const KnLat &L = lats[l];
+        k_plane_flux<<<(unsigned)(L.g.nx + 1), 256, 0, s>>>(L.g, w.stride, w.rank + L.rk0,
+                                                            w.g[cur_l[l]],
+                                                            w.steady[frame_l[l]] + L.sh0,
+                                                            w.plane + L.sh0);
+        LBM_CHECK_LAUNCH();
+    }
+    LBM_TRY_HIP(hipMemcpyAsync(planes.data(), w.plane, sizeof(double) * w.ntab,
+                               hipMemcpyDeviceToHost, s));
+    LBM_TRY_HIP(hipEventRecord(R.join, s));
+    LBM_TRY_HIP(hipStreamWaitEvent(caller, R.join, 0));
+    LBM_TRY_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l < count; l++) {
+        kn_result(r_h + l, p, lats[l].g, nf_h[l], steps_l[l], conv_l[l], resid_l[l],
+                  sums_l.data() + (size_t)l * kKnSums, tau_sum[l], planes.data() + lats[l].sh0,
+                  sweep_ms, updates);
+    }
+    if (diverged) {
+        set_error("batched Knudsen solve diverged (NaN/Inf) by step %lld", (long long)t);
+        return LBM_E_DIVERGED;
+    }
+    for (int l = 0; l < count; l++)
+        if (!conv_l[l] && p->fixed_steps <= 0) {
+            set_error("lattice %d not converged after %lld steps", l, (long long)steps_l[l]);
+            return LBM_W_NOT_CONVERGED;
+        }
     return LBM_OK;
 }

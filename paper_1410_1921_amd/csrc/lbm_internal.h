@@ -137,6 +137,55 @@ __device__ inline void block_sum(double (&v)[NV], double *lds /* [4*NV] */, doub
 
 // Sum `nblocks` rows of NV partials into res[NV] with one 256-thread block, in a fixed
 // order (deterministic for a given nblocks).
+// Batched solves: res[l][k] = the sum of the partial rows [b0, b1) of lattice lat_ids[l]
+// (blockIdx.x = l), in a fixed order.  LD is the solve's lattice descriptor.
+template <int NV, class LD>
+__global__ __launch_bounds__(256) void k_lat_reduce(const double *__restrict__ partials,
+                                                    const LD *__restrict__ lats,
+                                                    const int32_t *__restrict__ lat_ids,
+                                                    double *__restrict__ res) {
+    __shared__ double lds[256];
+    const int lat = lat_ids[blockIdx.x];
+    const int64_t b0 = lats[lat].b0, b1 = lats[lat].b1;
+    for (int k = 0; k < NV; k++) {
+        double s = 0.0;
+        for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) s += partials[b * NV + k];
+        lds[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) res[lat * NV + k] = lds[0];
+        __syncthreads();
+    }
+}
+
+// Batched solves: the internal stream (ordered after the caller's stream by `join`),
+// timing events and the captured graphs of a check interval, released on every return.
+struct BatchRes {
+    static constexpr int kGraphs = 4;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, join = nullptr;
+    hipGraphExec_t exec[kGraphs] = {};
+    hipGraph_t graph[kGraphs] = {};
+    void drop_graphs() {
+        for (int k = 0; k < kGraphs; k++) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            exec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+    }
+    ~BatchRes() {
+        drop_graphs();
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
 lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, double *res,
                            hipStream_t s);
 

@@ -120,6 +120,10 @@ _SIGS = {
                            C.POINTER(lbm_knudsen_result), _P, _P, _P, _P, C.c_size_t, _P],
                           C.c_int32),
     "lbm_knudsen_step": ([_P, C.c_size_t, C.c_int64, _P], C.c_int32),
+    "lbm_knudsen_batch_workspace": ([C.c_int32, _P, _P], C.c_size_t),
+    "lbm_knudsen_solve_batch": ([C.c_int32, _P, _P, _P, _P, C.POINTER(lbm_knudsen_params),
+                                 C.POINTER(lbm_knudsen_result), _P, _P, C.POINTER(C.c_int32), _P,
+                                 C.c_size_t, _P], C.c_int32),
     "lbm_knudsen_sample": ([_P, C.c_size_t, _P, C.c_int64, _P, _P, _P, _P], C.c_int32),
     "lbm_props": ([C.POINTER(lbm_label_stats), C.POINTER(lbm_flow_result),
                    C.POINTER(lbm_knudsen_result), C.POINTER(lbm_props_params),
@@ -416,6 +420,57 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
     res = _as_dict(r)
     res["plane_flux"] = planes
     return Solve(st, res, c, workspace, tuple(fluid.shape))
+
+
+def lbm_knudsen_batch_workspace(shapes, n_fluids):
+    """Workspace bytes of lbm_knudsen_solve_batch (0: invalid sizes)."""
+    n = np.array([[s[2], s[1], s[0]] for s in shapes], np.int32)
+    nf = np.ascontiguousarray(n_fluids, np.int64)
+    return load().lbm_knudsen_batch_workspace(len(n), n.ctypes.data_as(C.c_void_p),
+                                              nf.ctypes.data_as(C.c_void_p))
+
+
+def lbm_knudsen_solve_batch(fluids, pore_diams, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5,
+                            c_in=1.0, c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000,
+                            fixed_steps=0, check_every=100, tol=1e-7, want_c=False, c_inits=None,
+                            n_fluids=None, variant=LBM_VARIANT_AUTO, workspace=None):
+    """D3Q7 Knudsen solves of several lattices in one batch.  c_inits: None or a list of
+    float32 fields (entries may be None).  Returns (status, list of result dicts, list of
+    concentration fields or None, the variant run)."""
+    for m, d in zip(fluids, pore_diams):
+        _vol(m, torch.uint8, "fluid")
+        _vol(d, torch.float64, "pore_diam")
+        if d.shape != m.shape:
+            raise ValueError("pore_diam and fluid shapes differ")
+    if c_inits is not None:
+        for c0, m in zip(c_inits, fluids):
+            if c0 is not None and (_vol(c0, torch.float32, "c_init").shape != m.shape):
+                raise ValueError("c_init and fluid shapes differ")
+    if n_fluids is None:
+        n_fluids = [lbm_count(m) for m in fluids]
+    count = len(fluids)
+    n = np.array([[m.shape[2], m.shape[1], m.shape[0]] for m in fluids], np.int32)
+    nf = np.ascontiguousarray(n_fluids, np.int64)
+    if workspace is None:
+        workspace = Workspace(lbm_knudsen_batch_workspace([m.shape for m in fluids], nf),
+                              fluids[0].device)
+    p = lbm_knudsen_params(tau_ref, d_ref_nm, voxel_nm, c_in, c_out, T, M, max_steps, fixed_steps,
+                           check_every, 0, tol, int(variant), 0)
+    res = (lbm_knudsen_result * count)()
+    cs = [torch.empty(m.shape, dtype=torch.float32, device=m.device) for m in fluids] \
+        if want_c else None
+    V = C.c_void_p * count
+    masks = V(*[m.data_ptr() for m in fluids])
+    diams = V(*[d.data_ptr() for d in pore_diams])
+    c_ptrs = V(*[c.data_ptr() for c in cs]) if want_c else None
+    i_ptrs = V(*[0 if c0 is None else c0.data_ptr() for c0 in c_inits]) if c_inits else None
+    ran = C.c_int32(0)
+    st = _check(load().lbm_knudsen_solve_batch(count, n.ctypes.data_as(C.c_void_p), masks, diams,
+                                               nf.ctypes.data_as(C.c_void_p), C.byref(p), res,
+                                               c_ptrs, i_ptrs, C.byref(ran), workspace.ptr,
+                                               workspace.nbytes, _stream()),
+                "lbm_knudsen_solve_batch")
+    return st, [_as_dict(r) for r in res], cs, ran.value
 
 
 def lbm_knudsen_step(workspace, steps):

@@ -27,7 +27,7 @@ def _declared(header=HEADER):
 def test_every_declared_symbol_is_exported(lib):
     L = lib.load()
     names = _declared() + _declared(os.path.join(ROOT, "include", "lbm_nn.h"))
-    assert len(names) == 18 + 15
+    assert len(names) == 20 + 15
     for name in names:
         assert hasattr(L, name), name
     # and the binding wraps each of them
@@ -168,4 +168,29 @@ def test_batch_sizes_and_checks(lib):
     for kw in (dict(storage=1), dict(storage=2), dict(resume=1), dict(with_rho=1),
                dict(force=(0, 1e-6, 0)), dict(tau=0.5), dict(variant=2), dict(collision=2),
                dict(count=0)):
+        assert call(**kw) == lib.LBM_E_INVAL, kw
+
+
+def test_knudsen_batch_sizes_and_checks(lib):
+    L = lib.load()
+    one = lib.lbm_knudsen_batch_workspace([(32, 32, 32)], [1000])
+    two = lib.lbm_knudsen_batch_workspace([(32, 32, 32), (16, 24, 40)], [1000, 3000])
+    assert one >= 2 * 7 * 4 * 1024
+    assert two - one >= 2 * 7 * 4 * 3072
+    assert lib.lbm_knudsen_batch_workspace([(8, 8, 2000)], [10]) == 0
+    n = (C.c_int32 * 6)(8, 8, 8, 8, 8, 8)
+    nf = (C.c_int64 * 2)(100, 100)
+    ptrs = (C.c_void_p * 2)(1, 1)
+    res = (lib.lbm_knudsen_result * 2)()
+
+    def call(count=2, **kw):
+        a = dict(tau_ref=1.0, c_in=1.0, c_out=0.0, resume=0, variant=0, check_every=10)
+        a.update(kw)
+        p = lib.lbm_knudsen_params(a["tau_ref"], 60.0, 1.5, a["c_in"], a["c_out"], 323.0, 0.016,
+                                   10, 0, a["check_every"], a["resume"], 1e-7, a["variant"], 0)
+        return L.lbm_knudsen_solve_batch(count, n, ptrs, ptrs, nf, C.byref(p), res, None, None,
+                                         None, C.c_void_p(1), 1 << 30, None)
+
+    for kw in (dict(resume=1), dict(c_out=1.0), dict(tau_ref=0.5), dict(variant=2),
+               dict(check_every=0), dict(count=0)):
         assert call(**kw) == lib.LBM_E_INVAL, kw

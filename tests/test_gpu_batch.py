@@ -126,3 +126,94 @@ def test_reconstructed_batch():
     st, res, us, ran = lbm.lbm_flow_solve_batch(fluids, want_u=True, **kw)
     say("reconstructed batch: variant", ran, "mlups", res[0]["mlups"])
     same(res, singles(fluids, **kw), us)
+
+
+# ------------------------------------------------------------------ Knudsen
+def kn_batch():
+    """Uneven lattices with hashed pore diameters (1-40 voxels) at their fluid voxels."""
+    out = []
+    for shape, seed in (((19, 10, 14), 2), ((33, 7, 5), 8), ((1, 9, 30), 4), ((16, 16, 64), 6),
+                        ((12, 30, 41), 9)):
+        m = W.blob_mask(shape, 0.6, seed)
+        d = W.hash_field(shape, seed, 1.0, 40.0).astype(np.float64) * m
+        out.append((dev(m), dev(d), m, d))
+    return out
+
+
+KN = dict(d_ref_nm=30.0, voxel_nm=1.5, c_in=0.8, c_out=0.3)
+
+
+def kn_singles(items, c_inits=None, **kw):
+    return [lbm.lbm_knudsen_solve(m, d, want_c=True, c_init=None if c_inits is None else c_inits[l],
+                                  **KN, **kw) for l, (m, d, _, _) in enumerate(items)]
+
+
+def kn_same(batch, ones, cs):
+    for l, (b, s) in enumerate(zip(batch, ones)):
+        assert b["steps"] == s["steps"], l
+        assert b["converged"] == s["converged"], l
+        assert torch.equal(cs[l], s.field), l
+        assert b["Deff_lattice"] == pytest.approx(s["Deff_lattice"], rel=1e-12), l
+        assert b["residual"] == pytest.approx(s["residual"], rel=1e-9), l
+        assert b["flux_spread"] == pytest.approx(s["flux_spread"], rel=1e-9, abs=1e-15), l
+        assert b["tortuosity_local"] == pytest.approx(s["tortuosity_local"], rel=1e-12), l
+
+
+def test_knudsen_fixed_steps_equal_single_solves():
+    items = kn_batch()
+    kw = dict(fixed_steps=333, check_every=50)
+    st, res, cs, ran = lbm.lbm_knudsen_solve_batch([i[0] for i in items], [i[1] for i in items],
+                                                   want_c=True, **KN, **kw)
+    assert st == lbm.LBM_OK and ran & E
+    kn_same(res, kn_singles(items, **kw), cs)
+
+
+@pytest.mark.parametrize("variant", [E, E | lbm.LBM_VARIANT_REMAP | lbm.LBM_VARIANT_NTSTORE])
+def test_knudsen_graph_and_host_launches_agree(variant):
+    items = kn_batch()
+    f, d = [i[0] for i in items], [i[1] for i in items]
+    for k in (1, 2, 3, 4, 5):
+        kw = dict(fixed_steps=k * 25, check_every=25)
+        _, a, ca, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, variant=variant, **KN, **kw)
+        _, b, cb, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, variant=variant | NOGRAPH,
+                                                  **KN, **kw)
+        for l in range(len(items)):
+            assert torch.equal(ca[l], cb[l]), (k, l)
+            assert a[l]["Deff_lattice"] == b[l]["Deff_lattice"], (k, l)
+        say("knudsen variant", variant, "intervals", k, "agree")
+
+
+def test_knudsen_retirement_and_warm_start():
+    # ducts of different lengths converge after different numbers of checks; a warm start
+    # (a linear profile) is passed to some lattices only
+    items = []
+    for nx in (6, 12, 24, 40):
+        m = W.square_duct(nx, 3)
+        d = np.full(m.shape, 30.0) * m
+        items.append((dev(m), dev(d), m, d))
+    c0 = [None, dev((np.linspace(0.8, 0.3, 12, dtype=np.float32)[None, None, :] *
+                     items[1][2]).astype(np.float32)), None,
+          dev((np.float32(0.55) * items[3][2]).astype(np.float32))]
+    kw = dict(max_steps=200_000, check_every=100, tol=1e-7)
+    f, d = [i[0] for i in items], [i[1] for i in items]
+    for variant in (0, NOGRAPH):
+        st, res, cs, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, c_inits=c0,
+                                                     variant=variant, **KN, **kw)
+        ones = kn_singles(items, c_inits=c0, **kw)
+        say("knudsen retire steps", [r["steps"] for r in res], [s["steps"] for s in ones])
+        assert len({r["steps"] for r in res}) >= 3
+        assert st == lbm.LBM_OK and all(r["converged"] for r in res)
+        kn_same(res, ones, cs)
+
+
+def test_knudsen_batch_against_oracle(orc):
+    items = kn_batch()[:3]
+    kw = dict(fixed_steps=400, check_every=50)
+    _, res, cs, _ = lbm.lbm_knudsen_solve_batch([i[0] for i in items], [i[1] for i in items],
+                                                want_c=True, **KN, **kw)
+    for l, (_, _, m, d) in enumerate(items):
+        tg = np.where(m == 1, orc.tau_g(d, 20.0, 1.0), 1.0)
+        o = orc.knudsen_solve(m, tg, 0.8, 0.3, **kw)
+        assert np.abs(cs[l].cpu().numpy() - o["c"]).max() < 1e-5
+        assert res[l]["Deff_lattice"] == pytest.approx(o["Deff_lattice"], rel=1e-4)
+        say("knudsen oracle", res[l]["Deff_lattice"], o["Deff_lattice"])
