@@ -260,26 +260,27 @@ lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_
  * Batched flow solves: `count` independent lattices (Section 3.1, as lbm_flow_solve,
  * with one parameter set for all of them), advanced together so that small lattices
  * fill the device.  Each lattice's fluid list starts on a 256-node block of one
- * concatenated list; every launch runs the blocks of the lattices still iterating,
- * and the per-lattice sums of a check are reduced in a fixed order.  A lattice stops
- * at its first check with residual < tol (its result is then frozen); the others go
- * on.  A check interval is one captured HIP graph (re-captured when a lattice
- * retires) unless variant has LBM_VARIANT_NOGRAPH.  Without LBM_VARIANT_EXPLICIT the
- * first steps time the four kernel variants on this batch and keep the fastest (every
- * variant computes the same state).  The populations, residuals and k of each lattice
- * are those lbm_flow_solve gives it alone (the sums of a check may differ in the last
- * bits through their order).
+ * concatenated list.  The lattices still iterating are split, in order, into groups of
+ * at most a byte budget of state (168 bytes per fluid node); each check interval runs
+ * the groups one after the other, each for the whole interval, so that a group whose
+ * state fits the 256 MB Infinity Cache keeps it there.  A group's interval is one
+ * captured HIP graph (re-captured when the groups change) unless variant has
+ * LBM_VARIANT_NOGRAPH; its kernel variant follows from its size unless variant has
+ * LBM_VARIANT_EXPLICIT.  A lattice stops at its first check with residual < tol (its
+ * result is then frozen) and the groups are formed again.  The populations, residuals,
+ * steps and k of each lattice are those lbm_flow_solve gives it alone (the sums of a
+ * check may differ in the last bits through their order), whatever the schedule.
  *
  * n_h      : host int32[count][3] lattice sizes (nx, ny, nz), each <= 1024.
  * fluid    : host array of count device pointers, each uint8[nz][ny][nx] (1 = fluid).
  * nf_h     : host int64[count] fluid-node counts (each >= 1; checked against the masks).
  * p        : one parameter set; storage must be LBM_STORE_FP32, resume and with_rho 0,
  *            force[0] != 0 (k is reported along x).
+ * sched    : nullable, in/out (see lbm_batch_sched); null = autotuned budget.
  * r_h      : host lbm_flow_result[count] out; sweep_ms, mlups and gbps are those of
- *            the whole batch in every entry.
+ *            the whole batch (autotuning included) in every entry.
  * u_out    : host array of count device pointers (or null; entries may be null), each
  *            float[3][nz][ny][nx] out: the lattice's velocity at its last check.
- * variant_h: host int32 out, nullable: the variant bits the solve ran.
  * workspace: lbm_flow_batch_workspace(count, n_h, nf_h) bytes of device memory.
  * The work runs on an internal stream ordered after `stream` and before later work
  * on it; the call returns when the solve is finished.
@@ -287,12 +288,25 @@ lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_
  * binary64 storage, resume, with_rho), LBM_E_NOMEM (workspace too small),
  * LBM_E_DIVERGED, LBM_W_NOT_CONVERGED (some lattice reached max_steps), LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
+typedef struct {
+    int64_t group_bytes;      /* in: 0 autotune (the first check intervals run one
+                                 candidate each: the whole batch as one group, then
+                                 budgets of 128, 192, 256 and 384 MB; the fastest per
+                                 node update runs the rest), < 0 one group, > 0 this
+                                 budget */
+    int64_t group_bytes_run;  /* out: the budget run (-1: one group) */
+    int32_t groups;           /* out: groups once the budget is fixed */
+    int32_t variant;          /* out: the variant bits run (0: chosen per group) */
+    double tune_ms;           /* out: GPU time of the tuning intervals (their steps count) */
+} lbm_batch_sched;
+
 size_t lbm_flow_batch_workspace(int32_t count, const int32_t *n_h, const int64_t *nf_h);
 
 lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t *const *fluid,
                                 const int64_t *nf_h, const lbm_flow_params *p,
-                                lbm_flow_result *r_h, float *const *u_out, int32_t *variant_h,
-                                void *workspace, size_t ws_bytes, void *stream);
+                                lbm_batch_sched *sched, lbm_flow_result *r_h,
+                                float *const *u_out, void *workspace, size_t ws_bytes,
+                                void *stream);
 
 /* ------------------------------------------------------------------------------
  * Knudsen mass-transport solve (Section 3.2, Eq. 10, on the D3Q7 lattice with rest
@@ -358,24 +372,25 @@ lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const int64_t *v
 
 /* ------------------------------------------------------------------------------
  * Batched Knudsen solves: `count` independent lattices (Section 3.2, as
- * lbm_knudsen_solve, one parameter set for all), advanced together as the batched flow
- * solves are (block-aligned concatenated lists, per-lattice retirement at checks,
- * captured check intervals unless LBM_VARIANT_NOGRAPH, variant autotuning without
- * LBM_VARIANT_EXPLICIT).  Each lattice keeps its own reference frames; the
- * populations, steps and D_eff of a lattice are those lbm_knudsen_solve gives it alone
- * (check sums up to their summation order).
+ * lbm_knudsen_solve, one parameter set for all), scheduled as the batched flow solves
+ * are (block-aligned concatenated lists, groups of at most a byte budget of state at 68
+ * bytes per fluid node run one after the other for whole check intervals, captured
+ * intervals unless LBM_VARIANT_NOGRAPH, per-lattice retirement at checks).  Each
+ * lattice keeps its own reference frames; the populations, steps and D_eff of a
+ * lattice are those lbm_knudsen_solve gives it alone (check sums up to their
+ * summation order), whatever the schedule.
  *
  * n_h       : host int32[count][3] lattice sizes, each <= 1024.
  * fluid     : host array of count device pointers, uint8[nz][ny][nx] each.
  * pore_diam : host array of count device pointers, double[nz][ny][nx] each (voxels).
  * nf_h      : host int64[count] fluid-node counts (each >= 1; checked).
  * p         : one parameter set; resume must be 0.
+ * sched     : nullable, in/out (lbm_batch_sched); null = autotuned budget.
  * r_h       : host lbm_knudsen_result[count] out (sweep_ms, mlups, gbps of the batch).
  * c_field   : host array of count device pointers or null (entries may be null),
  *             float[nz][ny][nx] out: C at the lattice's last check.
  * c_init    : host array of count device pointers or null (entries may be null),
  *             float[nz][ny][nx] in: initial C (warm start).
- * variant_h : host int32 out, nullable: the variant bits the solve ran.
  * workspace : lbm_knudsen_batch_workspace(count, n_h, nf_h) bytes.
  * The work runs on an internal stream ordered after `stream` and before later work on
  * it; the call returns when the solve is finished.
@@ -385,9 +400,9 @@ size_t lbm_knudsen_batch_workspace(int32_t count, const int32_t *n_h, const int6
 
 lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h, const uint8_t *const *fluid,
                                    const double *const *pore_diam, const int64_t *nf_h,
-                                   const lbm_knudsen_params *p, lbm_knudsen_result *r_h,
-                                   float *const *c_field, const float *const *c_init,
-                                   int32_t *variant_h, void *workspace, size_t ws_bytes,
+                                   const lbm_knudsen_params *p, lbm_batch_sched *sched,
+                                   lbm_knudsen_result *r_h, float *const *c_field,
+                                   const float *const *c_init, void *workspace, size_t ws_bytes,
                                    void *stream);
 
 /* ------------------------------------------------------------------------------

@@ -98,6 +98,7 @@ extern "C" size_t lbm_sizeof(int32_t which) {
     case 6: return sizeof(lbm_knudsen_result);
     case 7: return sizeof(lbm_props_params);
     case 8: return sizeof(lbm_props_out);
+    case 9: return sizeof(lbm_batch_sched);
     default: return 0;
     }
 }

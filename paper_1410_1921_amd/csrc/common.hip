@@ -180,6 +180,45 @@ lbm_status layout_count(const Grid &g, const uint8_t *fluid, RankWord *rank, int
     return LBM_OK;
 }
 
+std::vector<BatchGroup> form_groups(const std::vector<int32_t> &act,
+                                    const std::vector<BatchLat> &lat, double per_node,
+                                    double budget, std::vector<int32_t> &blocks,
+                                    std::vector<int32_t> &lat_ids, std::vector<int32_t> *planes) {
+    std::vector<BatchGroup> groups;
+    blocks.clear();
+    lat_ids.clear();
+    if (planes) planes->clear();
+    double bytes = 0.0;
+    for (int32_t l : act) {
+        const BatchLat &L = lat[l];
+        const double b = per_node * (double)L.nf;
+        if (groups.empty() || (budget > 0 && bytes > 0 && bytes + b > budget)) {
+            BatchGroup g;
+            g.blk_off = (int64_t)blocks.size();
+            g.lat_off = (int32_t)lat_ids.size();
+            g.pl_off = planes ? (int64_t)planes->size() / 2 : 0;
+            g.n_blk = g.n_lat = g.n_pl = 0;
+            g.nodes = 0.0;
+            groups.push_back(g);
+            bytes = 0.0;
+        }
+        BatchGroup &g = groups.back();
+        for (int64_t k = L.b0; k < L.b1; k++) blocks.push_back((int32_t)k);
+        lat_ids.push_back(l);
+        if (planes)
+            for (int x = 0; x < L.nx; x++) {
+                planes->push_back(l);
+                planes->push_back(x);
+            }
+        g.n_blk += L.b1 - L.b0;
+        g.n_lat += 1;
+        g.n_pl += planes ? L.nx : 0;
+        g.nodes += (double)L.nf;
+        bytes += b;
+    }
+    return groups;
+}
+
 lbm_status layout_fill(const Grid &g, const RankWord *rank, uint32_t *coords, hipStream_t s) {
     k_seg_fill<<<(unsigned)((g.nsegs() + 3) / 4), 256, 0, s>>>(g, rank, coords);
     LBM_CHECK_LAUNCH();

@@ -419,43 +419,50 @@ __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
 }
 
 // ---------------------------------------------------------------- batched solves
-// Many lattices in one launch: their fluid lists are concatenated, each starting on a
-// 256-node block, with rank maps whose bases are global node ids.  Block b of the launch
-// runs physical block blocks[b] of the lattice blk_lat says; each lattice brings its own
-// grid, rank map and collision parameters.
+// Many lattices in one launch, all with one set of collision parameters.  Lattice l owns
+// the blocks [b0, b1) of the batch: its nodes are the local ids [0, nf) at offset
+// n0 = 256 b0, and each of its arrays is a contiguous run at that offset with its own
+// stride span = 256 (b1 - b0) (populations at 19 n0, snapshot at 3 n0), so that the state
+// of consecutive lattices is one contiguous range, as in a single solve.  Launched block b
+// runs the work that descs[b] describes: one 64-byte record, found with one scalar load.
+struct BlkDesc19 {
+    Grid g;          // the lattice's grid
+    int32_t pb;      // physical block (partial-sum row)
+    int32_t b0, b1;  // the lattice's blocks
+    int32_t nf;      // its fluid nodes
+    int64_t rk0;     // its first rank word (local ids)
+    float *u_out;    // its velocity field, written at checks (nullable)
+    int64_t pad;
+};
+static_assert(sizeof(BlkDesc19) == 64, "one record per launched block");
+
+// Per lattice, for the reduction of a check: its physical blocks.
 struct LatDesc {
-    Grid g;
-    int64_t n_end;          // one past the lattice's last node (global id)
-    int64_t rk0;            // first rank word of the lattice
-    int64_t b0, b1;         // its physical blocks
-    float omega, fpre, Fx, Fy, Fz, sq;
-    double nvox;
-    float *u_out;           // the lattice's velocity field, written at checks (nullable)
+    int64_t b0, b1;
 };
 
 template <bool CHECK, bool NT, bool MRT>
-__global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const LatDesc *__restrict__ lats,
-                                                  const int32_t *__restrict__ blocks,
-                                                  const int32_t *__restrict__ blk_lat) {
+__global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__restrict__ descs) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
     const bool live = lb < a.launched_live;
-    const int64_t pb = live ? blocks[lb] : 0;
+    int64_t pb = 0;
     if (live) {
-        const LatDesc L = lats[blk_lat[pb]];
+        const BlkDesc19 D = descs[lb];
+        pb = D.pb;
+        const int64_t n0 = (int64_t)D.b0 * 256;
         Sweep19 b = a;
-        b.g = L.g;
-        b.nf = L.n_end;
-        b.rank = a.rank + L.rk0;
-        b.omega = L.omega;
-        b.fpre = L.fpre;
-        b.Fx = L.Fx;
-        b.Fy = L.Fy;
-        b.Fz = L.Fz;
-        b.sq = L.sq;
-        b.u_out = L.u_out;
-        const int64_t n = pb * 256 + threadIdx.x;
-        if (n < L.n_end) sweep19_node<StoreF32, CHECK, NT, MRT>(b, n, acc);
+        b.g = D.g;
+        b.nf = D.nf;
+        b.stride = (int64_t)(D.b1 - D.b0) * 256;
+        b.coords = a.coords + n0;
+        b.rank = a.rank + D.rk0;
+        b.src = static_cast<const float *>(a.src) + 19 * n0;
+        b.dst = static_cast<float *>(a.dst) + 19 * n0;
+        b.usnap = a.usnap + 3 * n0;
+        b.u_out = D.u_out;
+        const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
+        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, MRT>(b, n, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
 }
@@ -515,10 +522,10 @@ __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
     }
 }
 
-// Kernel variant: explicit bits, or chosen from the working set: when the two
-// population arrays exceed ~3/4 of the 256 MB Infinity Cache the sweep streams from HBM
-// (plain workgroup order, non-temporal stores), otherwise it keeps the state in the cache
-// (XCD-contiguous order, ordinary stores).
+// Kernel variant: explicit bits, or chosen from the working set: when the two population
+// arrays and the coordinates exceed the 256 MB Infinity Cache the sweep streams from HBM
+// (plain workgroup order, non-temporal stores), otherwise it keeps the state in the
+// cache (XCD-contiguous order, ordinary stores).
 struct Variant19 {
     bool remap, nt;
 };
@@ -530,7 +537,7 @@ static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
         m.nt = v & LBM_VARIANT_NTSTORE;
         return m;
     }
-    const bool stream = 2.0 * 19 * pop_bytes(storage) * (double)stride > 192e6;
+    const bool stream = (2.0 * 19 * pop_bytes(storage) + 4.0) * (double)stride > kCacheBytes;
     m.remap = !stream;
     m.nt = stream;
     return m;
@@ -871,7 +878,8 @@ namespace lbm {
 
 struct BatchWs {
     LatDesc *lats;
-    int32_t *blocks, *blk_lat, *lat_ids, *total;
+    BlkDesc19 *descs;
+    int32_t *lat_ids, *total;
     double *res;
     RankWord *rank;
     uint32_t *coords;
@@ -894,8 +902,7 @@ static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int6
     w.stride = w.nblk * 256;
     Carver c(base);
     w.lats = c.take<LatDesc>(count);
-    w.blocks = c.take<int32_t>(w.nblk);
-    w.blk_lat = c.take<int32_t>(w.nblk);
+    w.descs = c.take<BlkDesc19>(w.nblk);
     w.lat_ids = c.take<int32_t>(count);
     w.total = c.take<int32_t>(count);
     w.res = c.take<double>((size_t)count * kFlowSums);
@@ -910,40 +917,46 @@ static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int6
 }
 
 template <bool CHECK>
-static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision, const BatchWs &w,
-                      hipStream_t s) {
+static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision,
+                      const BlkDesc19 *descs, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
     if (collision == LBM_COLLIDE_MRT) {
-        if (m.nt) k_sweep19b<CHECK, true, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
-        else k_sweep19b<CHECK, false, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+        if (m.nt) k_sweep19b<CHECK, true, true><<<grid, 256, 0, s>>>(a, descs);
+        else k_sweep19b<CHECK, false, true><<<grid, 256, 0, s>>>(a, descs);
     } else {
-        if (m.nt) k_sweep19b<CHECK, true, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
-        else k_sweep19b<CHECK, false, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+        if (m.nt) k_sweep19b<CHECK, true, false><<<grid, 256, 0, s>>>(a, descs);
+        else k_sweep19b<CHECK, false, false><<<grid, 256, 0, s>>>(a, descs);
     }
 }
 
-// `steps` sweeps of every active lattice from buffer cur; the last one checks, then the
-// per-lattice sums of the n_act active lattices go to w.res.
+// `steps` sweeps of the lattices of group g from buffer cur; the last one checks, then
+// the group's per-lattice sums go to w.res.
 static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, int32_t collision,
-                              int64_t n_live, int n_act, int cur, int64_t steps, bool check_last,
+                              const BatchGroup &g, int cur, int64_t steps, bool check_last,
                               hipStream_t s) {
+    const int64_t n_live = g.n_blk;
     a.launched_live = n_live;
     a.chunk = m.remap ? (n_live + kXcd - 1) / kXcd : 0;
     a.launched = a.chunk ? xcd_launch(n_live, a.chunk) : n_live;
+    const BlkDesc19 *descs = w.descs + g.blk_off;
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
-        if (check_last && t == steps - 1) launch19b<true>(a, m, collision, w, s);
-        else launch19b<false>(a, m, collision, w, s);
+        if (check_last && t == steps - 1) launch19b<true>(a, m, collision, descs, s);
+        else launch19b<false>(a, m, collision, descs, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
     if (check_last) {
-        k_lat_reduce<kFlowSums><<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
+        k_lat_reduce<kFlowSums><<<(unsigned)g.n_lat, 256, 0, s>>>(w.partials, w.lats,
+                                                                  w.lat_ids + g.lat_off, w.res);
         LBM_CHECK_LAUNCH();
     }
     return LBM_OK;
 }
+
+// Binary32 flow state per fluid node: two population buffers, coordinate, snapshot.
+constexpr double kBatchFlowNodeBytes = 2 * 19 * 4 + 4 + 12;
 
 }  // namespace lbm
 
@@ -958,8 +971,8 @@ extern "C" size_t lbm_flow_batch_workspace(int32_t count, const int32_t *n_h, co
 
 extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
                                            const uint8_t *const *fluid, const int64_t *nf_h,
-                                           const lbm_flow_params *p, lbm_flow_result *r_h,
-                                           float *const *u_out, int32_t *variant_h,
+                                           const lbm_flow_params *p, lbm_batch_sched *sched,
+                                           lbm_flow_result *r_h, float *const *u_out,
                                            void *workspace, size_t ws_bytes, void *stream) {
     LBM_REQUIRE(count >= 1 && n_h && fluid && nf_h && p && r_h && workspace, LBM_E_INVAL,
                 "lbm_flow_solve_batch: null argument or empty batch");
@@ -981,164 +994,142 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     const BatchWs w = carve_batch(workspace, count, n_h, nf_h);
-    LBM_REQUIRE(19 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
-                "%lld nodes exceed the 32-bit population offsets", (long long)w.stride);
+    for (int l = 0; l < count; l++)
+        LBM_REQUIRE(19 * blocks_for(nf_h[l]) * 256 <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                    "lattice %d: %lld nodes exceed the 32-bit population offsets", l,
+                    (long long)nf_h[l]);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace of %zu bytes; %zu needed", ws_bytes,
                 w.bytes);
     hipStream_t caller = static_cast<hipStream_t>(stream);
-
     BatchRes R;
-    LBM_TRY_HIP(hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
-    LBM_TRY_HIP(hipEventCreate(&R.e0));
-    LBM_TRY_HIP(hipEventCreate(&R.e1));
-    LBM_TRY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
-    LBM_TRY_HIP(hipEventRecord(R.join, caller));
-    LBM_TRY_HIP(hipStreamWaitEvent(R.s, R.join, 0));
+    st = R.open(caller);
+    if (st != LBM_OK) return st;
     hipStream_t s = R.s;
 
-    // layout, lattice table, initial state
+    // layout, lattice tables, initial state
     std::vector<LatDesc> lats(count);
-    std::vector<int32_t> blk_lat(w.nblk);
+    std::vector<BatchLat> bl(count);
+    std::vector<BlkDesc19> blk(w.nblk);  // the record of each physical block
+    std::vector<double> nvox(count);
     int64_t n0 = 0, rk0 = 0, b0 = 0;
     for (int l = 0; l < count; l++) {
         const Grid g = make_grid(n_h + 3 * l);
         int64_t nf = 0;
-        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s, (uint32_t)n0);
+        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s);
         if (st != LBM_OK) return st;
         LBM_REQUIRE(nf == nf_h[l], LBM_E_INVAL, "lattice %d has %lld fluid nodes, not %lld", l,
                     (long long)nf, (long long)nf_h[l]);
-        st = layout_fill(g, w.rank + rk0, w.coords, s);
+        st = layout_fill(g, w.rank + rk0, w.coords + n0, s);
         if (st != LBM_OK) return st;
+        const int64_t b1 = b0 + blocks_for(nf), span = (b1 - b0) * 256;
         k_flow_init<StoreF32><<<(unsigned)blocks_for(nf), 256, 0, s>>>(
-            g, nf, w.stride, w.coords + n0, nullptr, 0, w.f[0] + n0, 1.f, nullptr, w.usnap + n0);
+            g, nf, span, w.coords + n0, nullptr, 0, w.f[0] + 19 * n0, 1.f, nullptr,
+            w.usnap + 3 * n0);
         LBM_CHECK_LAUNCH();
-        LatDesc &L = lats[l];
-        L.g = g;
-        L.n_end = n0 + nf;
-        L.rk0 = rk0;
-        L.b0 = b0;
-        L.b1 = b0 + blocks_for(nf);
-        L.omega = (float)(1.0 / p->tau);
-        L.fpre = (float)(1.0 - 0.5 / p->tau);
-        L.Fx = (float)p->force[0];
-        L.Fy = (float)p->force[1];
-        L.Fz = (float)p->force[2];
-        L.sq = (float)(8.0 * (2.0 * p->tau - 1.0) / (8.0 * p->tau - 1.0));
-        L.nvox = (double)g.nvox();
-        L.u_out = u_out ? u_out[l] : nullptr;
-        if (L.u_out) LBM_TRY_HIP(hipMemsetAsync(L.u_out, 0, sizeof(float) * 3 * g.nvox(), s));
-        for (int64_t b = L.b0; b < L.b1; b++) blk_lat[b] = l;
-        n0 = L.b1 * 256;
+        float *uo = u_out ? u_out[l] : nullptr;
+        if (uo) LBM_TRY_HIP(hipMemsetAsync(uo, 0, sizeof(float) * 3 * g.nvox(), s));
+        lats[l] = LatDesc{b0, b1};
+        bl[l] = BatchLat{b0, b1, nf, g.nx};
+        nvox[l] = (double)g.nvox();
+        for (int64_t b = b0; b < b1; b++)
+            blk[b] = BlkDesc19{g, (int32_t)b, (int32_t)b0, (int32_t)b1, (int32_t)nf, rk0, uo, 0};
+        n0 = b1 * 256;
         rk0 += g.nsegs();
-        b0 = L.b1;
+        b0 = b1;
     }
     LBM_TRY_HIP(hipMemcpyAsync(w.lats, lats.data(), sizeof(LatDesc) * count, hipMemcpyHostToDevice, s));
-    LBM_TRY_HIP(hipMemcpyAsync(w.blk_lat, blk_lat.data(), sizeof(int32_t) * w.nblk, hipMemcpyHostToDevice, s));
 
-    // the active set: lattices not yet converged, and their blocks
-    std::vector<int32_t> act(count), act_blocks;
+    // the active lattices in groups; each group's block records in launch order
+    std::vector<int32_t> act(count), blocks_h, lat_ids_h;
+    std::vector<BlkDesc19> descs_h;
     for (int l = 0; l < count; l++) act[l] = l;
-    double live_nodes = 0.0;  // fluid nodes of the active lattices
-    auto upload_active = [&]() -> lbm_status {
-        act_blocks.clear();
-        live_nodes = 0.0;
-        for (int l : act) {
-            for (int64_t b = lats[l].b0; b < lats[l].b1; b++) act_blocks.push_back((int32_t)b);
-            live_nodes += (double)nf_h[l];
-        }
-        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, act.data(), sizeof(int32_t) * act.size(),
+    std::vector<BatchGroup> groups;
+    auto regroup = [&](double budget) -> lbm_status {
+        groups = form_groups(act, bl, kBatchFlowNodeBytes, budget, blocks_h, lat_ids_h, nullptr);
+        descs_h.resize(blocks_h.size());
+        for (size_t k = 0; k < blocks_h.size(); k++) descs_h[k] = blk[blocks_h[k]];
+        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, lat_ids_h.data(), sizeof(int32_t) * lat_ids_h.size(),
                                    hipMemcpyHostToDevice, s));
-        LBM_TRY_HIP(hipMemcpyAsync(w.blocks, act_blocks.data(), sizeof(int32_t) * act_blocks.size(),
+        LBM_TRY_HIP(hipMemcpyAsync(w.descs, descs_h.data(), sizeof(BlkDesc19) * descs_h.size(),
                                    hipMemcpyHostToDevice, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));  // the host vectors are reused
+        R.reset_graphs(groups.size());
         return LBM_OK;
     };
-    st = upload_active();
-    if (st != LBM_OK) return st;
+    const int32_t vbits = p->variant & kVariantBits;
+    auto group_mode = [&](const BatchGroup &g) {
+        return pick_variant(vbits, (int64_t)g.nodes, LBM_STORE_FP32);
+    };
+    double live_nodes = 0.0;
+    for (int l : act) live_nodes += (double)nf_h[l];
 
     Sweep19 a{};
     a.stride = w.stride;
     a.coords = w.coords;
     a.rank = w.rank;
+    a.omega = (float)(1.0 / p->tau);
+    a.fpre = (float)(1.0 - 0.5 / p->tau);
+    a.Fx = (float)p->force[0];
+    a.Fy = (float)p->force[1];
+    a.Fz = (float)p->force[2];
+    a.sq = (float)(8.0 * (2.0 * p->tau - 1.0) / (8.0 * p->tau - 1.0));  // Eq. 7
     a.omega_d = 1.0 / p->tau;
     a.fpre_d = 1.0 - 0.5 / p->tau;
     a.scale = 1.f;
     a.inv_scale = 1.f;
     a.usnap = w.usnap;
-    a.u_out = nullptr;
     a.partials = w.partials;
     a.update_snap = 1;
-    a.with_rho = 0;
 
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
-    Variant19 mode = pick_variant(p->variant & kVariantBits, w.stride, LBM_STORE_FP32);
     int cur = 0;
     int64_t t = 0;
-    double sweep_ms = 0.0, updates = 0.0;
+    double sweep_ms = 0.0, updates = 0.0, tune_ms = 0.0;
 
-    // autotuner: without an explicit variant, the first steps time each candidate on
-    // this batch (every variant computes the same state, so the steps count)
-    int32_t chosen = p->variant & kVariantBits;
-    if (!(p->variant & LBM_VARIANT_EXPLICIT)) {
-        const int32_t cand[4] = {LBM_VARIANT_EXPLICIT, LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP,
-                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_NTSTORE,
-                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE};
-        const int64_t per = 8;
-        float best = 0.f;
-        for (int k = 0; k < 4 && t + per + 1 < std::min<int64_t>(limit, nc); k++) {
-            const Variant19 m = pick_variant(cand[k], w.stride, LBM_STORE_FP32);
-            st = batch_steps(w, a, m, p->collision, (int64_t)act_blocks.size(), (int)act.size(), cur,
-                             1, false, s);  // warm the variant's code
-            if (st != LBM_OK) return st;
-            cur ^= 1;
-            LBM_TRY_HIP(hipEventRecord(R.e0, s));
-            st = batch_steps(w, a, m, p->collision, (int64_t)act_blocks.size(), (int)act.size(), cur,
-                             per, false, s);
-            if (st != LBM_OK) return st;
-            LBM_TRY_HIP(hipEventRecord(R.e1, s));
-            LBM_TRY_HIP(hipEventSynchronize(R.e1));
-            float ms = 0.f;
-            LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
-            cur ^= (int)(per & 1);
-            t += per + 1;
-            sweep_ms += ms;
-            updates += (double)per * live_nodes;
-            if (k == 0 || ms < best) {
-                best = ms;
-                mode = m;
-                chosen = cand[k];
-            }
-        }
-    }
-    if (variant_h) *variant_h = chosen | (p->variant & LBM_VARIANT_NOGRAPH);
+    // schedule: a given group budget, or the autotuner's: the first check intervals run
+    // one candidate budget each (all give the same state), timed per node update, and the
+    // fastest runs the rest
+    const double cand[kBatchBudgets] = LBM_BATCH_BUDGETS;
+    const bool tuning = !sched || sched->group_bytes == 0;
+    int tune_k = tuning ? 0 : kBatchBudgets;
+    double budget = tuning ? cand[0] : (double)sched->group_bytes, best_rate = INFINITY;
+    st = regroup(budget);
+    if (st != LBM_OK) return st;
+    int32_t groups_run = tuning ? -1 : (int32_t)groups.size();
 
-    std::vector<double> res((size_t)count * kFlowSums, 0.0);
+    std::vector<double> res((size_t)count * kFlowSums, 0.0), sums_l((size_t)count * kFlowSums, 0.0);
     std::vector<int64_t> steps_l(count, 0);
     std::vector<double> resid_l(count, INFINITY);
-    std::vector<int> conv_l(count, 0), cur_l(count, 0);
-    std::vector<double> sums_l((size_t)count * kFlowSums, 0.0);
+    std::vector<int> conv_l(count, 0);
     bool diverged = false;
     while (t < limit && !act.empty()) {
         const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
-        const int64_t live = (int64_t)act_blocks.size();
-        LBM_TRY_HIP(hipEventRecord(R.e0, s));
         if (use_graph && chunk == nc) {
-            if (!R.exec[cur]) {
+            // capture what is missing first, so that the timed region holds kernels only
+            for (size_t gi = 0; gi < groups.size(); gi++) {
+                hipGraphExec_t &ex = R.exec[gi * BatchRes::kKeys + cur];
+                if (ex) continue;
                 LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                st = batch_steps(w, a, mode, p->collision, live, (int)act.size(), cur, chunk, true, s);
+                st = batch_steps(w, a, group_mode(groups[gi]), p->collision, groups[gi], cur, chunk,
+                                 true, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (st != LBM_OK) return st;
                 LBM_TRY_HIP(ec);
-                R.graph[cur] = graph;
-                LBM_TRY_HIP(hipGraphInstantiate(&R.exec[cur], graph, nullptr, nullptr, 0));
+                R.graph[gi * BatchRes::kKeys + cur] = graph;
+                LBM_TRY_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
             }
-            LBM_TRY_HIP(hipGraphLaunch(R.exec[cur], s));
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            for (size_t gi = 0; gi < groups.size(); gi++)
+                LBM_TRY_HIP(hipGraphLaunch(R.exec[gi * BatchRes::kKeys + cur], s));
         } else {
-            st = batch_steps(w, a, mode, p->collision, live, (int)act.size(), cur, chunk, true, s);
-            if (st != LBM_OK) return st;
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            for (const BatchGroup &g : groups) {
+                st = batch_steps(w, a, group_mode(g), p->collision, g, cur, chunk, true, s);
+                if (st != LBM_OK) return st;
+            }
         }
         LBM_TRY_HIP(hipEventRecord(R.e1, s));
         LBM_TRY_HIP(hipMemcpyAsync(res.data(), w.res, sizeof(double) * count * kFlowSums,
@@ -1148,6 +1139,18 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
         sweep_ms += ms;
         updates += (double)chunk * live_nodes;
+        bool regroup_now = false;
+        if (tune_k < kBatchBudgets) {
+            tune_ms += ms;
+            const double rate = ms / ((double)chunk * live_nodes);
+            if (rate < best_rate) {
+                best_rate = rate;
+                budget = cand[tune_k];
+            }
+            // the next candidate, or the winner (unless it is the one just run)
+            ++tune_k;
+            regroup_now = tune_k < kBatchBudgets || budget != cand[kBatchBudgets - 1];
+        }
         cur ^= (int)(chunk & 1);
         t += chunk;
         std::vector<int32_t> keep;
@@ -1155,7 +1158,6 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
             const double *sm = res.data() + (size_t)l * kFlowSums;
             std::copy(sm, sm + kFlowSums, sums_l.begin() + (size_t)l * kFlowSums);
             steps_l[l] = t;
-            cur_l[l] = cur;
             if (!std::isfinite(sm[0]) || !std::isfinite(sm[1]) || !std::isfinite(sm[2])) {
                 diverged = true;
                 continue;
@@ -1173,15 +1175,24 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         if (diverged) break;
         if (keep.size() != act.size()) {
             act = keep;
-            R.drop_graphs();
-            if (!act.empty()) {
-                st = upload_active();
-                if (st != LBM_OK) return st;
-            }
+            live_nodes = 0.0;
+            for (int l : act) live_nodes += (double)nf_h[l];
+            regroup_now = true;
         }
+        if (regroup_now && !act.empty()) {
+            st = regroup(tune_k < kBatchBudgets ? cand[tune_k] : budget);
+            if (st != LBM_OK) return st;
+        }
+        if (tune_k == kBatchBudgets && groups_run < 0) groups_run = (int32_t)groups.size();
     }
-    LBM_TRY_HIP(hipEventRecord(R.join, s));
-    LBM_TRY_HIP(hipStreamWaitEvent(caller, R.join, 0));
+    if (sched) {
+        sched->variant = vbits | (p->variant & LBM_VARIANT_NOGRAPH);
+        sched->group_bytes_run = (int64_t)budget;
+        sched->groups = groups_run < 0 ? (int32_t)groups.size() : groups_run;
+        sched->tune_ms = tune_ms;
+    }
+    st = R.close(caller);
+    if (st != LBM_OK) return st;
 
     const double nu = (p->tau - 0.5) / 3.0;
     for (int l = 0; l < count; l++) {
@@ -1192,7 +1203,7 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         r.n_fluid = nf_h[l];
         r.converged = conv_l[l];
         r.residual = resid_l[l];
-        for (int k = 0; k < 3; k++) r.mean_rho_u[k] = sm[2 + k] / lats[l].nvox;
+        for (int k = 0; k < 3; k++) r.mean_rho_u[k] = sm[2 + k] / nvox[l];
         r.mass_dev = sm[5];
         r.k_lattice = nu * r.mean_rho_u[0] / p->force[0];
         const double dx = p->voxel_nm * 1e-9;

@@ -241,25 +241,46 @@ struct KnLat {
     float *c_out;   // concentration field written at checks (nullable)
 };
 
+// Launched block b of a batched sweep runs the work descs[b] describes (one record, one
+// scalar load).  As in the batched flow solve, lattice l owns blocks [b0, b1): local node
+// ids [0, nf) at offset n0 = 256 b0, arrays contiguous there with stride 256 (b1 - b0)
+// (populations at 7 n0).
+struct KnBlk {
+    Grid g;
+    int32_t pb;      // physical block (partial-sum row)
+    int32_t b0, b1;  // the lattice's blocks
+    int32_t nf;      // its fluid nodes
+    int64_t rk0;     // first rank word (local ids)
+    int64_t sh0;     // first entry of the per-x tables
+    float *c_out;    // concentration field written at checks (nullable)
+};
+static_assert(sizeof(KnBlk) == 64, "one record per launched block");
+
 template <bool CHECK, bool NT>
-__global__ __launch_bounds__(256) void k_sweep7b(Sweep7 a, const KnLat *__restrict__ lats,
-                                                 const int32_t *__restrict__ blocks,
-                                                 const int32_t *__restrict__ blk_lat) {
+__global__ __launch_bounds__(256) void k_sweep7b(Sweep7 a, const KnBlk *__restrict__ descs) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
     const bool live = lb < a.launched_live;
-    const int64_t pb = live ? blocks[lb] : 0;
+    int64_t pb = 0;
     if (live) {
-        const KnLat L = lats[blk_lat[pb]];
+        const KnBlk D = descs[lb];
+        pb = D.pb;
+        const int64_t n0 = (int64_t)D.b0 * 256;
         Sweep7 b = a;
-        b.g = L.g;
-        b.nf = L.n_end;
-        b.rank = a.rank + L.rk0;
-        b.shift = a.shift + L.sh0;
-        b.ref_out = a.ref_out + L.sh0;
-        b.c_out = L.c_out;
-        const int64_t n = pb * 256 + threadIdx.x;
-        if (n < L.n_end) sweep7_node<CHECK, NT>(b, n, acc);
+        b.g = D.g;
+        b.nf = D.nf;
+        b.stride = (int64_t)(D.b1 - D.b0) * 256;
+        b.coords = a.coords + n0;
+        b.rank = a.rank + D.rk0;
+        b.omega = a.omega + n0;
+        b.src = a.src + 7 * n0;
+        b.dst = a.dst + 7 * n0;
+        b.csnap = a.csnap + n0;
+        b.shift = a.shift + D.sh0;
+        b.ref_out = a.ref_out + D.sh0;
+        b.c_out = D.c_out;
+        const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
+        if (n < D.nf) sweep7_node<CHECK, NT>(b, n, acc);
     }
     if (CHECK) write_partials7<kKnSums>(acc, pb, live, a.partials);
 }
@@ -356,7 +377,8 @@ __global__ __launch_bounds__(256) void k_plane_mean_b(const int32_t *__restrict_
     const int p = (int)(blockIdx.x % kPlaneParts);
     const int x = planes[2 * q + 1];
     const KnLat L = lats[planes[2 * q]];
-    plane_mean_part(L.g, rank + L.rk0, csnap, x, p, part + 2 * ((L.pl0 + x) * kPlaneParts + p));
+    plane_mean_part(L.g, rank + L.rk0, csnap + L.b0 * 256, x, p,
+                    part + 2 * ((L.pl0 + x) * kPlaneParts + p));
 }
 
 // The next frame: plane means (planes without fluid keep the current value), its steady
@@ -477,8 +499,9 @@ static lbm_status kn_next_frame(const KnWs &w, const Grid &g, const KnHeader &h,
 }
 
 // Kernel variant: explicit bits, or chosen from the working set (see the flow solve):
-// streaming (plain order, non-temporal stores) once the two population arrays exceed
-// ~3/4 of the 256 MB Infinity Cache, cache-resident (XCD-contiguous order) below.
+// streaming (plain order, non-temporal stores) once the two population arrays, 1/tau_g,
+// the snapshot and the coordinates exceed the 256 MB Infinity Cache, cache-resident
+// (XCD-contiguous order) below.
 struct Variant7 {
     bool remap, nt;
 };
@@ -490,7 +513,7 @@ static Variant7 pick_variant7(int32_t v, int64_t stride) {
         m.nt = v & LBM_VARIANT_NTSTORE;
         return m;
     }
-    const bool stream = 2.0 * 7 * 4 * (double)stride > 192e6;
+    const bool stream = (2.0 * 7 * 4 + 12.0) * (double)stride > kCacheBytes;
     m.remap = !stream;
     m.nt = stream;
     return m;
@@ -807,7 +830,8 @@ namespace lbm {
 
 struct KnBatchWs {
     KnLat *lats;
-    int32_t *blocks, *blk_lat, *lat_ids, *total, *planes;
+    KnBlk *descs;
+    int32_t *lat_ids, *total, *planes;
     unsigned long long *counter;
     double *res, *tau_sum, *plane;
     RankWord *rank;
@@ -836,8 +860,7 @@ static KnBatchWs carve_kn_batch(void *base, int count, const int32_t *n_h, const
     w.stride = w.nblk * 256;
     Carver c(base);
     w.lats = c.take<KnLat>(count);
-    w.blocks = c.take<int32_t>(w.nblk);
-    w.blk_lat = c.take<int32_t>(w.nblk);
+    w.descs = c.take<KnBlk>(w.nblk);
     w.lat_ids = c.take<int32_t>(count);
     w.total = c.take<int32_t>(count);
     w.planes = c.take<int32_t>(2 * w.nplane);
@@ -861,10 +884,10 @@ static KnBatchWs carve_kn_batch(void *base, int count, const int32_t *n_h, const
 }
 
 template <bool CHECK>
-static void launch7b(const Sweep7 &a, const Variant7 &m, const KnBatchWs &w, hipStream_t s) {
+static void launch7b(const Sweep7 &a, const Variant7 &m, const KnBlk *descs, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep7b<CHECK, true><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
-    else k_sweep7b<CHECK, false><<<grid, 256, 0, s>>>(a, w.lats, w.blocks, w.blk_lat);
+    if (m.nt) k_sweep7b<CHECK, true><<<grid, 256, 0, s>>>(a, descs);
+    else k_sweep7b<CHECK, false><<<grid, 256, 0, s>>>(a, descs);
 }
 
 // The batch's position in its iteration: population buffer, frame of the stored state,
@@ -874,27 +897,30 @@ struct KnPos {
     bool pending = false;
 };
 
-// The plane means of the active lattices' checked concentration become their next frames.
-static lbm_status kn_batch_frames(const KnBatchWs &w, int64_t n_planes, int n_act, int frame,
+// The plane means of group g's checked concentration become its lattices' next frames.
+static lbm_status kn_batch_frames(const KnBatchWs &w, const BatchGroup &g, int frame,
                                   const lbm_knudsen_params *p, hipStream_t s) {
-    k_plane_mean_b<<<(unsigned)(n_planes * kPlaneParts), 256, 0, s>>>(w.planes, w.lats, w.rank,
-                                                                      w.csnap, w.part);
+    k_plane_mean_b<<<(unsigned)(g.n_pl * kPlaneParts), 256, 0, s>>>(
+        w.planes + 2 * g.pl_off, w.lats, w.rank, w.csnap, w.part);
     LBM_CHECK_LAUNCH();
-    k_frame_next_b<<<(unsigned)n_act, 1024, 0, s>>>(w.lat_ids, w.lats, p->c_in, p->c_out, w.part,
-                                                    w.ref[frame], w.ref[frame ^ 1],
-                                                    w.steady[frame ^ 1], w.trans);
+    k_frame_next_b<<<(unsigned)g.n_lat, 1024, 0, s>>>(w.lat_ids + g.lat_off, w.lats, p->c_in,
+                                                      p->c_out, w.part, w.ref[frame],
+                                                      w.ref[frame ^ 1], w.steady[frame ^ 1],
+                                                      w.trans);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
 
-// `steps` sweeps of the active lattices from position q; with check_last the last one
-// checks, the per-lattice sums go to w.res and the next frames are formed.
-static lbm_status kn_batch_steps(const KnBatchWs &w, Sweep7 a, const Variant7 &m, int64_t n_live,
-                                 int n_act, int64_t n_planes, KnPos &q, int64_t steps,
-                                 bool check_last, const lbm_knudsen_params *p, hipStream_t s) {
+// `steps` sweeps of group g from position q; with check_last the last one checks, the
+// group's per-lattice sums go to w.res and its next frames are formed.
+static lbm_status kn_batch_steps(const KnBatchWs &w, Sweep7 a, const Variant7 &m,
+                                 const BatchGroup &g, KnPos &q, int64_t steps, bool check_last,
+                                 const lbm_knudsen_params *p, hipStream_t s) {
+    const int64_t n_live = g.n_blk;
     a.launched_live = n_live;
     a.chunk = m.remap ? (n_live + kXcd - 1) / kXcd : 0;
     a.launched = a.chunk ? xcd_launch(n_live, a.chunk) : n_live;
+    const KnBlk *descs = w.descs + g.blk_off;
     for (int64_t t = 0; t < steps; t++) {
         if (q.pending) {
             a.shift = w.trans;
@@ -906,20 +932,25 @@ static lbm_status kn_batch_steps(const KnBatchWs &w, Sweep7 a, const Variant7 &m
         a.ref_out = w.ref[q.frame];
         a.src = w.g[q.cur];
         a.dst = w.g[q.cur ^ 1];
-        if (check_last && t == steps - 1) launch7b<true>(a, m, w, s);
-        else launch7b<false>(a, m, w, s);
+        if (check_last && t == steps - 1) launch7b<true>(a, m, descs, s);
+        else launch7b<false>(a, m, descs, s);
         LBM_CHECK_LAUNCH();
         q.cur ^= 1;
     }
     if (check_last) {
-        k_lat_reduce<kKnSums><<<(unsigned)n_act, 256, 0, s>>>(w.partials, w.lats, w.lat_ids, w.res);
+        k_lat_reduce<kKnSums><<<(unsigned)g.n_lat, 256, 0, s>>>(w.partials, w.lats,
+                                                                w.lat_ids + g.lat_off, w.res);
         LBM_CHECK_LAUNCH();
-        lbm_status st = kn_batch_frames(w, n_planes, n_act, q.frame, p, s);
+        lbm_status st = kn_batch_frames(w, g, q.frame, p, s);
         if (st != LBM_OK) return st;
         q.pending = true;
     }
     return LBM_OK;
 }
+
+// Binary32 Knudsen state per fluid node: two population buffers, 1/tau_g, snapshot,
+// coordinate.
+constexpr double kBatchKnNodeBytes = 2 * 7 * 4 + 4 + 4 + 4;
 
 }  // namespace lbm
 
@@ -936,9 +967,9 @@ extern "C" size_t lbm_knudsen_batch_workspace(int32_t count, const int32_t *n_h,
 extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
                                               const uint8_t *const *fluid,
                                               const double *const *pore_diam, const int64_t *nf_h,
-                                              const lbm_knudsen_params *p, lbm_knudsen_result *r_h,
-                                              float *const *c_field, const float *const *c_init,
-                                              int32_t *variant_h, void *workspace,
+                                              const lbm_knudsen_params *p, lbm_batch_sched *sched,
+                                              lbm_knudsen_result *r_h, float *const *c_field,
+                                              const float *const *c_init, void *workspace,
                                               size_t ws_bytes, void *stream) {
     LBM_REQUIRE(count >= 1 && n_h && fluid && pore_diam && nf_h && p && r_h && workspace,
                 LBM_E_INVAL, "lbm_knudsen_solve_batch: null argument or empty batch");
@@ -961,34 +992,33 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     const KnBatchWs w = carve_kn_batch(workspace, count, n_h, nf_h);
-    LBM_REQUIRE(7 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
-                "%lld nodes exceed the 32-bit population offsets", (long long)w.stride);
+    for (int l = 0; l < count; l++)
+        LBM_REQUIRE(7 * kn_blocks(nf_h[l]) * 256 <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+                    "lattice %d: %lld nodes exceed the 32-bit population offsets", l,
+                    (long long)nf_h[l]);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace of %zu bytes; %zu needed", ws_bytes,
                 w.bytes);
     hipStream_t caller = static_cast<hipStream_t>(stream);
     BatchRes R;
-    LBM_TRY_HIP(hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
-    LBM_TRY_HIP(hipEventCreate(&R.e0));
-    LBM_TRY_HIP(hipEventCreate(&R.e1));
-    LBM_TRY_HIP(hipEventCreateWithFlags(&R.join, hipEventDisableTiming));
-    LBM_TRY_HIP(hipEventRecord(R.join, caller));
-    LBM_TRY_HIP(hipStreamWaitEvent(R.s, R.join, 0));
+    st = R.open(caller);
+    if (st != LBM_OK) return st;
     hipStream_t s = R.s;
 
     // layout, lattice table, initial state, relaxation times and frame 0 of every lattice
     const double d_ref = p->d_ref_nm / p->voxel_nm;
     std::vector<KnLat> lats(count);
-    std::vector<int32_t> blk_lat(w.nblk);
+    std::vector<BatchLat> bl(count);
+    std::vector<KnBlk> blk(w.nblk);  // the record of each physical block
     LBM_TRY_HIP(hipMemsetAsync(w.counter, 0, sizeof(unsigned long long), s));
     int64_t n0 = 0, rk0 = 0, b0 = 0, sh0 = 0, pl0 = 0;
     for (int l = 0; l < count; l++) {
         const Grid g = make_grid(n_h + 3 * l);
         int64_t nf = 0;
-        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s, (uint32_t)n0);
+        st = layout_count(g, fluid[l], w.rank + rk0, w.total + l, &nf, s);
         if (st != LBM_OK) return st;
         LBM_REQUIRE(nf == nf_h[l], LBM_E_INVAL, "lattice %d has %lld fluid nodes, not %lld", l,
                     (long long)nf, (long long)nf_h[l]);
-        st = layout_fill(g, w.rank + rk0, w.coords, s);
+        st = layout_fill(g, w.rank + rk0, w.coords + n0, s);
         if (st != LBM_OK) return st;
         KnLat &L = lats[l];
         L.g = g;
@@ -1000,16 +1030,20 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
         L.pl0 = pl0;
         L.c_out = c_field ? c_field[l] : nullptr;
         if (L.c_out) LBM_TRY_HIP(hipMemsetAsync(L.c_out, 0, sizeof(float) * g.nvox(), s));
+        const int64_t span = (L.b1 - L.b0) * 256;
         k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(
-            g, nf, w.stride, w.coords + n0, pore_diam[l], d_ref, p->tau_ref,
-            c_init ? c_init[l] : nullptr, w.g[0] + n0, w.omega + n0, w.csnap + n0, 1, w.counter,
-            w.partials + b0);
+            g, nf, span, w.coords + n0, pore_diam[l], d_ref, p->tau_ref,
+            c_init ? c_init[l] : nullptr, w.g[0] + 7 * n0, w.omega + n0, w.csnap + n0, 1,
+            w.counter, w.partials + b0);
         LBM_CHECK_LAUNCH();
         st = reduce_partials(w.partials + b0, kn_blocks(nf), 1, w.tau_sum + l, s);
         if (st != LBM_OK) return st;
         k_frame0<<<1, 1024, 0, s>>>(g.nx, p->c_in, p->c_out, w.ref[0] + sh0, w.steady[0] + sh0);
         LBM_CHECK_LAUNCH();
-        for (int64_t b = L.b0; b < L.b1; b++) blk_lat[b] = l;
+        bl[l] = BatchLat{L.b0, L.b1, nf, g.nx};
+        for (int64_t b = L.b0; b < L.b1; b++)
+            blk[b] = KnBlk{g, (int32_t)b, (int32_t)L.b0, (int32_t)L.b1, (int32_t)nf, rk0, sh0,
+                           L.c_out};
         n0 = L.b1 * 256;
         rk0 += g.nsegs();
         b0 = L.b1;
@@ -1022,44 +1056,38 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     LBM_TRY_HIP(hipMemcpyAsync(tau_sum.data(), w.tau_sum, sizeof(double) * count,
                                hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(w.lats, lats.data(), sizeof(KnLat) * count, hipMemcpyHostToDevice, s));
-    LBM_TRY_HIP(hipMemcpyAsync(w.blk_lat, blk_lat.data(), sizeof(int32_t) * w.nblk,
-                               hipMemcpyHostToDevice, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
     LBM_REQUIRE(bad == 0, LBM_E_INVAL, "%llu fluid nodes have tau_g <= 1/2 (pore diameter <= 0)", bad);
 
-    // the active set: lattices not yet converged, their blocks and their planes
-    std::vector<int32_t> act(count), act_blocks, act_planes;
+    // the active lattices in groups
+    std::vector<int32_t> act(count), blocks_h, lat_ids_h, planes_h;
+    std::vector<KnBlk> descs_h;
     for (int l = 0; l < count; l++) act[l] = l;
-    double live_nodes = 0.0;
-    auto upload_active = [&]() -> lbm_status {
-        act_blocks.clear();
-        act_planes.clear();
-        live_nodes = 0.0;
-        for (int l : act) {
-            for (int64_t b = lats[l].b0; b < lats[l].b1; b++) act_blocks.push_back((int32_t)b);
-            for (int x = 0; x < lats[l].g.nx; x++) {
-                act_planes.push_back(l);
-                act_planes.push_back(x);
-            }
-            live_nodes += (double)nf_h[l];
-        }
-        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, act.data(), sizeof(int32_t) * act.size(),
+    std::vector<BatchGroup> groups;
+    auto regroup = [&](double budget) -> lbm_status {
+        groups = form_groups(act, bl, kBatchKnNodeBytes, budget, blocks_h, lat_ids_h, &planes_h);
+        descs_h.resize(blocks_h.size());
+        for (size_t k = 0; k < blocks_h.size(); k++) descs_h[k] = blk[blocks_h[k]];
+        LBM_TRY_HIP(hipMemcpyAsync(w.lat_ids, lat_ids_h.data(), sizeof(int32_t) * lat_ids_h.size(),
                                    hipMemcpyHostToDevice, s));
-        LBM_TRY_HIP(hipMemcpyAsync(w.blocks, act_blocks.data(), sizeof(int32_t) * act_blocks.size(),
+        LBM_TRY_HIP(hipMemcpyAsync(w.descs, descs_h.data(), sizeof(KnBlk) * descs_h.size(),
                                    hipMemcpyHostToDevice, s));
-        LBM_TRY_HIP(hipMemcpyAsync(w.planes, act_planes.data(), sizeof(int32_t) * act_planes.size(),
+        LBM_TRY_HIP(hipMemcpyAsync(w.planes, planes_h.data(), sizeof(int32_t) * planes_h.size(),
                                    hipMemcpyHostToDevice, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));  // the host vectors are reused
+        R.reset_graphs(groups.size());
         return LBM_OK;
     };
-    st = upload_active();
-    if (st != LBM_OK) return st;
-    auto n_live = [&]() { return (int64_t)act_blocks.size(); };
-    auto n_planes = [&]() { return (int64_t)act_planes.size() / 2; };
+    const int32_t vbits = p->variant & kVariantBits;
+    auto group_mode = [&](const BatchGroup &g) { return pick_variant7(vbits, (int64_t)g.nodes); };
+    double live_nodes = 0.0;
+    for (int l : act) live_nodes += (double)nf_h[l];
 
     // frame 0 holds the initial state; its plane means become the first pending frame
+    st = regroup(-1.0);
+    if (st != LBM_OK) return st;
     KnPos q;
-    st = kn_batch_frames(w, n_planes(), (int)act.size(), 0, p, s);
+    st = kn_batch_frames(w, groups[0], 0, p, s);
     if (st != LBM_OK) return st;
     q.pending = true;
 
@@ -1074,40 +1102,30 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
-    Variant7 mode = pick_variant7(p->variant & kVariantBits, w.stride);
     int64_t t = 0;
-    double sweep_ms = 0.0, updates = 0.0;
+    double sweep_ms = 0.0, updates = 0.0, tune_ms = 0.0;
 
-    // autotuner, as in the batched flow solve
-    int32_t chosen = p->variant & kVariantBits;
-    if (!(p->variant & LBM_VARIANT_EXPLICIT)) {
-        const int32_t cand[4] = {LBM_VARIANT_EXPLICIT, LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP,
-                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_NTSTORE,
-                                 LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE};
-        const int64_t per = 8;
-        float best = 0.f;
-        for (int k = 0; k < 4 && t + per + 1 < std::min<int64_t>(limit, nc); k++) {
-            const Variant7 m = pick_variant7(cand[k], w.stride);
-            st = kn_batch_steps(w, a, m, n_live(), (int)act.size(), n_planes(), q, 1, false, p, s);
-            if (st != LBM_OK) return st;
-            LBM_TRY_HIP(hipEventRecord(R.e0, s));
-            st = kn_batch_steps(w, a, m, n_live(), (int)act.size(), n_planes(), q, per, false, p, s);
-            if (st != LBM_OK) return st;
-            LBM_TRY_HIP(hipEventRecord(R.e1, s));
-            LBM_TRY_HIP(hipEventSynchronize(R.e1));
-            float ms = 0.f;
-            LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
-            t += per + 1;
-            sweep_ms += ms;
-            updates += (double)per * live_nodes;
-            if (k == 0 || ms < best) {
-                best = ms;
-                mode = m;
-                chosen = cand[k];
-            }
+    // every group of an interval starts from the same position and ends in the same one
+    auto run_groups = [&](int64_t steps, bool check_last) -> lbm_status {
+        KnPos end = q;
+        for (const BatchGroup &g : groups) {
+            end = q;
+            lbm_status e = kn_batch_steps(w, a, group_mode(g), g, end, steps, check_last, p, s);
+            if (e != LBM_OK) return e;
         }
-    }
-    if (variant_h) *variant_h = chosen | (p->variant & LBM_VARIANT_NOGRAPH);
+        q = end;
+        return LBM_OK;
+    };
+
+    // schedule, as in the batched flow solve: a given budget, or one tuning interval per
+    // candidate and the fastest for the rest
+    const double cand[kBatchBudgets] = LBM_BATCH_BUDGETS;
+    const bool tuning = !sched || sched->group_bytes == 0;
+    int tune_k = tuning ? 0 : kBatchBudgets;
+    double budget = tuning ? cand[0] : (double)sched->group_bytes, best_rate = INFINITY;
+    st = regroup(budget);
+    if (st != LBM_OK) return st;
+    int32_t groups_run = tuning ? -1 : (int32_t)groups.size();
 
     std::vector<double> res((size_t)count * kKnSums, 0.0), sums_l((size_t)count * kKnSums, 0.0);
     std::vector<int64_t> steps_l(count, 0);
@@ -1116,31 +1134,33 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     bool diverged = false;
     while (t < limit && !act.empty()) {
         const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
-        LBM_TRY_HIP(hipEventRecord(R.e0, s));
         if (use_graph && chunk == nc && q.pending) {
-            // one graph per (buffer, frame) at the start of the interval
+            // one graph per group and (buffer, frame) at the start of the interval, captured
+            // before the timed region
             const int key = q.cur * 2 + q.frame;
-            KnPos q0 = q;
-            if (!R.exec[key]) {
+            for (size_t gi = 0; gi < groups.size(); gi++) {
+                hipGraphExec_t &ex = R.exec[gi * BatchRes::kKeys + key];
+                if (ex) continue;
+                KnPos qc = q;
                 LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                st = kn_batch_steps(w, a, mode, n_live(), (int)act.size(), n_planes(), q, chunk,
-                                    true, p, s);
+                st = kn_batch_steps(w, a, group_mode(groups[gi]), groups[gi], qc, chunk, true, p, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (st != LBM_OK) return st;
                 LBM_TRY_HIP(ec);
-                R.graph[key] = graph;
-                LBM_TRY_HIP(hipGraphInstantiate(&R.exec[key], graph, nullptr, nullptr, 0));
+                R.graph[gi * BatchRes::kKeys + key] = graph;
+                LBM_TRY_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
             }
-            LBM_TRY_HIP(hipGraphLaunch(R.exec[key], s));
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            for (size_t gi = 0; gi < groups.size(); gi++)
+                LBM_TRY_HIP(hipGraphLaunch(R.exec[gi * BatchRes::kKeys + key], s));
             // the position after the interval: one frame change, chunk buffer swaps
-            q = q0;
             q.frame ^= 1;
             q.cur ^= (int)(chunk & 1);
             q.pending = true;
         } else {
-            st = kn_batch_steps(w, a, mode, n_live(), (int)act.size(), n_planes(), q, chunk, true,
-                                p, s);
+            LBM_TRY_HIP(hipEventRecord(R.e0, s));
+            st = run_groups(chunk, true);
             if (st != LBM_OK) return st;
         }
         LBM_TRY_HIP(hipEventRecord(R.e1, s));
@@ -1151,6 +1171,17 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
         LBM_TRY_HIP(hipEventElapsedTime(&ms, R.e0, R.e1));
         sweep_ms += ms;
         updates += (double)chunk * live_nodes;
+        bool regroup_now = false;
+        if (tune_k < kBatchBudgets) {
+            tune_ms += ms;
+            const double rate = ms / ((double)chunk * live_nodes);
+            if (rate < best_rate) {
+                best_rate = rate;
+                budget = cand[tune_k];
+            }
+            ++tune_k;
+            regroup_now = tune_k < kBatchBudgets || budget != cand[kBatchBudgets - 1];
+        }
         t += chunk;
         std::vector<int32_t> keep;
         for (int l : act) {
@@ -1176,28 +1207,36 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
         if (diverged) break;
         if (keep.size() != act.size()) {
             act = keep;
-            R.drop_graphs();
-            if (!act.empty()) {
-                st = upload_active();
-                if (st != LBM_OK) return st;
-            }
+            live_nodes = 0.0;
+            for (int l : act) live_nodes += (double)nf_h[l];
+            regroup_now = true;
         }
+        if (regroup_now && !act.empty()) {
+            st = regroup(tune_k < kBatchBudgets ? cand[tune_k] : budget);
+            if (st != LBM_OK) return st;
+        }
+        if (tune_k == kBatchBudgets && groups_run < 0) groups_run = (int32_t)groups.size();
+    }
+    if (sched) {
+        sched->variant = vbits | (p->variant & LBM_VARIANT_NOGRAPH);
+        sched->group_bytes_run = (int64_t)budget;
+        sched->groups = groups_run < 0 ? (int32_t)groups.size() : groups_run;
+        sched->tune_ms = tune_ms;
     }
 
     // link-plane fluxes of each lattice's final state, then the results
     std::vector<double> planes(w.ntab);
     for (int l = 0; l < count; l++) {
         const KnLat &L = lats[l];
-        k_plane_flux<<<(unsigned)(L.g.nx + 1), 256, 0, s>>>(L.g, w.stride, w.rank + L.rk0,
-                                                            w.g[cur_l[l]],
-                                                            w.steady[frame_l[l]] + L.sh0,
-                                                            w.plane + L.sh0);
+        k_plane_flux<<<(unsigned)(L.g.nx + 1), 256, 0, s>>>(
+            L.g, (L.b1 - L.b0) * 256, w.rank + L.rk0, w.g[cur_l[l]] + 7 * L.b0 * 256,
+            w.steady[frame_l[l]] + L.sh0, w.plane + L.sh0);
         LBM_CHECK_LAUNCH();
     }
     LBM_TRY_HIP(hipMemcpyAsync(planes.data(), w.plane, sizeof(double) * w.ntab,
                                hipMemcpyDeviceToHost, s));
-    LBM_TRY_HIP(hipEventRecord(R.join, s));
-    LBM_TRY_HIP(hipStreamWaitEvent(caller, R.join, 0));
+    st = R.close(caller);
+    if (st != LBM_OK) return st;
     LBM_TRY_HIP(hipStreamSynchronize(s));
     for (int l = 0; l < count; l++) {
         kn_result(r_h + l, p, lats[l].g, nf_h[l], steps_l[l], conv_l[l], resid_l[l],

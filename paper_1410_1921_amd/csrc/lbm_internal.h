@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/lbm.h"
 
@@ -162,29 +163,78 @@ __global__ __launch_bounds__(256) void k_lat_reduce(const double *__restrict__ p
 }
 
 // Batched solves: the internal stream (ordered after the caller's stream by `join`),
-// timing events and the captured graphs of a check interval, released on every return.
+// timing events and the captured graphs (kKeys per group: buffer parity and frame at
+// the start of a check interval), released on every return.
 struct BatchRes {
-    static constexpr int kGraphs = 4;
+    static constexpr int kKeys = 4;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr, join = nullptr;
-    hipGraphExec_t exec[kGraphs] = {};
-    hipGraph_t graph[kGraphs] = {};
-    void drop_graphs() {
-        for (int k = 0; k < kGraphs; k++) {
+    std::vector<hipGraphExec_t> exec;
+    std::vector<hipGraph_t> graph;
+    void reset_graphs(size_t groups) {
+        for (size_t k = 0; k < exec.size(); k++) {
             if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
             if (graph[k]) (void)hipGraphDestroy(graph[k]);
-            exec[k] = nullptr;
-            graph[k] = nullptr;
         }
+        exec.assign(groups * kKeys, nullptr);
+        graph.assign(groups * kKeys, nullptr);
+    }
+    lbm_status open(hipStream_t caller) {
+        LBM_TRY_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        LBM_TRY_HIP(hipEventCreate(&e0));
+        LBM_TRY_HIP(hipEventCreate(&e1));
+        LBM_TRY_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        LBM_TRY_HIP(hipEventRecord(join, caller));
+        LBM_TRY_HIP(hipStreamWaitEvent(s, join, 0));
+        return LBM_OK;
+    }
+    // later work on the caller's stream waits for everything issued on ours
+    lbm_status close(hipStream_t caller) {
+        LBM_TRY_HIP(hipEventRecord(join, s));
+        LBM_TRY_HIP(hipStreamWaitEvent(caller, join, 0));
+        return LBM_OK;
     }
     ~BatchRes() {
-        drop_graphs();
+        reset_graphs(0);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
         if (join) (void)hipEventDestroy(join);
         if (s) (void)hipStreamDestroy(s);
     }
 };
+
+// A group of active lattices that run a whole check interval together, one group after
+// the other, so that a group whose state fits the Infinity Cache keeps it there.
+struct BatchGroup {
+    int64_t blk_off, n_blk;  // its run of the device block list
+    int32_t lat_off, n_lat;  // its run of the device lattice-id list
+    int64_t pl_off, n_pl;    // its run of the device plane list (Knudsen)
+    double nodes;            // fluid nodes
+};
+
+// The Infinity Cache (MALL) of the device: a sweep whose state fits it runs
+// cache-resident, a larger one streams from HBM.
+constexpr double kCacheBytes = 256e6;
+
+// Group budgets the autotuner of a batched solve tries, one check interval each: the
+// whole batch as one group, then groups of at most 128, 192, 256 and 384 MB of state
+// (the Infinity Cache holds 256 MB; a group a little larger still reuses part of it).
+constexpr int kBatchBudgets = 5;
+#define LBM_BATCH_BUDGETS {-1.0, 128e6, 192e6, 256e6, 384e6}
+
+struct BatchLat {
+    int64_t b0, b1, nf;
+    int32_t nx;
+};
+
+// Splits the active lattices, in order, into groups of at most `budget` bytes of working
+// set at `per_node` bytes per fluid node (budget <= 0: one group; a lattice above the
+// budget is a group of its own) and fills the concatenated lists: blocks, lattice ids and,
+// when `planes` is given, (lattice, x) pairs of every plane.
+std::vector<BatchGroup> form_groups(const std::vector<int32_t> &act,
+                                    const std::vector<BatchLat> &lat, double per_node,
+                                    double budget, std::vector<int32_t> &blocks,
+                                    std::vector<int32_t> &lat_ids, std::vector<int32_t> *planes);
 
 lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, double *res,
                            hipStream_t s);

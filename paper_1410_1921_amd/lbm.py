@@ -98,8 +98,14 @@ class lbm_props_out(C.Structure):
         "tortuosity", "bruggeman_alpha", "mean_free_path_m", "fc_dgm", "k_apparent_m2")]
 
 
+class lbm_batch_sched(C.Structure):
+    _fields_ = [("group_bytes", C.c_int64), ("group_bytes_run", C.c_int64), ("groups", C.c_int32),
+                ("variant", C.c_int32), ("tune_ms", C.c_double)]
+
+
 STRUCTS = [lbm_recon_params, lbm_recon_stats, lbm_label_stats, lbm_flow_params, lbm_flow_result,
-           lbm_knudsen_params, lbm_knudsen_result, lbm_props_params, lbm_props_out]
+           lbm_knudsen_params, lbm_knudsen_result, lbm_props_params, lbm_props_out,
+           lbm_batch_sched]
 
 _P = C.c_void_p
 _SIGS = {
@@ -114,7 +120,7 @@ _SIGS = {
     "lbm_flow_sample": ([_P, C.c_size_t, _P, C.c_int64, _P, _P, _P], C.c_int32),
     "lbm_flow_batch_workspace": ([C.c_int32, _P, _P], C.c_size_t),
     "lbm_flow_solve_batch": ([C.c_int32, _P, _P, _P, C.POINTER(lbm_flow_params),
-                              C.POINTER(lbm_flow_result), _P, C.POINTER(C.c_int32), _P,
+                              C.POINTER(lbm_batch_sched), C.POINTER(lbm_flow_result), _P, _P,
                               C.c_size_t, _P], C.c_int32),
     "lbm_knudsen_solve": ([_P, _P, _P, C.POINTER(lbm_knudsen_params),
                            C.POINTER(lbm_knudsen_result), _P, _P, _P, _P, C.c_size_t, _P],
@@ -122,8 +128,8 @@ _SIGS = {
     "lbm_knudsen_step": ([_P, C.c_size_t, C.c_int64, _P], C.c_int32),
     "lbm_knudsen_batch_workspace": ([C.c_int32, _P, _P], C.c_size_t),
     "lbm_knudsen_solve_batch": ([C.c_int32, _P, _P, _P, _P, C.POINTER(lbm_knudsen_params),
-                                 C.POINTER(lbm_knudsen_result), _P, _P, C.POINTER(C.c_int32), _P,
-                                 C.c_size_t, _P], C.c_int32),
+                                 C.POINTER(lbm_batch_sched), C.POINTER(lbm_knudsen_result), _P,
+                                 _P, _P, C.c_size_t, _P], C.c_int32),
     "lbm_knudsen_sample": ([_P, C.c_size_t, _P, C.c_int64, _P, _P, _P, _P], C.c_int32),
     "lbm_props": ([C.POINTER(lbm_label_stats), C.POINTER(lbm_flow_result),
                    C.POINTER(lbm_knudsen_result), C.POINTER(lbm_props_params),
@@ -365,9 +371,10 @@ def lbm_flow_batch_workspace(shapes, n_fluids):
 def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000,
                          fixed_steps=0, check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False,
                          n_fluids=None, variant=LBM_VARIANT_AUTO, collision=LBM_COLLIDE_BGK,
-                         workspace=None):
-    """D3Q19 flow solves of several lattices in one batch (binary32 storage).  Returns
-    (status, list of result dicts, list of velocity fields or None, the variant run)."""
+                         group_bytes=0, workspace=None):
+    """D3Q19 flow solves of several lattices in one batch (binary32 storage).
+    group_bytes: 0 autotuned, < 0 one group, > 0 the group budget.  Returns (status, list
+    of result dicts, list of velocity fields or None, schedule dict)."""
     for m in fluids:
         _vol(m, torch.uint8, "fluid")
     if n_fluids is None:
@@ -385,12 +392,12 @@ def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_00
           for m in fluids] if want_u else None
     masks = (C.c_void_p * count)(*[m.data_ptr() for m in fluids])
     u_ptrs = (C.c_void_p * count)(*[u.data_ptr() for u in us]) if want_u else None
-    ran = C.c_int32(0)
+    sched = lbm_batch_sched(int(group_bytes))
     st = _check(load().lbm_flow_solve_batch(count, n.ctypes.data_as(C.c_void_p), masks,
-                                            nf.ctypes.data_as(C.c_void_p), C.byref(p), res,
-                                            u_ptrs, C.byref(ran), workspace.ptr,
+                                            nf.ctypes.data_as(C.c_void_p), C.byref(p),
+                                            C.byref(sched), res, u_ptrs, workspace.ptr,
                                             workspace.nbytes, _stream()), "lbm_flow_solve_batch")
-    return st, [_as_dict(r) for r in res], us, ran.value
+    return st, [_as_dict(r) for r in res], us, _as_dict(sched)
 
 
 # ------------------------------------------------------------------ Knudsen
@@ -433,10 +440,11 @@ def lbm_knudsen_batch_workspace(shapes, n_fluids):
 def lbm_knudsen_solve_batch(fluids, pore_diams, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5,
                             c_in=1.0, c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000,
                             fixed_steps=0, check_every=100, tol=1e-7, want_c=False, c_inits=None,
-                            n_fluids=None, variant=LBM_VARIANT_AUTO, workspace=None):
+                            n_fluids=None, variant=LBM_VARIANT_AUTO, group_bytes=0,
+                            workspace=None):
     """D3Q7 Knudsen solves of several lattices in one batch.  c_inits: None or a list of
-    float32 fields (entries may be None).  Returns (status, list of result dicts, list of
-    concentration fields or None, the variant run)."""
+    float32 fields (entries may be None); group_bytes as in lbm_flow_solve_batch.  Returns
+    (status, list of result dicts, list of concentration fields or None, schedule dict)."""
     for m, d in zip(fluids, pore_diams):
         _vol(m, torch.uint8, "fluid")
         _vol(d, torch.float64, "pore_diam")
@@ -464,13 +472,13 @@ def lbm_knudsen_solve_batch(fluids, pore_diams, tau_ref=1.0, d_ref_nm=60.0, voxe
     diams = V(*[d.data_ptr() for d in pore_diams])
     c_ptrs = V(*[c.data_ptr() for c in cs]) if want_c else None
     i_ptrs = V(*[0 if c0 is None else c0.data_ptr() for c0 in c_inits]) if c_inits else None
-    ran = C.c_int32(0)
+    sched = lbm_batch_sched(int(group_bytes))
     st = _check(load().lbm_knudsen_solve_batch(count, n.ctypes.data_as(C.c_void_p), masks, diams,
-                                               nf.ctypes.data_as(C.c_void_p), C.byref(p), res,
-                                               c_ptrs, i_ptrs, C.byref(ran), workspace.ptr,
+                                               nf.ctypes.data_as(C.c_void_p), C.byref(p),
+                                               C.byref(sched), res, c_ptrs, i_ptrs, workspace.ptr,
                                                workspace.nbytes, _stream()),
                 "lbm_knudsen_solve_batch")
-    return st, [_as_dict(r) for r in res], cs, ran.value
+    return st, [_as_dict(r) for r in res], cs, _as_dict(sched)
 
 
 def lbm_knudsen_step(workspace, steps):

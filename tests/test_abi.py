@@ -39,6 +39,7 @@ def test_struct_layouts_match(lib):
     for i, cls in enumerate(lib.STRUCTS):
         assert lib.lbm_sizeof(i) == C.sizeof(cls), cls.__name__
     assert lib.lbm_sizeof(99) == 0
+    assert len(lib.STRUCTS) == 10
 
 
 def test_version(lib):
@@ -160,7 +161,7 @@ def test_batch_sizes_and_checks(lib):
                                 a["fixed_steps"], a["check_every"], a["storage"], a["tol"],
                                 a["voxel_nm"], a["resume"], a["variant"], a["with_rho"],
                                 a["collision"])
-        return L.lbm_flow_solve_batch(count, n, masks, nf, C.byref(p), res, None, None, dummy,
+        return L.lbm_flow_solve_batch(count, n, masks, nf, C.byref(p), None, res, None, dummy,
                                       1 << 30, None)
 
     # binary16 / binary64 storage, resume, density planes, F_x = 0, tau <= 1/2, unknown
@@ -188,7 +189,7 @@ def test_knudsen_batch_sizes_and_checks(lib):
         a.update(kw)
         p = lib.lbm_knudsen_params(a["tau_ref"], 60.0, 1.5, a["c_in"], a["c_out"], 323.0, 0.016,
                                    10, 0, a["check_every"], a["resume"], 1e-7, a["variant"], 0)
-        return L.lbm_knudsen_solve_batch(count, n, ptrs, ptrs, nf, C.byref(p), res, None, None,
+        return L.lbm_knudsen_solve_batch(count, n, ptrs, ptrs, nf, C.byref(p), None, res, None,
                                          None, C.c_void_p(1), 1 << 30, None)
 
     for kw in (dict(resume=1), dict(c_out=1.0), dict(tau_ref=0.5), dict(variant=2),

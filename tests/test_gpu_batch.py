@@ -54,8 +54,8 @@ def test_fixed_steps_equal_single_solves(collision):
     kw = dict(tau=0.7, force=(1e-5, 2e-6, -1e-6), fixed_steps=333, check_every=50,
               collision=collision)
     say("fixed steps, collision", collision)
-    st, res, us, ran = lbm.lbm_flow_solve_batch(fluids, want_u=True, **kw)
-    assert st == lbm.LBM_OK and ran & E
+    st, res, us, sc = lbm.lbm_flow_solve_batch(fluids, want_u=True, **kw)
+    assert st == lbm.LBM_OK and sc["group_bytes_run"] in (-1, 128e6, 192e6, 256e6, 384e6)
     same(res, singles(fluids, **kw), us)
 
 
@@ -67,10 +67,13 @@ def test_graph_and_host_launches_agree(variant):
     fluids = ragged_batch()
     for k in (1, 2, 3, 4):
         kw = dict(tau=0.8, force=(1e-5, 0, 0), fixed_steps=k * 25, check_every=25)
-        _, a, ua, ra = lbm.lbm_flow_solve_batch(fluids, want_u=True, variant=variant, **kw)
+        # two groups (the first four lattices fit 2 MB, the fifth does not)
+        _, a, ua, ra = lbm.lbm_flow_solve_batch(fluids, want_u=True, variant=variant,
+                                                group_bytes=2_000_000, **kw)
         _, b, ub, rb = lbm.lbm_flow_solve_batch(fluids, want_u=True, variant=variant | NOGRAPH,
-                                                **kw)
-        assert ra == variant and rb == variant | NOGRAPH
+                                                group_bytes=2_000_000, **kw)
+        assert ra["variant"] == variant and rb["variant"] == variant | NOGRAPH
+        assert ra["groups"] == 2
         for l in range(len(fluids)):
             assert torch.equal(ua[l], ub[l]), (k, l)
             assert a[l]["k_lattice"] == b[l]["k_lattice"], (k, l)
@@ -123,9 +126,21 @@ def test_reconstructed_batch():
                                          rp["p_overlap"], rp["seed"])
         fluids.append(pore)
     kw = dict(tau=0.8, force=(1e-6, 0, 0), fixed_steps=300, check_every=100)
-    st, res, us, ran = lbm.lbm_flow_solve_batch(fluids, want_u=True, **kw)
-    say("reconstructed batch: variant", ran, "mlups", res[0]["mlups"])
+    st, res, us, sc = lbm.lbm_flow_solve_batch(fluids, want_u=True, **kw)
+    say("reconstructed batch: schedule", sc, "mlups", res[0]["mlups"])
     same(res, singles(fluids, **kw), us)
+
+
+@pytest.mark.parametrize("group_bytes", [-1, 1, 300_000, 2_000_000])
+def test_every_schedule_gives_the_same_state(group_bytes):
+    # one group, one lattice per group, and budgets in between, with retirement
+    fluids = ragged_batch() + [dev(W.slit(4, 7, 4, 5, axis=1)), dev(W.square_duct(6, 4))]
+    kw = dict(tau=0.9, force=(1e-6, 0, 0), max_steps=3000, check_every=100, tol=1e-5)
+    st, res, us, sc = lbm.lbm_flow_solve_batch(fluids, want_u=True, group_bytes=group_bytes, **kw)
+    ones = singles(fluids, **kw)
+    say("schedule", group_bytes, sc["groups"], "groups; steps", [r["steps"] for r in res])
+    assert sc["groups"] == {-1: 1, 1: len(fluids)}.get(group_bytes, sc["groups"])
+    same(res, ones, us)
 
 
 # ------------------------------------------------------------------ Knudsen
@@ -162,9 +177,9 @@ def kn_same(batch, ones, cs):
 def test_knudsen_fixed_steps_equal_single_solves():
     items = kn_batch()
     kw = dict(fixed_steps=333, check_every=50)
-    st, res, cs, ran = lbm.lbm_knudsen_solve_batch([i[0] for i in items], [i[1] for i in items],
-                                                   want_c=True, **KN, **kw)
-    assert st == lbm.LBM_OK and ran & E
+    st, res, cs, sc = lbm.lbm_knudsen_solve_batch([i[0] for i in items], [i[1] for i in items],
+                                                  want_c=True, **KN, **kw)
+    assert st == lbm.LBM_OK and sc["group_bytes_run"] in (-1, 128e6, 192e6, 256e6, 384e6)
     kn_same(res, kn_singles(items, **kw), cs)
 
 
@@ -173,10 +188,11 @@ def test_knudsen_graph_and_host_launches_agree(variant):
     items = kn_batch()
     f, d = [i[0] for i in items], [i[1] for i in items]
     for k in (1, 2, 3, 4, 5):
-        kw = dict(fixed_steps=k * 25, check_every=25)
-        _, a, ca, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, variant=variant, **KN, **kw)
+        kw = dict(fixed_steps=k * 25, check_every=25, group_bytes=500_000)
+        _, a, ca, sa = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, variant=variant, **KN, **kw)
         _, b, cb, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, variant=variant | NOGRAPH,
                                                   **KN, **kw)
+        assert sa["groups"] >= 2
         for l in range(len(items)):
             assert torch.equal(ca[l], cb[l]), (k, l)
             assert a[l]["Deff_lattice"] == b[l]["Deff_lattice"], (k, l)
@@ -196,9 +212,9 @@ def test_knudsen_retirement_and_warm_start():
           dev((np.float32(0.55) * items[3][2]).astype(np.float32))]
     kw = dict(max_steps=200_000, check_every=100, tol=1e-7)
     f, d = [i[0] for i in items], [i[1] for i in items]
-    for variant in (0, NOGRAPH):
+    for variant, gb in ((0, 0), (NOGRAPH, 0), (0, 1), (0, 12000)):
         st, res, cs, _ = lbm.lbm_knudsen_solve_batch(f, d, want_c=True, c_inits=c0,
-                                                     variant=variant, **KN, **kw)
+                                                     variant=variant, group_bytes=gb, **KN, **kw)
         ones = kn_singles(items, c_inits=c0, **kw)
         say("knudsen retire steps", [r["steps"] for r in res], [s["steps"] for s in ones])
         assert len({r["steps"] for r in res}) >= 3
