@@ -137,6 +137,129 @@ def roofline_512(lbm, W, steps):
                     "achieved": round(nf * BYTES_D3Q19 / (ms_mrt * 1e-3) / 1e9, 1)}}
 
 
+def batch_geometry(lbm, W, count):
+    """The first `count` reconstructions of the batch workload with their pore maps."""
+    import torch
+    fl, dm, nf = [], [], []
+    for rp in W.batch_params(W.BATCH["count"])[:count]:
+        pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                          rp["d_min"], rp["overlap_tol"], rp["p_overlap"],
+                                          rp["seed"])
+        fl.append(pore)
+        nf.append(rs["n_pore"])
+        dm.append(lbm.lbm_pore_diameter(pore, lbm.LBM_PSD_MIS))
+    torch.cuda.synchronize()
+    return fl, dm, nf
+
+
+def _kn_args(W):
+    b = W.BATCH
+    kp = b["knudsen"]
+    return dict(tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"], voxel_nm=b["voxel_nm"],
+                c_in=kp["c_in"], c_out=kp["c_out"], T=kp["T"], check_every=kp["check_every"])
+
+
+def batch_throughput(lbm, W, flow_steps, kn_steps):
+    """The whole batch workload for a fixed number of steps: the batched solves (autotuned
+    schedule, graphs) against the same lattices solved one after the other."""
+    import torch
+    fl, dm, nf = batch_geometry(lbm, W, W.BATCH["count"])
+    fp = W.BATCH["flow"]
+    ka = _kn_args(W)
+    out = {"lattices": len(fl), "n_fluid": int(sum(nf)), "flow_steps": flow_steps,
+           "knudsen_steps": kn_steps}
+    t0 = time.perf_counter()
+    _, res, _, sc = lbm.lbm_flow_solve_batch(fl, tau=fp["tau"], force=fp["force"],
+                                             fixed_steps=flow_steps,
+                                             check_every=fp["check_every"], n_fluids=nf)
+    torch.cuda.synchronize()
+    out["flow_batched"] = {"mlups": round(res[0]["mlups"], 1),
+                           "wall_s": round(time.perf_counter() - t0, 3),
+                           "group_bytes": sc["group_bytes_run"], "groups": sc["groups"]}
+    t0 = time.perf_counter()
+    sw = 0.0
+    for f, n in zip(fl, nf):
+        sw += lbm.lbm_flow_solve(f, tau=fp["tau"], force=fp["force"], fixed_steps=flow_steps,
+                                 check_every=fp["check_every"], n_fluid=n)["sweep_ms"]
+    torch.cuda.synchronize()
+    out["flow_single"] = {"mlups": round(sum(nf) * flow_steps / (sw * 1e3), 1),
+                          "wall_s": round(time.perf_counter() - t0, 3)}
+    t0 = time.perf_counter()
+    _, res, _, sc = lbm.lbm_knudsen_solve_batch(fl, dm, fixed_steps=kn_steps, n_fluids=nf, **ka)
+    torch.cuda.synchronize()
+    out["knudsen_batched"] = {"mlups": round(res[0]["mlups"], 1),
+                              "wall_s": round(time.perf_counter() - t0, 3),
+                              "group_bytes": sc["group_bytes_run"], "groups": sc["groups"]}
+    t0 = time.perf_counter()
+    sw = 0.0
+    for f, d, n in zip(fl, dm, nf):
+        sw += lbm.lbm_knudsen_solve(f, d, fixed_steps=kn_steps, n_fluid=n, want_planes=False,
+                                    **ka)["sweep_ms"]
+    torch.cuda.synchronize()
+    out["knudsen_single"] = {"mlups": round(sum(nf) * kn_steps / (sw * 1e3), 1),
+                             "wall_s": round(time.perf_counter() - t0, 3)}
+    del fl, dm
+    torch.cuda.empty_cache()
+    return out
+
+
+def batch_converge(lbm, W, count, net):
+    """Time to the converged k and D_eff (residual 1e-7) of the first `count` lattices of
+    the batch workload: plain (one solve after the other, from rest) against batched
+    (autotuned groups, graphs) with the Knudsen solves warm-started by the network."""
+    import torch
+    from paper_1410_1921_amd import warmstart as WS
+    fl, dm, nf = batch_geometry(lbm, W, count)
+    fp = W.BATCH["flow"]
+    ka = _kn_args(W)
+    kp = W.BATCH["knudsen"]
+    fkw = dict(tau=fp["tau"], force=fp["force"], max_steps=fp["max_steps"],
+               check_every=fp["check_every"], tol=fp["tol"], voxel_nm=W.BATCH["voxel_nm"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_f = [lbm.lbm_flow_solve(f, n_fluid=n, **fkw) for f, n in zip(fl, nf)]
+    torch.cuda.synchronize()
+    t_pf = time.perf_counter() - t0
+    plain_k = [lbm.lbm_knudsen_solve(f, d, n_fluid=n, max_steps=kp["max_steps"], tol=kp["tol"],
+                                     want_planes=False, **ka) for f, d, n in zip(fl, dm, nf)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"batch converge: plain {t_plain:.1f} s (flow {t_pf:.1f} s)")
+    t0 = time.perf_counter()
+    _, bf, _, sf = lbm.lbm_flow_solve_batch(fl, n_fluids=nf, **fkw)
+    torch.cuda.synchronize()
+    t_bf = time.perf_counter() - t0
+    c0 = [WS.predict(net, f, d)[1].contiguous() for f, d in zip(fl, dm)]
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0 - t_bf
+    _, bk, _, sk = lbm.lbm_knudsen_solve_batch(fl, dm, n_fluids=nf, max_steps=kp["max_steps"],
+                                               tol=kp["tol"], c_inits=c0, **ka)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch converge: batched + warm {t_batch:.1f} s (flow {t_bf:.1f} s)")
+    # relative differences over the lattices with a pore path along x (their flow
+    # converges); the others have k and D_eff at round-off level
+    perc = [i for i, p in enumerate(plain_f) if p["converged"]]
+    dk = [abs(bf[i]["k_lattice"] / plain_f[i]["k_lattice"] - 1) for i in perc]
+    dd = [abs(bk[i]["Deff_lattice"] / plain_k[i]["Deff_lattice"] - 1) for i in perc]
+    return {"lattices": count, "n_fluid": int(sum(nf)),
+            "plain_s": round(t_plain, 2), "plain_flow_s": round(t_pf, 2),
+            "batched_warm_s": round(t_batch, 2), "batched_flow_s": round(t_bf, 2),
+            "inference_s": round(t_inf, 2), "speedup": round(t_plain / t_batch, 3),
+            "flow_steps_plain": sum(p["steps"] for p in plain_f),
+            "flow_steps_batched": sum(b["steps"] for b in bf),
+            "knudsen_steps_plain": sum(p["steps"] for p in plain_k),
+            "knudsen_steps_warm": sum(b["steps"] for b in bk),
+            "converged": [sum(p["converged"] for p in plain_f), sum(b["converged"] for b in bf),
+                          sum(p["converged"] for p in plain_k), sum(b["converged"] for b in bk)],
+            "percolating": len(perc),
+            "k_rel_diff_max": max(dk) if dk else 0.0,
+            "deff_rel_diff_max": max(dd) if dd else 0.0,
+            "deff_plain": [p["Deff_lattice"] for p in plain_k],
+            "deff_warm": [b["Deff_lattice"] for b in bk],
+            "schedule": {"flow": sf, "knudsen": sk}}
+
+
 def knudsen_sweeps(lbm, w, steps):
     """`steps` D3Q7 sweeps on the workload's geometry: mean launch time from the
     library's HIP events."""
@@ -207,7 +330,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="recon128_eps0.40_d12_mis_ch4_400K")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-512", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started pipeline")
@@ -215,6 +338,12 @@ def main():
     ap.add_argument("--only-512", action="store_true",
                     help="only the 512^3 sweep roofline, after 2 GiB copies by the library's "
                          "copy kernel that calibrate the HBM byte counters (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload leg")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="fixed steps of each lattice in the batch-workload leg")
+    ap.add_argument("--batch-converge", type=int, default=0, metavar="COUNT",
+                    help="only the time to converged solutions of the first COUNT lattices of "
+                         "the batch workload, plain against batched + warm-started")
     ap.add_argument("--only-knudsen", type=int, default=0, metavar="STEPS",
                     help="only the geometry stages and STEPS Knudsen sweeps of the workload, "
                          "after the same copy calibration (profiling runs)")
@@ -236,6 +365,12 @@ def main():
         print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
                           "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
                           "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
+        return
+    if args.batch_converge:
+        from paper_1410_1921_amd import warmstart as WS
+        print(json.dumps({"batch_converge": batch_converge(lbm, W, args.batch_converge,
+                                                           WS.load_network()),
+                          "workload": W.BATCH["name"]}), flush=True)
         return
     w = W.WORKLOADS[args.workload]
     if args.only_knudsen:
@@ -316,6 +451,10 @@ def main():
             "deff_rel_diff": abs(wr["knudsen"]["Deff_lattice"] / last["knudsen"]["Deff_lattice"] - 1),
             "network": "U-Net 16-128 ch, trained on 400 solves of 96^3 geometries",
             "applied_to": "Knudsen C (the flow starts from rest)"}
+    if not args.no_batch:
+        log("batch workload")
+        out["batch"] = batch_throughput(lbm, W, args.batch_steps, args.batch_steps)
+        out["batch"]["workload"] = W.BATCH["name"]
     if not args.no_512:
         log("512^3 roofline")
         out["roofline_512"] = roofline_512(lbm, W, args.roofline_steps)

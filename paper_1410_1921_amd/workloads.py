@@ -62,6 +62,16 @@ def batch_params(count=150, seed=4):
     return out
 
 
+# The batch of uneven reconstructions (parameter draws of batch_params), 2 nm voxels,
+# flow and Knudsen settings as in the 128^3 methane workload, binary32 state.
+BATCH = dict(
+    name="batch150_edges64-160_eps0.2-0.5", count=150, voxel_nm=2.0,
+    flow=dict(tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=400_000, check_every=100, tol=1e-7),
+    knudsen=dict(tau_ref=1.0, d_ref_nm=60.0, c_in=1.0, c_out=0.0, T=400.0, check_every=100,
+                 max_steps=4_000_000, tol=1e-7),
+)
+
+
 # The learned warm start: 96^3 reconstructions drawn with the batch's parameter laws
 # (porosity U[0.2, 0.5], mean diameter U[6, 20] voxels with std = mean/4, overlap
 # tolerance U[0, 1]); training seeds 5000-5399, held-out seeds 6000-6049.  Flow and
