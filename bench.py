@@ -341,6 +341,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch-workload leg")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="fixed steps of each lattice in the batch-workload leg")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only the batch-workload leg (profiling runs)")
     ap.add_argument("--batch-converge", type=int, default=0, metavar="COUNT",
                     help="only the time to converged solutions of the first COUNT lattices of "
                          "the batch workload, plain against batched + warm-started")
@@ -365,6 +367,10 @@ def main():
         print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
                           "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
                           "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
+        return
+    if args.only_batch:
+        print(json.dumps({"batch": batch_throughput(lbm, W, args.batch_steps, args.batch_steps),
+                          "workload": W.BATCH["name"]}), flush=True)
         return
     if args.batch_converge:
         from paper_1410_1921_amd import warmstart as WS
