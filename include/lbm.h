@@ -82,8 +82,8 @@ typedef int32_t lbm_status;
  *   LBM_VARIANT_REMAP   workgroups ordered so that each XCD walks one contiguous region
  *   LBM_VARIANT_NTSTORE non-temporal (streaming) population stores
  * All variants compute identical results; they differ only in speed.  Any other bit
- * (2 included) is rejected with LBM_E_INVAL.  A batched solve with no explicit variant
- * times the candidates on its first steps and keeps the fastest. */
+ * (2 included) is rejected with LBM_E_INVAL.  A batched solve without
+ * LBM_VARIANT_EXPLICIT chooses the variant of each of its groups from the group's size. */
 #define LBM_VARIANT_AUTO 0
 #define LBM_VARIANT_EXPLICIT 1
 #define LBM_VARIANT_REMAP 4
