@@ -27,8 +27,42 @@ BYTES_D3Q19 = 152  # 19 loads + 19 stores of binary32 per fluid-node update
 BYTES_D3Q7 = 60    # 7 loads + 7 stores of binary32 + 1/tau_g
 
 
+# HBM bytes per launch from the committed counter runs (profiles/k_sweep7_recon128_methane.md,
+# profiles/k_sweep19_recon512.md): FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by
+# what the same counters read for the library's copy kernel on 2 GiB buffers (FETCH_SIZE
+# reports half of the bytes read, WRITE_SIZE all of the bytes written).  A figure holds
+# only while the kernel's sources are those that were profiled (hash of the files).
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+COUNTERS = {
+    "k_sweep7<false, false>": dict(
+        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15335.1, write_kib=22966.8,
+        files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
+               "paper_1410_1921_amd/csrc/common.hip"), sha="d8c126f70eb399be"),
+    "k_sweep19<StoreF32, false, true, false>": dict(
+        workload="recon512_eps0.25_d16", fetch_kib=2141860.4, write_kib=2490368.6,
+        files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
+               "paper_1410_1921_amd/csrc/common.hip"), sha="50b1dbb464f0441c"),
+}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def traffic_gb(kernel, workload):
+    """Calibrated HBM bytes per launch (GB) of `kernel` on `workload` from the committed
+    counter runs, or None when there are none or the kernel's sources have changed."""
+    import hashlib
+    c = COUNTERS.get(kernel)
+    if c is None or c["workload"] != workload:
+        return None
+    h = hashlib.sha256()
+    for f in c["files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != c["sha"]:
+        return None
+    return round((c["fetch_kib"] * FETCH_FACTOR + c["write_kib"] * WRITE_FACTOR) * 1024 / 1e9, 5)
 
 
 def pipeline(lbm, W, w, net=None):
@@ -127,13 +161,16 @@ def roofline_512(lbm, W, steps):
     ms_mrt = e0.elapsed_time(e1) / steps
     del r, pore
     torch.cuda.empty_cache()
-    return {"kernel": "k_sweep19<StoreF32, false, true>", "workload": w["name"], "n_fluid": nf,
+    name = "k_sweep19<StoreF32, false, true, false>"
+    return {"kernel": name, "workload": w["name"], "n_fluid": nf,
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": ms,
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_gb(name, w["name"]),
+            "traffic_unit": "GB per launch", "ms_per_launch": ms,
             "mlups": nf / (ms * 1e3),
             "fp16": {"ms_per_launch": ms16, "mlups": nf / (ms16 * 1e3),
                      "achieved": round(nf * 84 / (ms16 * 1e-3) / 1e9, 1)},
-            "mrt": {"ms_per_launch": ms_mrt, "mlups": nf / (ms_mrt * 1e3),
+            "mrt": {"kernel": "k_sweep19<StoreF32, false, true, true>",
+                    "ms_per_launch": ms_mrt, "mlups": nf / (ms_mrt * 1e3),
                     "achieved": round(nf * BYTES_D3Q19 / (ms_mrt * 1e-3) / 1e9, 1)}}
 
 
@@ -412,10 +449,12 @@ def main():
     if kn_ms >= fl_ms:
         name, per, bpu, ms = "k_sweep7<false, false>", kn_ms / kn_n, BYTES_D3Q7, kn_ms
     else:
-        name, per, bpu, ms = "k_sweep19<StoreF32, false, false>", fl_ms / fl_n, BYTES_D3Q19, fl_ms
+        name, per, bpu, ms = ("k_sweep19<StoreF32, false, false, false>", fl_ms / fl_n,
+                              BYTES_D3Q19, fl_ms)
     achieved = nf * bpu / (per * 1e-3) / 1e9
     roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_gb(name, w["name"]), "traffic_unit": "GB per launch",
             "bytes_per_update": bpu, "n_fluid": nf, "ms_per_launch": per,
             "share_of_step": round(ms / (wall * 1e3), 4)}
     out = {
