@@ -866,6 +866,162 @@ void orc_knudsen_update_node(const uint8_t *nb_kind, const double *nb_g, double 
 }
 
 /* ======================================================================
+ * Section 3.2 (Eq. 10) on the paper's own D3Q19 lattice: g_eq,i = a_i C with
+ * a_0 = 1/3, a_1..6 = 1/18, a_7..18 = 1/36 (the printed "C/a_i" read as a_i C),
+ * velocities as in the flow lattice, D = (tau_g - 1/2)/3 (c_s^2 = 1/3).  The
+ * same boundaries as the D3Q7 solve: bounce-back at solid links, periodic in y
+ * and z, ghost planes at x = -1 and x = nx holding a_i C_in and a_i C_out (a
+ * population arriving from beyond an x face takes the ghost's value whatever
+ * its y, z offset, the ghost planes being uniform).
+ * ====================================================================== */
+void orc_collide19_diff(const double *gin, double tau, double *gout, double *conc) {
+    double c = 0.0;
+    for (int i = 0; i < 19; i++) c += gin[i];
+    for (int i = 0; i < 19; i++) gout[i] = gin[i] - (gin[i] - w19(i) * c) / tau;
+    if (conc) *conc = c;
+}
+
+/* initial g = a_i C (C_init planar [N^3], zero when null) */
+void orc_diffusion19_init(int nx, int ny, int nz, const uint8_t *fluid, const double *c_init,
+                          double *g) {
+    int64_t nvox = (int64_t)nx * ny * nz;
+    for (int64_t v = 0; v < nvox; v++)
+        for (int i = 0; i < 19; i++)
+            g[19 * v + i] = (fluid[v] && c_init) ? w19(i) * c_init[v] : 0.0;
+}
+
+/*
+ * The D3Q19 diffusion solve, as orc_knudsen_solve (same checks, outputs and
+ * Eq. 14 reading).  The net flux into the outlet ghost plane is, over the
+ * fluid nodes at x = nx - 1, the sum of their post-collision populations with
+ * e_x = +1 less the ghost's populations with e_x = -1 arriving there (each
+ * a_i C_out; the five of them weigh 1/6); the inlet likewise.  plane_flux:
+ * over the links crossing x - 1/2 (the five directions with e_x = +1) whose
+ * two ends are fluid (ghost planes count as fluid), g_i(left) - g_opp(i)(right).
+ */
+int orc_diffusion19_solve(int nx, int ny, int nz, const uint8_t *fluid, const double *tau_g,
+                          double c_in, double c_outv, int64_t max_steps, int64_t fixed_steps,
+                          int check_every, double tol, const double *c_prev0, double *g,
+                          double *c_out, double *plane_flux, double *out) {
+    if (check_every < 1) return ORC_E_INVAL;
+    int64_t nvox = (int64_t)nx * ny * nz;
+    for (int64_t v = 0; v < nvox; v++)
+        if (fluid[v] && !(tau_g[v] > 0.5)) return ORC_E_INVAL;
+    double *g0 = g;
+    double *h = (double *)malloc((size_t)nvox * 19 * sizeof(double));
+    double *hbuf = h;
+    double *cprev = (double *)calloc((size_t)nvox, sizeof(double));
+    double *ccur = (double *)calloc((size_t)nvox, sizeof(double));
+    double *pl = (double *)calloc((size_t)nz * 5, sizeof(double));
+    if (!h || !cprev || !ccur || !pl) { free(h); free(cprev); free(ccur); free(pl); return ORC_E_NOMEM; }
+    if (c_prev0) memcpy(cprev, c_prev0, (size_t)nvox * sizeof(double));
+    const double a_side = 1.0 / 6.0; /* the five populations with e_x = +1 (or -1) together */
+    int64_t limit = fixed_steps > 0 ? fixed_steps : max_steps;
+    double resid = INFINITY, sums[5] = {0, 0, 0, 0, 0};
+    int status = ORC_W_NOT_CONVERGED, diverged = 0;
+    int64_t t = 0;
+    while (t < limit) {
+        t++;
+        int check = (t % check_every == 0) || (t == limit);
+        memset(pl, 0, (size_t)nz * 5 * sizeof(double));
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                for (int x = 0; x < nx; x++) {
+                    int64_t v = vidx(x, y, z, nx, ny);
+                    if (!fluid[v]) {
+                        for (int i = 0; i < 19; i++) h[19 * v + i] = 0.0;
+                        continue;
+                    }
+                    double gin[19], conc;
+                    for (int i = 0; i < 19; i++) {
+                        int sx = x - E19[i][0];
+                        if (sx < 0) { gin[i] = w19(i) * c_in; continue; }
+                        if (sx >= nx) { gin[i] = w19(i) * c_outv; continue; }
+                        int64_t s = vidx(sx, wrap(y - E19[i][1], ny), wrap(z - E19[i][2], nz), nx, ny);
+                        gin[i] = fluid[s] ? g[19 * s + i] : g[19 * v + opp19(i)];
+                    }
+                    orc_collide19_diff(gin, tau_g[v], h + 19 * v, &conc);
+                    if (check) {
+                        ccur[v] = conc;
+                        pl[5 * z + 0] += (conc - cprev[v]) * (conc - cprev[v]);
+                        pl[5 * z + 1] += conc * conc;
+                        double plus = 0.0, minus = 0.0;
+                        for (int i = 1; i < 19; i++) {
+                            if (E19[i][0] == 1) plus += h[19 * v + i];
+                            if (E19[i][0] == -1) minus += h[19 * v + i];
+                        }
+                        if (x == nx - 1) pl[5 * z + 2] += plus - a_side * c_outv;
+                        if (x == 0) pl[5 * z + 3] += a_side * c_in - minus;
+                        pl[5 * z + 4] += conc;
+                    }
+                }
+        double *tmp = g; g = h; h = tmp;
+        if (check) {
+            for (int k = 0; k < 5; k++) sums[k] = 0.0;
+            for (int z = 0; z < nz; z++) for (int k = 0; k < 5; k++) sums[k] += pl[5 * z + k];
+            if (!isfinite(sums[0]) || !isfinite(sums[1]) || !isfinite(sums[2])) { diverged = 1; break; }
+            if (t % check_every == 0) {
+                resid = sqrt(sums[0]) / ((double)check_every * sqrt(sums[1]));
+                memcpy(cprev, ccur, (size_t)nvox * sizeof(double));
+                if (fixed_steps <= 0 && resid < tol) { status = ORC_OK; break; }
+            }
+        }
+    }
+    if (g != g0) memcpy(g0, g, (size_t)nvox * 19 * sizeof(double));
+    if (fixed_steps > 0) status = ORC_OK;
+    if (c_out) for (int64_t v = 0; v < nvox; v++) c_out[v] = fluid[v] ? ccur[v] : 0.0;
+    if (plane_flux) {
+        for (int px = 0; px <= nx; px++) {
+            double s = 0.0;
+            for (int z = 0; z < nz; z++)
+                for (int y = 0; y < ny; y++) {
+                    int right = px; /* the right end at (px, y, z) */
+                    int rf = right >= nx ? 1 : fluid[vidx(right, y, z, nx, ny)];
+                    if (!rf) continue;
+                    for (int i = 1; i < 19; i++) {
+                        if (E19[i][0] != 1) continue;
+                        int left = px - 1, ly = wrap(y - E19[i][1], ny), lz = wrap(z - E19[i][2], nz);
+                        int lf = left < 0 ? 1 : fluid[vidx(left, ly, lz, nx, ny)];
+                        if (!lf) continue;
+                        double fwd = left < 0 ? w19(i) * c_in : g[19 * vidx(left, ly, lz, nx, ny) + i];
+                        double bwd = right >= nx ? w19(opp19(i)) * c_outv
+                                                 : g[19 * vidx(right, y, z, nx, ny) + opp19(i)];
+                        s += fwd - bwd;
+                    }
+                }
+            plane_flux[px] = s;
+        }
+    }
+    out[0] = (double)t;
+    out[1] = sums[2] / ((double)ny * nz) * (double)(nx + 1) / (c_in - c_outv);
+    out[2] = resid;
+    out[3] = sums[2];
+    out[4] = sums[3];
+    out[5] = sums[4];
+    out[6] = status == ORC_OK ? 1.0 : 0.0;
+    free(hbuf); free(cprev); free(ccur); free(pl);
+    if (diverged) return ORC_E_DIVERGED;
+    return status;
+}
+
+/* One node's D3Q19 diffusion update from its neighbourhood (nb_kind, nb_g as in
+ * orc_knudsen_update_node with 19 rows of 19). */
+void orc_diffusion19_update_node(const uint8_t *nb_kind, const double *nb_g, double tau,
+                                 double c_in, double c_outv, double *gout, double *conc) {
+    double gin[19];
+    for (int i = 0; i < 19; i++) {
+        switch (nb_kind[i]) {
+        case 0: gin[i] = nb_g[19 * i + i]; break;
+        case 1: gin[i] = nb_g[opp19(i)]; break;
+        case 2: gin[i] = w19(i) * c_in; break;
+        default: gin[i] = w19(i) * c_outv; break;
+        }
+    }
+    orc_collide19_diff(gin, tau, gout, conc);
+}
+
+/* ======================================================================
  * Eq. 11: Knudsen diffusivity of a pore of diameter d (m), gas of molar mass
  * M (kg/mol) at temperature T (K); R = 8.314462618 J/(mol K).
  * ====================================================================== */

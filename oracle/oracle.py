@@ -103,6 +103,14 @@ def lib():
     L.orc_knudsen_update_node.argtypes = [_u8p, _f64p, C.c_double, C.c_double, C.c_double, _f64p,
                                           C.POINTER(C.c_double)]
     L.orc_knudsen_update_node.restype = None
+    L.orc_collide19_diff.argtypes = [_f64p, C.c_double, _f64p, C.POINTER(C.c_double)]
+    L.orc_collide19_diff.restype = None
+    L.orc_diffusion19_init.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, _nullable(_f64p), _f64p]
+    L.orc_diffusion19_init.restype = None
+    L.orc_diffusion19_solve.argtypes = L.orc_knudsen_solve.argtypes
+    L.orc_diffusion19_solve.restype = C.c_int
+    L.orc_diffusion19_update_node.argtypes = L.orc_knudsen_update_node.argtypes
+    L.orc_diffusion19_update_node.restype = None
     for name in ("orc_knudsen_diffusivity", "orc_mean_free_path"):
         getattr(L, name).restype = C.c_double
     L.orc_knudsen_diffusivity.argtypes = [C.c_double] * 3
@@ -324,6 +332,54 @@ def knudsen_solve(fluid, tau_g_field, c_in=1.0, c_out=0.0, max_steps=1_000_000, 
     return {"status": st, "steps": int(out[0]), "Deff_lattice": out[1], "residual": out[2],
             "phi_out": out[3], "phi_in": out[4], "sum_c": out[5], "converged": bool(out[6]),
             "c": c, "plane_flux": planes, "g": g}
+
+
+def diffusion19_init(fluid, c_init=None):
+    fluid = np.ascontiguousarray(fluid, np.uint8)
+    nz, ny, nx = fluid.shape
+    g = np.zeros(fluid.shape + (19,), np.float64)
+    ci = None if c_init is None else np.ascontiguousarray(c_init, np.float64)
+    lib().orc_diffusion19_init(nx, ny, nz, fluid, ci, g)
+    return g
+
+
+def diffusion19_solve(fluid, tau_g_field, c_in=1.0, c_out=0.0, max_steps=1_000_000,
+                      fixed_steps=0, check_every=100, tol=1e-7, g=None, c_prev0=None,
+                      want_c=True, want_planes=True):
+    """The mass-transport solve on the D3Q19 lattice (Section 3.2); same returns as
+    knudsen_solve."""
+    fluid = np.ascontiguousarray(fluid, np.uint8)
+    nz, ny, nx = fluid.shape
+    if g is None:
+        g = diffusion19_init(fluid)
+    tg = np.ascontiguousarray(np.broadcast_to(tau_g_field, fluid.shape), np.float64)
+    c = np.zeros(fluid.shape, np.float64) if want_c else None
+    planes = np.zeros(nx + 1, np.float64) if want_planes else None
+    out = np.zeros(7, np.float64)
+    cp = None if c_prev0 is None else np.ascontiguousarray(c_prev0, np.float64)
+    st = lib().orc_diffusion19_solve(nx, ny, nz, fluid, tg, c_in, c_out, max_steps, fixed_steps,
+                                     check_every, tol, cp, g, c, planes, out)
+    if st < 0:
+        raise OracleError(st, "diffusion19_solve")
+    return {"status": st, "steps": int(out[0]), "Deff_lattice": out[1], "residual": out[2],
+            "phi_out": out[3], "phi_in": out[4], "sum_c": out[5], "converged": bool(out[6]),
+            "c": c, "plane_flux": planes, "g": g}
+
+
+def collide19_diff(gin, tau):
+    gout = np.zeros(19)
+    conc = C.c_double(0.0)
+    lib().orc_collide19_diff(np.ascontiguousarray(gin, np.float64), tau, gout, C.byref(conc))
+    return gout, conc.value
+
+
+def diffusion19_update_node(nb_kind, nb_g, tau, c_in, c_out):
+    gout = np.zeros(19)
+    conc = C.c_double(0.0)
+    lib().orc_diffusion19_update_node(np.ascontiguousarray(nb_kind, np.uint8),
+                                      np.ascontiguousarray(nb_g, np.float64), tau, c_in, c_out,
+                                      gout, C.byref(conc))
+    return gout, conc.value
 
 
 def collide7(gin, tau):
