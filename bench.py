@@ -25,6 +25,7 @@ METRIC = "MLUPS & % HBM roofline; time-to-converged k and D_eff, plain vs warm-s
 HBM_PEAK_GBS = 8000.0
 BYTES_D3Q19 = 152  # 19 loads + 19 stores of binary32 per fluid-node update
 BYTES_D3Q7 = 60    # 7 loads + 7 stores of binary32 + 1/tau_g
+BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_g
 
 
 # HBM bytes per launch from the committed counter runs (profiles/k_sweep7_recon128_methane.md,
@@ -316,6 +317,29 @@ def knudsen_sweeps(lbm, w, steps):
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def diffusion19_sweeps(lbm, w, steps):
+    """`steps` sweeps of the paper's D3Q19 mass-transport lattice on the workload's
+    geometry (mean launch time from the library's HIP events), beside the D3Q7 sweep."""
+    rp, kp = w["recon"], w["knudsen"]
+    pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                      rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    method = lbm.LBM_PSD_MIS if rp["psd"] == "mis" else lbm.LBM_PSD_CHORD13
+    diam = lbm.lbm_pore_diameter(pore, method)
+    kw = dict(tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"], voxel_nm=w["voxel_nm"],
+              c_in=kp["c_in"], c_out=kp["c_out"], T=kp["T"], fixed_steps=steps,
+              check_every=kp["check_every"], n_fluid=rs["n_pore"], want_planes=False)
+    out = {"workload": w["name"], "n_fluid": rs["n_pore"], "steps": steps}
+    for name, lat, bpu in (("d3q19", lbm.LBM_LATTICE_D3Q19, BYTES_D3Q19D),
+                           ("d3q7", lbm.LBM_LATTICE_D3Q7, BYTES_D3Q7)):
+        kr = lbm.lbm_knudsen_solve(pore, diam, lattice=lat, **kw)
+        per = kr["sweep_ms"] / kr["steps"]
+        out[name] = {"ms_per_launch": per, "mlups": round(kr["mlups"], 1),
+                     "achieved_gbs": round(kr["n_fluid"] * bpu / (per * 1e-3) / 1e9, 1),
+                     "bytes_per_update": bpu}
+    out["d3q19"]["kernel"] = "k_sweep19d<false, false>"
+    return out
+
+
 def copy_ceiling(lbm, nbytes=1 << 30, reps=5):
     """Attainable HBM bandwidth: the library's streaming copy kernel on `nbytes` buffers,
     read + write bytes per second from HIP events on the current stream (best of reps)."""
@@ -500,6 +524,8 @@ def main():
         log("batch workload")
         out["batch"] = batch_throughput(lbm, W, args.batch_steps, args.batch_steps)
         out["batch"]["workload"] = W.BATCH["name"]
+    log("D3Q19 mass-transport sweeps")
+    out["diffusion_d3q19"] = diffusion19_sweeps(lbm, w, 2000)
     if not args.no_512:
         log("512^3 roofline")
         out["roofline_512"] = roofline_512(lbm, W, args.roofline_steps)

@@ -61,6 +61,11 @@ typedef int32_t lbm_status;
 #define LBM_WS_KNUDSEN 3
 #define LBM_WS_FLOW_FP16 4 /* flow solve, binary16 storage */
 #define LBM_WS_FLOW_FP64 5 /* flow solve, binary64 storage */
+#define LBM_WS_KNUDSEN_D3Q19 6 /* mass-transport solve on the D3Q19 lattice */
+
+/* mass-transport lattice (the `lattice` field of lbm_knudsen_params) */
+#define LBM_LATTICE_D3Q7 0  /* rest weight 1/4, face weights 1/8, c_s^2 = 1/4 */
+#define LBM_LATTICE_D3Q19 1 /* the paper's: a_i = 1/3, 1/18, 1/36, c_s^2 = 1/3 */
 
 /* population storage of the flow solve: the offsets f_i - w_i are stored in */
 #define LBM_STORE_FP32 0 /* binary32, collision in binary32 */
@@ -309,12 +314,15 @@ lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t
                                 void *stream);
 
 /* ------------------------------------------------------------------------------
- * Knudsen mass-transport solve (Section 3.2, Eq. 10, on the D3Q7 lattice with rest
- * weight 1/4 and face weights 1/8, g_eq = w_i C, c_s^2 = 1/4).  Local relaxation
+ * Knudsen mass-transport solve (Section 3.2, Eq. 10) on the D3Q7 lattice (rest weight
+ * 1/4, face weights 1/8, c_s^2 = 1/4) or the paper's D3Q19 lattice (a_i = 1/3, 1/18,
+ * 1/36, c_s^2 = 1/3, velocities as in the flow solve), g_eq = w_i C.  Local relaxation
  * time from the local pore diameter (Eq. 12): tau_g = (d_p/d_ref)(tau_ref - 1/2) +
  * 1/2 with d_ref = d_ref_nm / voxel_nm.  Boundaries (Section 3.3): bounce-back at
  * solid links, periodic in y and z, equilibrium ghost planes w_i C_in at x = -1 and
- * w_i C_out at x = nx.  Starts from C = c_init (or 0); checks as in the flow solve
+ * w_i C_out at x = nx (every population arriving from beyond an x face, diagonal ones
+ * included, takes the ghost's value).  Starts from C = c_init (or 0); checks as in the
+ * flow solve
  * with C as the field.  Eq. 14 on the lattice: D_eff = Phi_out / (ny nz) *
  * (nx + 1)/(C_in - C_out), Phi_out the net flux into the outlet ghost plane of the
  * last step's post-collision state.  Reported: D_eff / D_K,ref with D_K,ref =
@@ -327,9 +335,11 @@ lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t
  * c_field      : device float[N^3] out (0 at solids), nullable.
  * c_init       : device float[N^3] in, nullable.
  * plane_flux_h : host double[nx + 1] out, nullable: Phi(x - 1/2), x = 0..nx, over
- *                links with both ends fluid (ghost planes count as fluid).
- * workspace    : LBM_WS_KNUDSEN bytes.
- * Errors: LBM_E_INVAL (tau_g <= 1/2 anywhere, C_in == C_out, ...), LBM_E_NOMEM,
+ *                links with both ends fluid (ghost planes count as fluid; on D3Q19
+ *                the five links with e_x = +1 per node).
+ * workspace    : LBM_WS_KNUDSEN (LBM_WS_KNUDSEN_D3Q19 for that lattice) bytes.
+ * Errors: LBM_E_INVAL (tau_g <= 1/2 anywhere, C_in == C_out, unknown lattice, a resume
+ * with another lattice, ...), LBM_E_NOMEM,
  * LBM_E_DIVERGED, LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
@@ -344,7 +354,7 @@ typedef struct {
     int32_t resume;
     double tol;
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
-    int32_t reserved;
+    int32_t lattice;      /* LBM_LATTICE_D3Q7 (0) or LBM_LATTICE_D3Q19 */
 } lbm_knudsen_params;
 
 typedef struct {
@@ -354,7 +364,8 @@ typedef struct {
     double tortuosity, tortuosity_local; /* eps D_ref/D_eff and eps <D_L>/D_eff */
     double phi_in, phi_out, flux_spread; /* spread = (max - min)/mean of plane fluxes */
     double residual, sum_c;
-    double sweep_ms, mlups, gbps;        /* gbps with 60 algorithmic bytes per update */
+    double sweep_ms, mlups, gbps;        /* gbps with 60 (D3Q7) or 156 (D3Q19) algorithmic
+                                            bytes per update */
 } lbm_knudsen_result;
 
 lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid, const double *pore_diam,
@@ -364,8 +375,9 @@ lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid, const dou
 
 lbm_status lbm_knudsen_step(void *workspace, size_t ws_bytes, int64_t steps, void *stream);
 
-/* g_h[count][7] receives the stored post-collision g_i; tau_h[count] the node's
- * tau_g as used (binary32 widened), fluid_h as in lbm_flow_sample. */
+/* g_h[count][q] (q = 7, or 19 for a D3Q19 state) receives the post-collision g_i (the
+ * stored deviation plus w_i C_ref of its frame); tau_h[count] the node's tau_g as used
+ * (binary32 widened), fluid_h as in lbm_flow_sample.  count <= 65536. */
 lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const int64_t *vox_h,
                               int64_t count, double *g_h, double *tau_h, uint8_t *fluid_h,
                               void *stream);
@@ -384,7 +396,7 @@ lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const int64_t *v
  * fluid     : host array of count device pointers, uint8[nz][ny][nx] each.
  * pore_diam : host array of count device pointers, double[nz][ny][nx] each (voxels).
  * nf_h      : host int64[count] fluid-node counts (each >= 1; checked).
- * p         : one parameter set; resume must be 0.
+ * p         : one parameter set; resume must be 0, lattice LBM_LATTICE_D3Q7.
  * sched     : nullable, in/out (lbm_batch_sched); null = autotuned budget.
  * r_h       : host lbm_knudsen_result[count] out (sweep_ms, mlups, gbps of the batch).
  * c_field   : host array of count device pointers or null (entries may be null),

@@ -8,7 +8,7 @@ namespace lbm {
 size_t label_ws_bytes_n(const int32_t n[3]);
 size_t diam_ws_bytes_n(const int32_t n[3]);
 size_t flow_ws_bytes_n(const int32_t n[3], int64_t nf, int32_t storage);
-size_t knudsen_ws_bytes_n(const int32_t n[3], int64_t nf);
+size_t knudsen_ws_bytes_n(const int32_t n[3], int64_t nf, int q);
 }  // namespace lbm
 
 using namespace lbm;
@@ -27,7 +27,8 @@ extern "C" lbm_status lbm_workspace_size(int32_t kind, const int32_t n[3], int64
     case LBM_WS_FLOW: *bytes_h = flow_ws_bytes_n(n, n_fluid, LBM_STORE_FP32); return LBM_OK;
     case LBM_WS_FLOW_FP16: *bytes_h = flow_ws_bytes_n(n, n_fluid, LBM_STORE_FP16); return LBM_OK;
     case LBM_WS_FLOW_FP64: *bytes_h = flow_ws_bytes_n(n, n_fluid, LBM_STORE_FP64); return LBM_OK;
-    case LBM_WS_KNUDSEN: *bytes_h = knudsen_ws_bytes_n(n, n_fluid); return LBM_OK;
+    case LBM_WS_KNUDSEN: *bytes_h = knudsen_ws_bytes_n(n, n_fluid, 7); return LBM_OK;
+    case LBM_WS_KNUDSEN_D3Q19: *bytes_h = knudsen_ws_bytes_n(n, n_fluid, 19); return LBM_OK;
     default: break;
     }
     set_error("unknown workspace kind %d", kind);

@@ -30,17 +30,6 @@
 
 namespace lbm {
 
-// D3Q19 velocities in the column order of the paper's transformation matrix.
-#define LBM_D3Q19_TABLES                                                                      \
-    [[maybe_unused]] constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1,              \
-                                             1, -1, 1, -1, 0, 0, 0, 0};                       \
-    [[maybe_unused]] constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1,              \
-                                             0, 0, 0, 0, 1, -1, 1, -1};                       \
-    [[maybe_unused]] constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0,                \
-                                             1, 1, -1, -1, 1, 1, -1, -1};                     \
-    [[maybe_unused]] constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8,                  \
-                                              7, 14, 13, 12, 11, 18, 17, 16, 15};
-
 constexpr uint64_t kFlowMagic = 0x4c424d464c4f5733ull;  // "LBMFLOW3"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;

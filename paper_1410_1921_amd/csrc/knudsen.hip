@@ -26,10 +26,14 @@ namespace lbm {
 // D3Q7: rest, then +x, -x, +y, -y, +z, -z.
 #define LBM_D3Q7_TABLES [[maybe_unused]] constexpr int OPP[7] = {0, 2, 1, 4, 3, 6, 5};
 
-constexpr uint64_t kKnMagic = 0x4c424d4b4e554432ull;  // "LBMKNUD2"
+constexpr uint64_t kKnMagic = 0x4c424d4b4e554433ull;  // "LBMKNUD3"
 constexpr int kKnSums = 5;  // |dC|^2, C^2, Phi_out, Phi_in, C
 constexpr int kKnSampleMax = 65536;
 constexpr float kW0 = 0.25f, kW1 = 0.125f;
+// The paper's D3Q19 diffusion weights a_i (Section 3.2), binary32.
+__host__ __device__ inline float a19(int i) {
+    return i == 0 ? 1.f / 3.f : (i < 7 ? 1.f / 18.f : 1.f / 36.f);
+}
 constexpr int kPlaneParts = 16;  // workgroups per plane in the plane-mean pass
 
 struct KnHeader {
@@ -39,12 +43,23 @@ struct KnHeader {
     double c_in, c_out;
     int32_t frame;    // reference profile the stored state is relative to
     int32_t variant;  // LBM_VARIANT_* of the solve
+    int32_t lattice;  // LBM_LATTICE_*
+    int32_t pad;
 };
 
-// Reference shifts for a sweep from frame `in` to frame `out`, per x (index x + 1):
-// t0 = w_1 (ref_in(x) - ref_out(x))      rest (x2), y/z and bounced populations
-// tm = w_1 (ref_in(x - 1) - ref_out(x))  +x population streamed from x - 1
-// tp = w_1 (ref_in(x + 1) - ref_out(x))  -x population streamed from x + 1
+// Populations per node and the weights of a lattice: D3Q7 (rest 1/4, faces 1/8) or the
+// paper's D3Q19 (1/3, 1/18, 1/36).
+static int kn_q(int32_t lattice) { return lattice == LBM_LATTICE_D3Q19 ? 19 : 7; }
+// Scale of the frame shift tables: D3Q7 stores w_1 times the reference differences (all
+// its moving weights are 1/8), D3Q19 the differences themselves (the sweep multiplies by
+// a_i).
+static double kn_shift_scale(int32_t lattice) { return lattice == LBM_LATTICE_D3Q19 ? 1.0 : 0.125; }
+
+// Reference shifts for a sweep from frame `in` to frame `out`, per x (index x + 1), times
+// the lattice's shift scale:
+// t0 = ref_in(x) - ref_out(x)      populations with e_x = 0 and bounced ones
+// tm = ref_in(x - 1) - ref_out(x)  populations with e_x = +1, streamed from x - 1
+// tp = ref_in(x + 1) - ref_out(x)  populations with e_x = -1, streamed from x + 1
 struct Shift {
     float t0, tm, tp, pad;
 };
@@ -74,7 +89,7 @@ struct KnWs {
 
 static int64_t kn_blocks(int64_t nf) { return (nf + 255) / 256; }
 
-static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
+static KnWs carve_kn(void *base, const Grid &g, int64_t nf, int q) {
     KnWs w;
     Carver c(base);
     w.hdr = c.take<KnHeader>(1);
@@ -84,7 +99,7 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     w.total = c.take<int32_t>(1);
     w.rank = c.take<RankWord>(g.nsegs());
     w.samp_vox = c.take<int64_t>(kKnSampleMax);
-    w.samp_out = c.take<double>((size_t)kKnSampleMax * 8);
+    w.samp_out = c.take<double>((size_t)kKnSampleMax * 20);
     w.samp_flag = c.take<uint8_t>(kKnSampleMax);
     for (int f = 0; f < 2; f++) w.ref[f] = c.take<double>(kMaxEdge + 2);
     for (int f = 0; f < 2; f++) w.steady[f] = c.take<Shift>(kMaxEdge + 2);
@@ -93,8 +108,8 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     int64_t nfp = nf < 1 ? 1 : nf;
     w.stride = (nfp + 63) / 64 * 64;
     w.coords = c.take<uint32_t>(nfp);
-    w.g[0] = c.take<float>((size_t)7 * w.stride);
-    w.g[1] = c.take<float>((size_t)7 * w.stride);
+    w.g[0] = c.take<float>((size_t)q * w.stride);
+    w.g[1] = c.take<float>((size_t)q * w.stride);
     w.omega = c.take<float>(w.stride);
     w.csnap = c.take<float>(w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(kn_blocks(nfp)) * kKnSums);
@@ -102,9 +117,9 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf) {
     return w;
 }
 
-size_t knudsen_ws_bytes_n(const int32_t n[3], int64_t nf) {
+size_t knudsen_ws_bytes_n(const int32_t n[3], int64_t nf, int q) {
     Grid g = make_grid(n);
-    return carve_kn(nullptr, g, nf < 0 ? g.nvox() : nf).bytes;
+    return carve_kn(nullptr, g, nf < 0 ? g.nvox() : nf, q).bytes;
 }
 
 struct Sweep7 {
@@ -227,6 +242,106 @@ __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
     if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
+// ---------------------------------------------------------------- D3Q19 diffusion
+// The same update on the paper's D3Q19 lattice (Section 3.2): 18 pull sources through the
+// rank map, bounce-back at solid links, the ghost planes beyond the x faces for the five
+// populations with e_x = +1 (at x = 0) or -1 (at x = nx - 1), shifts a_i (t0, tm, tp)
+// from the unscaled tables, BGK with 1/tau_g towards a_i C (the rest population closing
+// the balance of C).
+template <bool CHECK, bool NT>
+__device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
+    LBM_D3Q19_TABLES
+    const uint32_t c = a.coords[n];
+    const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
+    const Grid &g = a.g;
+    const bool gm = x == 0, gp = x == g.nx - 1;  // x - 1, x + 1 beyond a face
+    int xs[3], ys[3], zs[3];
+    xs[0] = gm ? x : x - 1; xs[1] = x; xs[2] = gp ? x : x + 1;  // the node stands in
+    ys[0] = y == 0 ? g.ny - 1 : y - 1; ys[1] = y; ys[2] = y == g.ny - 1 ? 0 : y + 1;
+    zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
+    RankWord rw[19];
+#pragma unroll
+    for (int i = 1; i < 19; i++)
+        rw[i] = a.rank[g.seg(xs[1 - EX[i]], ys[1 - EY[i]], zs[1 - EZ[i]])];
+    int ids[19];
+    ids[0] = 0;
+#pragma unroll
+    for (int i = 1; i < 19; i++) {
+        ids[i] = rank_lookup(rw[i], xs[1 - EX[i]] & (kSeg - 1));
+        if ((EX[i] == 1 && gm) || (EX[i] == -1 && gp)) ids[i] = -2;
+    }
+    const float om = a.omega[n];
+    const Shift sh = a.shift[x + 1];
+    uint32_t off[19];
+    off[0] = (uint32_t)n;
+#pragma unroll
+    for (int i = 1; i < 19; i++)
+        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+    float ai[19];
+#pragma unroll
+    for (int i = 0; i < 19; i++) ai[i] = a.src[off[i]];
+    // onto this node's output reference a_i C_ref(x); a ghost plane holds deviation 0
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        if (ids[i] == -2) ai[i] = 0.f;
+        const float d = (EX[i] == 0 || ids[i] == -1) ? sh.t0 : (EX[i] == 1 ? sh.tm : sh.tp);
+        ai[i] += a19(i) * d;
+    }
+    float cdev = 0.f;  // C - C_ref(x)
+#pragma unroll
+    for (int i = 0; i < 19; i++) cdev += ai[i];
+    // the moving populations relax towards a_i C; the rest one takes what remains of C,
+    // so the collision conserves C exactly although the binary32 a_i sum to 1 + 2.4e-8
+    float so[19], moved = 0.f;
+#pragma unroll
+    for (int i = 1; i < 19; i++) {
+        so[i] = ai[i] - om * (ai[i] - a19(i) * cdev);
+        moved += so[i];
+    }
+    so[0] = cdev - moved;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        if (NT)
+            __builtin_nontemporal_store(so[i], &a.dst[(int64_t)i * a.stride + n]);
+        else
+            a.dst[(int64_t)i * a.stride + n] = so[i];
+    }
+    if (CHECK) {
+        const double conc = a.ref_out[x + 1] + (double)cdev;
+        const double dd = conc - (double)a.csnap[n];
+        acc[0] += dd * dd;
+        acc[1] += conc * conc;
+        // net +x flux into the outlet ghost plane and out of the inlet one: the five
+        // populations leaving towards the plane less the five it sends (weight 1/6)
+        if (gp) {
+            double out = 0.0;
+#pragma unroll
+            for (int i = 1; i < 19; i++)
+                if (EX[i] == 1) out += (double)so[i];
+            acc[2] += out - (double)sh.tp / 6.0;
+        }
+        if (gm) {
+            double back = 0.0;
+#pragma unroll
+            for (int i = 1; i < 19; i++)
+                if (EX[i] == -1) back += (double)so[i];
+            acc[3] += (double)sh.tm / 6.0 - back;
+        }
+        acc[4] += conc;
+        a.csnap[n] = (float)conc;
+        if (a.c_out) a.c_out[a.g.lin(x, y, z)] = (float)conc;
+    }
+}
+
+template <bool CHECK, bool NT>
+__global__ __launch_bounds__(256) void k_sweep19d(Sweep7 a) {
+    const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
+    const int64_t n = lb * 256 + threadIdx.x;
+    double acc[kKnSums] = {0, 0, 0, 0, 0};
+    if (n < a.nf) sweep19d_node<CHECK, NT>(a, n, acc);
+    if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
+}
+
 // ---------------------------------------------------------------- batched solves
 // As in the batched flow solve: concatenated block-aligned fluid lists, rank maps with
 // global node ids, block b of a launch runs physical block blocks[b].  Each lattice has
@@ -296,7 +411,7 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
                                                  float *__restrict__ omega,
                                                  float *__restrict__ csnap, int init_pop,
                                                  unsigned long long *bad,
-                                                 double *__restrict__ partials) {
+                                                 double *__restrict__ partials, int q) {
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc[1] = {0.0};
     if (n < nf) {
@@ -308,8 +423,12 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
         acc[0] = tau - 0.5;
         if (init_pop) {
             const float c0 = c_init ? c_init[v] : 0.f;
-            gbuf[n] = kW0 * c0;
-            for (int i = 1; i < 7; i++) gbuf[(int64_t)i * stride + n] = kW1 * c0;
+            if (q == 7) {
+                gbuf[n] = kW0 * c0;
+                for (int i = 1; i < 7; i++) gbuf[(int64_t)i * stride + n] = kW1 * c0;
+            } else {
+                for (int i = 0; i < 19; i++) gbuf[(int64_t)i * stride + n] = a19(i) * c0;
+            }
             csnap[n] = c0;
         }
     }
@@ -322,15 +441,15 @@ __global__ __launch_bounds__(256) void k_kn_init(Grid g, int64_t nf, int64_t str
 // Frame 0: C_ref = 0 inside, C_in / C_out on the ghost planes, and its steady shifts.
 __global__ __launch_bounds__(1024) void k_frame0(int nx, double c_in, double c_out,
                                                  double *__restrict__ ref,
-                                                 Shift *__restrict__ steady) {
+                                                 Shift *__restrict__ steady, double ws) {
     for (int k = threadIdx.x; k < nx + 2; k += 1024)
         ref[k] = k == 0 ? c_in : (k == nx + 1 ? c_out : 0.0);
     __syncthreads();
     for (int k = threadIdx.x; k < nx + 2; k += 1024) {
         Shift s;
         s.t0 = 0.f;
-        s.tm = k >= 1 ? (float)(0.125 * (ref[k - 1] - ref[k])) : 0.f;
-        s.tp = k <= nx ? (float)(0.125 * (ref[k + 1] - ref[k])) : 0.f;
+        s.tm = k >= 1 ? (float)(ws * (ref[k - 1] - ref[k])) : 0.f;
+        s.tp = k <= nx ? (float)(ws * (ref[k + 1] - ref[k])) : 0.f;
         s.pad = 0.f;
         steady[k] = s;
     }
@@ -386,7 +505,8 @@ __global__ __launch_bounds__(256) void k_plane_mean_b(const int32_t *__restrict_
 __device__ inline void frame_next(int nx, double c_in, double c_out,
                                   const double *__restrict__ part,
                                   const double *__restrict__ ref_cur, double *__restrict__ ref_next,
-                                  Shift *__restrict__ steady_next, Shift *__restrict__ trans) {
+                                  Shift *__restrict__ steady_next, Shift *__restrict__ trans,
+                                  double ws) {
     for (int k = threadIdx.x; k < nx + 2; k += 1024) {
         double v;
         if (k == 0) {
@@ -407,12 +527,12 @@ __device__ inline void frame_next(int nx, double c_in, double c_out,
     for (int k = threadIdx.x; k < nx + 2; k += 1024) {
         Shift s, t;
         s.t0 = 0.f;
-        s.tm = k >= 1 ? (float)(0.125 * (ref_next[k - 1] - ref_next[k])) : 0.f;
-        s.tp = k <= nx ? (float)(0.125 * (ref_next[k + 1] - ref_next[k])) : 0.f;
+        s.tm = k >= 1 ? (float)(ws * (ref_next[k - 1] - ref_next[k])) : 0.f;
+        s.tp = k <= nx ? (float)(ws * (ref_next[k + 1] - ref_next[k])) : 0.f;
         s.pad = 0.f;
-        t.t0 = (float)(0.125 * (ref_cur[k] - ref_next[k]));
-        t.tm = k >= 1 ? (float)(0.125 * (ref_cur[k - 1] - ref_next[k])) : 0.f;
-        t.tp = k <= nx ? (float)(0.125 * (ref_cur[k + 1] - ref_next[k])) : 0.f;
+        t.t0 = (float)(ws * (ref_cur[k] - ref_next[k]));
+        t.tm = k >= 1 ? (float)(ws * (ref_cur[k - 1] - ref_next[k])) : 0.f;
+        t.tp = k <= nx ? (float)(ws * (ref_cur[k + 1] - ref_next[k])) : 0.f;
         t.pad = 0.f;
         steady_next[k] = s;
         trans[k] = t;
@@ -424,8 +544,8 @@ __global__ __launch_bounds__(1024) void k_frame_next(int nx, double c_in, double
                                                      const double *__restrict__ ref_cur,
                                                      double *__restrict__ ref_next,
                                                      Shift *__restrict__ steady_next,
-                                                     Shift *__restrict__ trans) {
-    frame_next(nx, c_in, c_out, part, ref_cur, ref_next, steady_next, trans);
+                                                     Shift *__restrict__ trans, double ws) {
+    frame_next(nx, c_in, c_out, part, ref_cur, ref_next, steady_next, trans, ws);
 }
 
 // Batched: workgroup l forms the next frame of lattice lat_ids[l].
@@ -439,7 +559,7 @@ __global__ __launch_bounds__(1024) void k_frame_next_b(const int32_t *__restrict
                                                        Shift *__restrict__ trans) {
     const KnLat L = lats[lat_ids[blockIdx.x]];
     frame_next(L.g.nx, c_in, c_out, part + 2 * L.pl0 * kPlaneParts, ref_cur + L.sh0,
-               ref_next + L.sh0, steady_next + L.sh0, trans + L.sh0);
+               ref_next + L.sh0, steady_next + L.sh0, trans + L.sh0, 0.125);
 }
 
 // Net +x flux through the link plane x = px - 1/2 (px = 0..nx), one block per plane,
@@ -469,10 +589,43 @@ __global__ __launch_bounds__(256) void k_plane_flux(Grid g, int64_t stride,
     if (threadIdx.x == 0) plane[px] = out[0];
 }
 
+// The same on D3Q19: over the five directions with e_x = +1, the links from
+// (px - 1, y - e_y, z - e_z) to (px, y, z) with both ends fluid; the shift tables are
+// unscaled, so the frame difference is a_i tm.
+__global__ __launch_bounds__(256) void k_plane_flux19(Grid g, int64_t stride,
+                                                      const RankWord *__restrict__ rank,
+                                                      const float *__restrict__ gcur,
+                                                      const Shift *__restrict__ steady,
+                                                      double *__restrict__ plane) {
+    LBM_D3Q19_TABLES
+    const int px = blockIdx.x;
+    const int left = px - 1, right = px;
+    const double tm = (double)steady[right + 1].tm;
+    double acc[1] = {0.0};
+    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
+        const int y = (int)(k % g.ny), z = (int)(k / g.ny);
+        const int ir = right < g.nx ? node_at(rank, g, right, y, z) : -2;
+        if (ir == -1) continue;
+        for (int i = 1; i < 19; i++) {
+            if (EX[i] != 1) continue;
+            const int ly = (y - EY[i] + g.ny) % g.ny, lz = (z - EZ[i] + g.nz) % g.nz;
+            const int il = left >= 0 ? node_at(rank, g, left, ly, lz) : -2;
+            if (il == -1) continue;
+            const double fwd = il >= 0 ? (double)gcur[(int64_t)i * stride + il] : 0.0;
+            const double bwd = ir >= 0 ? (double)gcur[(int64_t)OPP[i] * stride + ir] : 0.0;
+            acc[0] += (fwd - bwd) + (double)a19(i) * tm;
+        }
+    }
+    __shared__ double lds[4];
+    double out[1];
+    block_sum<1>(acc, lds, out);
+    if (threadIdx.x == 0) plane[px] = out[0];
+}
+
 __global__ void k_kn_sample(Grid g, int64_t count, int64_t stride, const int64_t *__restrict__ vox,
                             const RankWord *__restrict__ rank, const float *__restrict__ gcur,
                             const float *__restrict__ omega, const double *__restrict__ cref,
-                            double *__restrict__ out, uint8_t *__restrict__ flag) {
+                            double *__restrict__ out, uint8_t *__restrict__ flag, int q) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
     const int64_t v = vox[s];
@@ -480,10 +633,11 @@ __global__ void k_kn_sample(Grid g, int64_t count, int64_t stride, const int64_t
     const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
     const double ref = cref[x + 1];
-    for (int i = 0; i < 7; i++)
-        out[s * 8 + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] + (i ? 0.125 : 0.25) * ref
-                                 : 0.0;
-    out[s * 8 + 7] = id >= 0 ? 1.0 / (double)omega[id] : 0.0;
+    for (int i = 0; i < q; i++) {
+        const double w = q == 7 ? (i ? 0.125 : 0.25) : (double)a19(i);
+        out[s * (q + 1) + i] = id >= 0 ? (double)gcur[(int64_t)i * stride + id] + w * ref : 0.0;
+    }
+    out[s * (q + 1) + q] = id >= 0 ? 1.0 / (double)omega[id] : 0.0;
 }
 
 // Plane means of the checked concentration become the next frame (kept pending until
@@ -493,7 +647,7 @@ static lbm_status kn_next_frame(const KnWs &w, const Grid &g, const KnHeader &h,
     LBM_CHECK_LAUNCH();
     const int f = h.frame;
     k_frame_next<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.part, w.ref[f], w.ref[f ^ 1],
-                                    w.steady[f ^ 1], w.trans);
+                                    w.steady[f ^ 1], w.trans, kn_shift_scale(h.lattice));
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
@@ -506,24 +660,29 @@ struct Variant7 {
     bool remap, nt;
 };
 
-static Variant7 pick_variant7(int32_t v, int64_t stride) {
+static Variant7 pick_variant7(int32_t v, int64_t stride, int q = 7) {
     Variant7 m;
     if (v & LBM_VARIANT_EXPLICIT) {
         m.remap = v & LBM_VARIANT_REMAP;
         m.nt = v & LBM_VARIANT_NTSTORE;
         return m;
     }
-    const bool stream = (2.0 * 7 * 4 + 12.0) * (double)stride > kCacheBytes;
+    const bool stream = (2.0 * q * 4 + 12.0) * (double)stride > kCacheBytes;
     m.remap = !stream;
     m.nt = stream;
     return m;
 }
 
 template <bool CHECK>
-static void launch7(const Sweep7 &a, const Variant7 &m, hipStream_t s) {
+static void launch7(const Sweep7 &a, const Variant7 &m, int32_t lattice, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep7<CHECK, true><<<grid, 256, 0, s>>>(a);
-    else k_sweep7<CHECK, false><<<grid, 256, 0, s>>>(a);
+    if (lattice == LBM_LATTICE_D3Q19) {
+        if (m.nt) k_sweep19d<CHECK, true><<<grid, 256, 0, s>>>(a);
+        else k_sweep19d<CHECK, false><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (m.nt) k_sweep7<CHECK, true><<<grid, 256, 0, s>>>(a);
+        else k_sweep7<CHECK, false><<<grid, 256, 0, s>>>(a);
+    }
 }
 
 // `steps` sweeps; the first one moves the state into the pending frame if there is one.
@@ -554,9 +713,9 @@ static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, KnHeader &
         a.src = w.g[cur];
         a.dst = w.g[cur ^ 1];
         if (check_last && t == steps - 1)
-            launch7<true>(a, m, s);
+            launch7<true>(a, m, h.lattice, s);
         else
-            launch7<false>(a, m, s);
+            launch7<false>(a, m, h.lattice, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
     }
@@ -567,7 +726,8 @@ static lbm_status kn_launch(const KnWs &w, const Grid &g, int64_t nf, KnHeader &
 // sum C), the sum of tau_g - 1/2 and the link-plane fluxes (Eqs. 11, 14-16).
 static void kn_result(lbm_knudsen_result *r, const lbm_knudsen_params *p, const Grid &g,
                       int64_t nf, int64_t t, bool converged, double resid, const double *sums,
-                      double sum_tau, const double *planes, double sweep_ms, double updates) {
+                      double sum_tau, const double *planes, double sweep_ms, double updates,
+                      int32_t lattice) {
     std::memset(r, 0, sizeof(*r));
     r->steps = t;
     r->n_fluid = nf;
@@ -578,7 +738,7 @@ static void kn_result(lbm_knudsen_result *r, const lbm_knudsen_params *p, const 
     r->sum_c = sums[4];
     const double dc = p->c_in - p->c_out;
     r->Deff_lattice = sums[2] / ((double)g.ny * g.nz) * (double)(g.nx + 1) / dc;
-    const double cs2 = 0.25;
+    const double cs2 = lattice == LBM_LATTICE_D3Q19 ? 1.0 / 3.0 : 0.25;
     const double d_lref = cs2 * (p->tau_ref - 0.5);
     r->Deff_over_DKref = r->Deff_lattice / d_lref;
     const double R = 8.314462618, PI = 3.141592653589793;
@@ -597,7 +757,8 @@ static void kn_result(lbm_knudsen_result *r, const lbm_knudsen_params *p, const 
     r->flux_spread = mean != 0.0 ? (mx - mn) / std::fabs(mean) : INFINITY;
     r->sweep_ms = sweep_ms;
     r->mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
-    r->gbps = sweep_ms > 0 ? updates * 60.0 / (sweep_ms * 1e-3) / 1e9 : 0.0;
+    const double bytes = lattice == LBM_LATTICE_D3Q19 ? 156.0 : 60.0;  // 2 x q x 4 + 1/tau_g
+    r->gbps = sweep_ms > 0 ? updates * bytes / (sweep_ms * 1e-3) / 1e9 : 0.0;
 }
 
 }  // namespace lbm
@@ -622,20 +783,23 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
                 "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
     LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
+    LBM_REQUIRE(p->lattice == LBM_LATTICE_D3Q7 || p->lattice == LBM_LATTICE_D3Q19, LBM_E_INVAL,
+                "unknown lattice %d", p->lattice);
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Grid g = make_grid(n);
+    const int q = kn_q(p->lattice);
 
-    KnWs w0 = carve_kn(workspace, g, 1);
+    KnWs w0 = carve_kn(workspace, g, 1, q);
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
     st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
-    KnWs w = carve_kn(workspace, g, nf);
-    LBM_REQUIRE(7 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
+    KnWs w = carve_kn(workspace, g, nf, q);
+    LBM_REQUIRE(q * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
                 "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
                 "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
@@ -647,7 +811,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         LBM_REQUIRE(h.magic == kKnMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
-                        h.n_fluid == nf && h.c_in == p->c_in && h.c_out == p->c_out,
+                        h.n_fluid == nf && h.c_in == p->c_in && h.c_out == p->c_out &&
+                        h.lattice == p->lattice,
                     LBM_E_INVAL, "resume: the workspace holds no state for this problem");
         t0 = h.steps_done;
         cur = h.cur;
@@ -655,7 +820,9 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         h.frame = 0;
     }
     h.variant = p->variant;
-    const Variant7 mode = pick_variant7(p->variant, w.stride);
+    h.lattice = p->lattice;
+    h.pad = 0;
+    const Variant7 mode = pick_variant7(p->variant, w.stride, q);
     st = layout_fill(g, w.rank, w.coords, s);
     if (st != LBM_OK) return st;
     h.magic = kKnMagic;
@@ -668,12 +835,13 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, pore_diam, d_ref,
                                                       p->tau_ref, c_init, w.g[cur], w.omega,
                                                       w.csnap, p->resume ? 0 : 1, w.counter,
-                                                      w.partials);
+                                                      w.partials, q);
     LBM_CHECK_LAUNCH();
     bool pending = false;
     if (!p->resume) {
         // frame 0 holds the initial state; its plane means become the first pending frame
-        k_frame0<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.ref[0], w.steady[0]);
+        k_frame0<<<1, 1024, 0, s>>>(g.nx, h.c_in, h.c_out, w.ref[0], w.steady[0],
+                                    kn_shift_scale(h.lattice));
         LBM_CHECK_LAUNCH();
         st = kn_next_frame(w, g, h, s);
         if (st != LBM_OK) return st;
@@ -738,8 +906,12 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.steps_done = t0 + t;
     LBM_TRY_HIP(hipMemcpyAsync(w.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
     // link-plane fluxes of the final state
-    k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.rank, w.g[cur],
-                                                      w.steady[h.frame], w.plane);
+    if (h.lattice == LBM_LATTICE_D3Q19)
+        k_plane_flux19<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.rank, w.g[cur],
+                                                            w.steady[h.frame], w.plane);
+    else
+        k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.stride, w.rank, w.g[cur],
+                                                          w.steady[h.frame], w.plane);
     LBM_CHECK_LAUNCH();
     double planes[kMaxEdge + 1];
     LBM_TRY_HIP(hipMemcpyAsync(planes, w.plane, sizeof(double) * (g.nx + 1), hipMemcpyDeviceToHost, s));
@@ -747,7 +919,7 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     if (plane_flux_h) std::memcpy(plane_flux_h, planes, sizeof(double) * (g.nx + 1));
 
     kn_result(r, p, g, nf, t, converged, resid, sums, sum_tau, planes, sweep_ms,
-              (double)nf * (double)t);
+              (double)nf * (double)t, h.lattice);
     if (diverged) {
         set_error("Knudsen solve diverged (NaN/Inf) by step %lld", (long long)(t0 + t));
         return LBM_E_DIVERGED;
@@ -767,7 +939,7 @@ static lbm_status read_kn_state(void *workspace, size_t ws_bytes, hipStream_t s,
     LBM_REQUIRE(h.magic == kKnMagic, LBM_E_INVAL, "the workspace holds no Knudsen state");
     const int32_t n[3] = {h.nx, h.ny, h.nz};
     g = make_grid(n);
-    w = carve_kn(workspace, g, h.n_fluid);
+    w = carve_kn(workspace, g, h.n_fluid, kn_q(h.lattice));
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM, "workspace smaller than its state");
     return LBM_OK;
 }
@@ -782,8 +954,8 @@ extern "C" lbm_status lbm_knudsen_step(void *workspace, size_t ws_bytes, int64_t
     LBM_REQUIRE(steps >= 0, LBM_E_INVAL, "negative step count");
     int cur = h.cur;
     bool pending = false;
-    st = kn_launch(w, g, h.n_fluid, h, pick_variant7(h.variant, w.stride), cur, pending, steps,
-                   false, nullptr, s);
+    st = kn_launch(w, g, h.n_fluid, h, pick_variant7(h.variant, w.stride, kn_q(h.lattice)), cur,
+                   pending, steps, false, nullptr, s);
     if (st != LBM_OK) return st;
     h.cur = cur;
     h.steps_done += steps;
@@ -812,15 +984,17 @@ extern "C" lbm_status lbm_knudsen_sample(void *workspace, size_t ws_bytes, const
     k_kn_sample<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(g, count, w.stride, w.samp_vox,
                                                                w.rank, w.g[h.cur], w.omega,
                                                                w.ref[h.frame], w.samp_out,
-                                                               w.samp_flag);
+                                                               w.samp_flag, kn_q(h.lattice));
     LBM_CHECK_LAUNCH();
-    std::vector<double> tmp((size_t)count * 8);
-    LBM_TRY_HIP(hipMemcpyAsync(tmp.data(), w.samp_out, sizeof(double) * 8 * count, hipMemcpyDeviceToHost, s));
+    const int q = kn_q(h.lattice);
+    std::vector<double> tmp((size_t)count * (q + 1));
+    LBM_TRY_HIP(hipMemcpyAsync(tmp.data(), w.samp_out, sizeof(double) * (q + 1) * count,
+                               hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(fluid_h, w.samp_flag, count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
     for (int64_t i = 0; i < count; i++) {
-        for (int k = 0; k < 7; k++) g_h[i * 7 + k] = tmp[i * 8 + k];
-        tau_h[i] = tmp[i * 8 + 7];
+        for (int k = 0; k < q; k++) g_h[i * q + k] = tmp[i * (q + 1) + k];
+        tau_h[i] = tmp[i * (q + 1) + q];
     }
     return LBM_OK;
 }
@@ -987,6 +1161,8 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
                 "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
     LBM_REQUIRE(!p->resume, LBM_E_INVAL, "batched solves do not resume");
+    LBM_REQUIRE(p->lattice == LBM_LATTICE_D3Q7, LBM_E_INVAL,
+                "batched solves run the D3Q7 lattice only");
     LBM_REQUIRE((p->variant & ~(kVariantBits | LBM_VARIANT_NOGRAPH)) == 0, LBM_E_INVAL,
                 "unknown variant bits 0x%x", p->variant);
     lbm_status st = check_device();
@@ -1034,11 +1210,12 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
         k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(
             g, nf, span, w.coords + n0, pore_diam[l], d_ref, p->tau_ref,
             c_init ? c_init[l] : nullptr, w.g[0] + 7 * n0, w.omega + n0, w.csnap + n0, 1,
-            w.counter, w.partials + b0);
+            w.counter, w.partials + b0, 7);
         LBM_CHECK_LAUNCH();
         st = reduce_partials(w.partials + b0, kn_blocks(nf), 1, w.tau_sum + l, s);
         if (st != LBM_OK) return st;
-        k_frame0<<<1, 1024, 0, s>>>(g.nx, p->c_in, p->c_out, w.ref[0] + sh0, w.steady[0] + sh0);
+        k_frame0<<<1, 1024, 0, s>>>(g.nx, p->c_in, p->c_out, w.ref[0] + sh0, w.steady[0] + sh0,
+                                    0.125);
         LBM_CHECK_LAUNCH();
         bl[l] = BatchLat{L.b0, L.b1, nf, g.nx};
         for (int64_t b = L.b0; b < L.b1; b++)
@@ -1241,7 +1418,7 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     for (int l = 0; l < count; l++) {
         kn_result(r_h + l, p, lats[l].g, nf_h[l], steps_l[l], conv_l[l], resid_l[l],
                   sums_l.data() + (size_t)l * kKnSums, tau_sum[l], planes.data() + lats[l].sh0,
-                  sweep_ms, updates);
+                  sweep_ms, updates, LBM_LATTICE_D3Q7);
     }
     if (diverged) {
         set_error("batched Knudsen solve diverged (NaN/Inf) by step %lld", (long long)t);

@@ -212,6 +212,17 @@ struct BatchGroup {
     double nodes;            // fluid nodes
 };
 
+// D3Q19 velocities in the column order of the paper's transformation matrix.
+#define LBM_D3Q19_TABLES                                                                      \
+    [[maybe_unused]] constexpr int EX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1,              \
+                                             1, -1, 1, -1, 0, 0, 0, 0};                       \
+    [[maybe_unused]] constexpr int EY[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1,              \
+                                             0, 0, 0, 0, 1, -1, 1, -1};                       \
+    [[maybe_unused]] constexpr int EZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0,                \
+                                             1, 1, -1, -1, 1, 1, -1, -1};                     \
+    [[maybe_unused]] constexpr int OPP[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8,                  \
+                                              7, 14, 13, 12, 11, 18, 17, 16, 15};
+
 // The Infinity Cache (MALL) of the device: a sweep whose state fits it runs
 // cache-resident, a larger one streams from HBM.
 constexpr double kCacheBytes = 256e6;

@@ -20,6 +20,8 @@ LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_RECON_STALL, LBM_E_DIVERGED = -1, 
 LBM_PSD_CHORD13, LBM_PSD_MIS = 0, 1
 LBM_WS_LABEL, LBM_WS_PORE_DIAM, LBM_WS_FLOW, LBM_WS_KNUDSEN = 0, 1, 2, 3
 LBM_WS_FLOW_FP16, LBM_WS_FLOW_FP64 = 4, 5
+LBM_WS_KNUDSEN_D3Q19 = 6
+LBM_LATTICE_D3Q7, LBM_LATTICE_D3Q19 = 0, 1
 LBM_STORE_FP32, LBM_STORE_FP16, LBM_STORE_FP64 = 0, 1, 2
 LBM_COLLIDE_BGK, LBM_COLLIDE_MRT = 0, 1
 _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
@@ -74,7 +76,7 @@ class lbm_knudsen_params(C.Structure):
                 ("c_in", C.c_double), ("c_out", C.c_double), ("T_K", C.c_double),
                 ("M_kg_mol", C.c_double), ("max_steps", C.c_int64), ("fixed_steps", C.c_int64),
                 ("check_every", C.c_int32), ("resume", C.c_int32), ("tol", C.c_double),
-                ("variant", C.c_int32), ("reserved", C.c_int32)]
+                ("variant", C.c_int32), ("lattice", C.c_int32)]
 
 
 class lbm_knudsen_result(C.Structure):
@@ -404,16 +406,19 @@ def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_00
 def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5, c_in=1.0,
                       c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000, fixed_steps=0,
                       check_every=100, tol=1e-7, want_c=False, c_init=None, want_planes=True,
-                      workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO):
+                      workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
+                      lattice=LBM_LATTICE_D3Q7):
+    """Mass-transport solve on the D3Q7 lattice or (lattice=LBM_LATTICE_D3Q19) the
+    paper's D3Q19 lattice."""
     _vol(fluid, torch.uint8, "fluid")
     _vol(pore_diam, torch.float64, "pore_diam")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
     if workspace is None:
-        workspace = Workspace(lbm_workspace_size(LBM_WS_KNUDSEN, fluid.shape, n_fluid),
-                              fluid.device)
+        kind = LBM_WS_KNUDSEN_D3Q19 if lattice == LBM_LATTICE_D3Q19 else LBM_WS_KNUDSEN
+        workspace = Workspace(lbm_workspace_size(kind, fluid.shape, n_fluid), fluid.device)
     p = lbm_knudsen_params(tau_ref, d_ref_nm, voxel_nm, c_in, c_out, T, M, max_steps, fixed_steps,
-                           check_every, int(bool(resume)), tol, int(variant), 0)
+                           check_every, int(bool(resume)), tol, int(variant), int(lattice))
     r = lbm_knudsen_result()
     c = torch.empty(fluid.shape, dtype=torch.float32, device=fluid.device) if want_c else None
     nx = fluid.shape[2]
@@ -424,6 +429,7 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
         _n3(fluid.shape), _ptr(fluid), _ptr(pore_diam), C.byref(p), C.byref(r), _ptr(c),
         _ptr(c_init), None if planes is None else planes.ctypes.data_as(C.c_void_p),
         workspace.ptr, workspace.nbytes, _stream()), "lbm_knudsen_solve")
+    workspace.lattice = int(lattice)
     res = _as_dict(r)
     res["plane_flux"] = planes
     return Solve(st, res, c, workspace, tuple(fluid.shape))
@@ -487,9 +493,11 @@ def lbm_knudsen_step(workspace, steps):
 
 
 def lbm_knudsen_sample(workspace, vox):
-    """Post-collision g_i (float64 [count, 7]), tau_g as used, fluid flags at `vox`."""
+    """Post-collision g_i (float64 [count, q], q = 7 or 19 by the lattice of the solve
+    that left the state), tau_g as used, fluid flags at `vox`."""
     vox = np.ascontiguousarray(vox, np.int64)
-    g = np.zeros((len(vox), 7), np.float64)
+    q = 19 if getattr(workspace, "lattice", LBM_LATTICE_D3Q7) == LBM_LATTICE_D3Q19 else 7
+    g = np.zeros((len(vox), 19), np.float64)  # room for either lattice
     tau = np.zeros(len(vox), np.float64)
     flag = np.zeros(len(vox), np.uint8)
     _check(load().lbm_knudsen_sample(workspace.ptr, workspace.nbytes,
@@ -497,7 +505,7 @@ def lbm_knudsen_sample(workspace, vox):
                                      g.ctypes.data_as(C.c_void_p), tau.ctypes.data_as(C.c_void_p),
                                      flag.ctypes.data_as(C.c_void_p), _stream()),
            "lbm_knudsen_sample")
-    return g, tau, flag
+    return g.reshape(-1)[:len(vox) * q].reshape(len(vox), q), tau, flag
 
 
 # ------------------------------------------------------------------ properties

@@ -62,6 +62,9 @@ def test_workspace_sizes(lib):
     assert s16[1] - s16[0] < s_big - s_small < s64[1] - s64[0]
     assert s64[1] - s64[0] >= 2 * 19 * 8 * 19000
     assert lib.lbm_workspace_size(lib.LBM_WS_KNUDSEN, (16, 16, 16), 100) > 0
+    k7 = [lib.lbm_workspace_size(lib.LBM_WS_KNUDSEN, (32, 32, 32), m) for m in (1000, 20000)]
+    k19 = [lib.lbm_workspace_size(lib.LBM_WS_KNUDSEN_D3Q19, (32, 32, 32), m) for m in (1000, 20000)]
+    assert k19[1] - k19[0] - (k7[1] - k7[0]) >= 2 * 12 * 4 * 19000  # 12 more populations
     assert lib.lbm_workspace_size(lib.LBM_WS_LABEL, (16, 16, 16)) >= 2 * 16 ** 3
     assert lib.lbm_workspace_size(lib.LBM_WS_PORE_DIAM, (16, 16, 16)) >= 12 * 16 ** 3
     with pytest.raises(lib.LbmError) as e:
@@ -90,6 +93,12 @@ def test_argument_checks_before_device(lib):
     kr = lib.lbm_knudsen_result()
     assert L.lbm_knudsen_solve(n, dummy, dummy, C.byref(kp), C.byref(kr), None, None, None,
                                dummy, 1 << 20, None) == lib.LBM_E_INVAL
+    for bad_lattice in (2, -1, 19):
+        kp = lib.lbm_knudsen_params(1.0, 60.0, 1.5, 1.0, 0.0, 323.0, 0.016, 10, 0, 10, 0, 1e-7, 0,
+                                    bad_lattice)
+        assert L.lbm_knudsen_solve(n, dummy, dummy, C.byref(kp), C.byref(kr), None, None, None,
+                                   dummy, 1 << 20, None) == lib.LBM_E_INVAL
+        assert "lattice" in L.lbm_last_error().decode()
     rp = lib.lbm_recon_params((C.c_int32 * 3)(8, 8, 8), 1.5, 4.0, 1.0, 1.0, 0.5, 0.5, 1, 0)
     rs = lib.lbm_recon_stats()
     assert L.lbm_reconstruct(C.byref(rp), dummy, None, 0, C.byref(rs), None) == lib.LBM_E_INVAL
@@ -185,13 +194,15 @@ def test_knudsen_batch_sizes_and_checks(lib):
     res = (lib.lbm_knudsen_result * 2)()
 
     def call(count=2, **kw):
-        a = dict(tau_ref=1.0, c_in=1.0, c_out=0.0, resume=0, variant=0, check_every=10)
+        a = dict(tau_ref=1.0, c_in=1.0, c_out=0.0, resume=0, variant=0, check_every=10,
+                 lattice=0)
         a.update(kw)
         p = lib.lbm_knudsen_params(a["tau_ref"], 60.0, 1.5, a["c_in"], a["c_out"], 323.0, 0.016,
-                                   10, 0, a["check_every"], a["resume"], 1e-7, a["variant"], 0)
+                                   10, 0, a["check_every"], a["resume"], 1e-7, a["variant"],
+                                   a["lattice"])
         return L.lbm_knudsen_solve_batch(count, n, ptrs, ptrs, nf, C.byref(p), None, res, None,
                                          None, C.c_void_p(1), 1 << 30, None)
 
     for kw in (dict(resume=1), dict(c_out=1.0), dict(tau_ref=0.5), dict(variant=2),
-               dict(check_every=0), dict(count=0)):
+               dict(check_every=0), dict(count=0), dict(lattice=1)):
         assert call(**kw) == lib.LBM_E_INVAL, kw
