@@ -36,13 +36,13 @@ BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 COUNTERS = {
     "k_sweep7<false, false>": dict(
-        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15335.1, write_kib=22966.8,
+        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15338.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="d8c126f70eb399be"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="567ff54ea4aac6bc"),
     "k_sweep19<StoreF32, false, true, false>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2141860.4, write_kib=2490368.6,
+        workload="recon512_eps0.25_d16", fetch_kib=2141860.7, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="50b1dbb464f0441c"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="b513f7871dd4d374"),
 }
 
 
@@ -391,7 +391,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="recon128_eps0.40_d12_mis_ch4_400K")
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-512", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-started pipeline")
