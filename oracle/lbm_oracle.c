@@ -598,8 +598,50 @@ void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u
 }
 
 /*
+ * The two-relaxation-time form of the MRT collision above (Eq. 7 relaxes every even
+ * non-conserved moment at 1/tau and every odd one at s_q, with the equilibrium moments
+ * A1-A9 of the incompressible equilibrium, rho0 = 1): in velocity space, each pair of
+ * opposite velocities (i, i') splits into its even part f+ = (f_i + f_i')/2, relaxed at
+ * s+ = 1/tau towards the even part of f_eq,i = w_i [rho + 3 e.j + 9/2 (e.j)^2 - 3/2 j^2]
+ * (j = sum f e + F/2), and its odd part f- = (f_i - f_i')/2, relaxed at s- = s_q towards
+ * 3 w_i e.j; Guo's source splits alike, each part scaled by (1 - s/2).
+ */
+void orc_collide19_trt(const double *fin, double tau, const double *F, double *fout,
+                       double *mom) {
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; i++) {
+        rho += fin[i];
+        for (int a = 0; a < 3; a++) j[a] += fin[i] * E19[i][a];
+    }
+    for (int a = 0; a < 3; a++) j[a] += 0.5 * F[a];
+    const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    const double sp = 1.0 / tau, sm = 8.0 * (2.0 * tau - 1.0) / (8.0 * tau - 1.0);
+    const double jj = j[0] * j[0] + j[1] * j[1] + j[2] * j[2];
+    const double uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+    for (int i = 0; i < 19; i++) {
+        const int k = opp19(i);
+        const double ej = E19[i][0] * j[0] + E19[i][1] * j[1] + E19[i][2] * j[2];
+        const double eu = E19[i][0] * u[0] + E19[i][1] * u[1] + E19[i][2] * u[2];
+        const double eF = E19[i][0] * F[0] + E19[i][1] * F[1] + E19[i][2] * F[2];
+        const double w = w19(i);
+        const double feq_even = w * (rho + 4.5 * ej * ej - 1.5 * jj);
+        const double feq_odd = w * 3.0 * ej;
+        const double src_even = w * (-3.0 * uF + 9.0 * eu * eF);
+        const double src_odd = w * 3.0 * eF;
+        const double f_even = 0.5 * (fin[i] + fin[k]), f_odd = 0.5 * (fin[i] - fin[k]);
+        fout[i] = fin[i] - sp * (f_even - feq_even) - sm * (f_odd - feq_odd) +
+                  (1.0 - 0.5 * sp) * src_even + (1.0 - 0.5 * sm) * src_odd;
+    }
+    if (mom) {
+        mom[0] = rho;
+        for (int a = 0; a < 3; a++) mom[1 + a] = j[a];
+    }
+}
+
+/*
  * The flow solve: iterate stream + collide (collision 0: BGK, orc_collide19;
- * 1: MRT, orc_collide19_mrt) from the state in f (node-major
+ * 1: MRT, orc_collide19_mrt; 2: its two-relaxation-time form, orc_collide19_trt)
+ * from the state in f (node-major
  * 19*N^3, in/out).  Every check_every steps (and at the last step) the
  * moments of the incoming populations give u = rho*u / rho; the residual is
  * ||u(t) - u(t - n_c)||_2 / (n_c ||u(t)||_2) over fluid nodes (reading: the
@@ -648,6 +690,7 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int
                     double fin[19], mom[4];
                     gather19(nx, ny, nz, fluid, f, x, y, z, fin);
                     if (collision == 1) orc_collide19_mrt(fin, tau, NULL, F, g + 19 * v, mom);
+                    else if (collision == 2) orc_collide19_trt(fin, tau, F, g + 19 * v, mom);
                     else orc_collide19(fin, tau, F, g + 19 * v, mom);
                     if (check) {
                         double du2 = 0.0, u2 = 0.0;
@@ -710,6 +753,7 @@ void orc_flow_update_node(const uint8_t *nb_fluid, const double *nb_f, double ta
     double fin[19];
     for (int i = 0; i < 19; i++) fin[i] = nb_fluid[i] ? nb_f[19 * i + i] : nb_f[opp19(i)];
     if (collision == 1) orc_collide19_mrt(fin, tau, NULL, F, fout, mom);
+    else if (collision == 2) orc_collide19_trt(fin, tau, F, fout, mom);
     else orc_collide19(fin, tau, F, fout, mom);
 }
 

@@ -85,6 +85,8 @@ def lib():
     L.orc_flow_update_node.argtypes = [_u8p, _f64p, C.c_double, C.c_int, _f64p, _f64p,
                                        _nullable(_f64p)]
     L.orc_flow_update_node.restype = None
+    L.orc_collide19_trt.argtypes = [_f64p, C.c_double, _f64p, _f64p, _f64p]
+    L.orc_collide19_trt.restype = None
     L.orc_collide19_mrt.argtypes = [_f64p, C.c_double, _nullable(_f64p), _f64p, _f64p,
                                     _nullable(_f64p)]
     L.orc_collide19_mrt.restype = None
@@ -240,7 +242,7 @@ def flow_init(fluid, u_init=None, drho_init=None):
     return f
 
 
-BGK, MRT = 0, 1
+BGK, MRT, TRT = 0, 1, 2
 
 
 def flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
@@ -287,6 +289,15 @@ def collide19_mrt(fin, tau, force, rates=None):
     mom = np.zeros(4)
     r = None if rates is None else np.ascontiguousarray(rates, np.float64)
     lib().orc_collide19_mrt(np.ascontiguousarray(fin, np.float64), tau, r,
+                            np.ascontiguousarray(force, np.float64), fout, mom)
+    return fout, mom
+
+
+def collide19_trt(fin, tau, force):
+    """The MRT collision of Eq. 7 in its two-relaxation-time form (``orc_collide19_trt``)."""
+    fout = np.zeros(19)
+    mom = np.zeros(4)
+    lib().orc_collide19_trt(np.ascontiguousarray(fin, np.float64), tau,
                             np.ascontiguousarray(force, np.float64), fout, mom)
     return fout, mom
 

@@ -10,6 +10,8 @@
   3/16.  For that value the discrete slit with half-way bounce-back has the
   tau-independent permeability (H / n_y)(H^2 + 1/2)/12 (the BGK value has 8 (tau - 1/2)^2
   in place of 3/2).
+* That two-relaxation-time form, written in velocity space from its own definition,
+  gives the moment-space collision to rounding, also away from rho = 1 and with a force.
 """
 import os
 from fractions import Fraction
@@ -85,3 +87,28 @@ def test_slit_permeability_is_viscosity_independent(orc, tau, h):
                        tol=1e-13, want_u=False, collision=orc.MRT)
     assert r["converged"]
     assert r["k_lattice"] == pytest.approx(h / (h + 2) * (h * h + 0.5) / 12, rel=1e-8)
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.7])
+def test_two_relaxation_time_form_is_the_same_collision(orc, tau):
+    # the velocity-space TRT form (pairs of opposite velocities, even part at 1/tau, odd
+    # part at s_q, incompressible equilibrium) against the moment-space MRT, away from
+    # rho = 1 and with a force: the same operator, to rounding
+    rng = np.random.default_rng(int(tau * 100))
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    for _ in range(6):
+        fin = w * (0.9 + 0.25 * rng.random(19))
+        F = 1e-3 * rng.standard_normal(3)
+        a, ma = orc.collide19_mrt(fin, tau, F)
+        b, mb = orc.collide19_trt(fin, tau, F)
+        assert np.allclose(a, b, rtol=0, atol=2e-15)
+        assert np.allclose(ma, mb, rtol=0, atol=1e-15)
+
+
+def test_two_relaxation_time_form_in_a_solve(orc):
+    m = W.blob_mask((7, 9, 11), 0.6, 5)
+    kw = dict(tau=0.75, force=(1e-4, 2e-5, -3e-5), fixed_steps=200, check_every=50)
+    a = orc.flow_solve(m, collision=orc.MRT, **kw)
+    b = orc.flow_solve(m, collision=orc.TRT, **kw)
+    assert np.abs(a["u"] - b["u"]).max() <= 1e-12 * np.abs(a["u"]).max()
+    assert b["k_lattice"] == pytest.approx(a["k_lattice"], rel=1e-12)
