@@ -81,6 +81,11 @@ typedef int32_t lbm_status;
                              s_q = 8 (2 tau - 1)/(8 tau - 1) (m4, m6, m8, m16-m18), equilibrium
                              moments A1-A9 with rho0 = 1; the body force as Guo's source in
                              moment space scaled by (1 - s_k/2) */
+#define LBM_COLLIDE_TRT 2 /* the same collision in velocity space: Eq. 7 relaxes the even
+                             moments at 1/tau and the odd ones at s_q, so each pair of
+                             opposite velocities splits into an even part (rate 1/tau) and an
+                             odd part (rate s_q) around the incompressible equilibrium; equal to
+                             LBM_COLLIDE_MRT up to rounding, at the cost of BGK */
 
 /* sweep kernel variant (the `variant` field of the solve parameters): 0 lets the library
  * choose from the working-set size; otherwise LBM_VARIANT_EXPLICIT plus any of
@@ -228,7 +233,7 @@ typedef struct {
     int32_t resume;       /* 1: continue from the state in the workspace */
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
     int32_t with_rho;     /* 1: u_init / u_out carry rho - 1 as a fourth plane */
-    int32_t collision;    /* LBM_COLLIDE_BGK or LBM_COLLIDE_MRT */
+    int32_t collision;    /* LBM_COLLIDE_BGK, LBM_COLLIDE_MRT or LBM_COLLIDE_TRT */
 } lbm_flow_params;
 
 typedef struct {

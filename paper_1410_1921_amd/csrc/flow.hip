@@ -256,9 +256,42 @@ __device__ inline void mrt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
     }
 }
 
+// The same collision in its two-relaxation-time form (Eq. 7 relaxes every even
+// non-conserved moment at 1/tau and every odd one at s_q, towards the incompressible
+// equilibrium of Appendix A): for each pair of opposite velocities the even part of the
+// offsets relaxes at s+ = 1/tau towards w_i [drho + 9/2 (e.j)^2 - 3/2 j^2], the odd part
+// at s- = s_q towards 3 w_i e.j (j = rho u including F/2); Guo's source splits alike,
+// each part scaled by (1 - s/2).  fpre = 1 - s+/2.
+template <class R>
+__device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R ux, R uy, R uz,
+                                   R Fx, R Fy, R Fz, R s_nu, R s_q, R fpre, R (&out)[19]) {
+    LBM_D3Q19_TABLES
+    const R W0 = R(1) / R(3), W1 = R(1) / R(18), W2 = R(1) / R(36);
+    const R jj15 = R(1.5) * (jx * jx + jy * jy + jz * jz);
+    const R uF3 = R(3) * (ux * Fx + uy * Fy + uz * Fz);
+    const R mpre = R(1) - R(0.5) * s_q;
+    out[0] = f[0] - s_nu * (f[0] - W0 * (drho - jj15)) - fpre * W0 * uF3;
+#pragma unroll
+    for (int i = 1; i < 19; i++) {
+        if (OPP[i] < i) continue;  // each pair once, from its first member
+        const int k = OPP[i];
+        const R w = i < 7 ? W1 : W2;
+        const R ej = EX[i] * jx + EY[i] * jy + EZ[i] * jz;
+        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
+        const R even = R(0.5) * (f[i] + f[k]) - w * (drho + R(4.5) * ej * ej - jj15);
+        const R odd = R(0.5) * (f[i] - f[k]) - w * R(3) * ej;
+        const R se = fpre * w * (R(9) * eu * eF - uF3);
+        const R so = mpre * w * R(3) * eF;
+        const R de = se - s_nu * even, dd = so - s_q * odd;
+        out[i] = f[i] + de + dd;
+        out[k] = f[k] + de - dd;
+    }
+}
+
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
-template <class P, bool CHECK, bool NT, bool MRT>
+template <class P, bool CHECK, bool NT, int COLL>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
                               const int (&ids)[19], double (&acc)[kFlowSums]) {
     using T = typename P::T;
@@ -301,9 +334,12 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
     const R ux = mx * inv, uy = my * inv, uz = mz * inv;
     R posts[19];
-    if constexpr (MRT) {
+    if constexpr (COLL == LBM_COLLIDE_MRT) {
         mrt_collide<R>(f, drho, mx, my, mz, ux, uy, uz, Fx, Fy, Fz, omega, par<R>(a.sq, a.sq_d),
                        posts);
+    } else if constexpr (COLL == LBM_COLLIDE_TRT) {
+        trt_collide<R>(f, drho, mx, my, mz, ux, uy, uz, Fx, Fy, Fz, omega, par<R>(a.sq, a.sq_d),
+                       fpre, posts);
     } else {
         const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
         const R uF = ux * Fx + uy * Fy + uz * Fz;
@@ -366,7 +402,7 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
 
 // The update of fluid node n (n < a.nf): its coordinates, the 18 pull sources from the
 // rank map (one batch of loads), then node19.
-template <class P, bool CHECK, bool NT, bool MRT>
+template <class P, bool CHECK, bool NT, int COLL>
 __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[kFlowSums]) {
     LBM_D3Q19_TABLES
     const uint32_t c = a.coords[n];
@@ -393,17 +429,17 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
     ids[0] = 0;
 #pragma unroll
     for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
-    node19<P, CHECK, NT, MRT>(a, n, x, y, z, ids, acc);
+    node19<P, CHECK, NT, COLL>(a, n, x, y, z, ids, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
 // sums of the convergence check and writes the velocity snapshot / field.
-template <class P, bool CHECK, bool NT, bool MRT>
+template <class P, bool CHECK, bool NT, int COLL>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
-    if (n < a.nf) sweep19_node<P, CHECK, NT, MRT>(a, n, acc);
+    if (n < a.nf) sweep19_node<P, CHECK, NT, COLL>(a, n, acc);
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
@@ -430,7 +466,7 @@ struct LatDesc {
     int64_t b0, b1;
 };
 
-template <bool CHECK, bool NT, bool MRT>
+template <bool CHECK, bool NT, int COLL>
 __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__restrict__ descs) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
@@ -451,7 +487,7 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
         b.usnap = a.usnap + 3 * n0;
         b.u_out = D.u_out;
         const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
-        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, MRT>(b, n, acc);
+        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, COLL>(b, n, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
 }
@@ -532,25 +568,26 @@ static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
     return m;
 }
 
-template <class P, bool CHECK, bool MRT>
+template <class P, bool CHECK, int COLL>
 static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep19<P, CHECK, true, MRT><<<grid, 256, 0, s>>>(a);
-    else k_sweep19<P, CHECK, false, MRT><<<grid, 256, 0, s>>>(a);
+    if (m.nt) k_sweep19<P, CHECK, true, COLL><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<P, CHECK, false, COLL><<<grid, 256, 0, s>>>(a);
 }
 
-template <bool CHECK, bool MRT>
+template <bool CHECK, int COLL>
 static void launch19c(const Sweep19 &a, const Variant19 &m, int32_t storage, hipStream_t s) {
-    if (storage == LBM_STORE_FP16) launch19p<StoreF16, CHECK, MRT>(a, m, s);
-    else if (storage == LBM_STORE_FP64) launch19p<StoreF64, CHECK, MRT>(a, m, s);
-    else launch19p<StoreF32, CHECK, MRT>(a, m, s);
+    if (storage == LBM_STORE_FP16) launch19p<StoreF16, CHECK, COLL>(a, m, s);
+    else if (storage == LBM_STORE_FP64) launch19p<StoreF64, CHECK, COLL>(a, m, s);
+    else launch19p<StoreF32, CHECK, COLL>(a, m, s);
 }
 
 template <bool CHECK>
 static void launch19(const Sweep19 &a, const Variant19 &m, int32_t storage, int32_t collision,
                      hipStream_t s) {
-    if (collision == LBM_COLLIDE_MRT) launch19c<CHECK, true>(a, m, storage, s);
-    else launch19c<CHECK, false>(a, m, storage, s);
+    if (collision == LBM_COLLIDE_MRT) launch19c<CHECK, LBM_COLLIDE_MRT>(a, m, storage, s);
+    else if (collision == LBM_COLLIDE_TRT) launch19c<CHECK, LBM_COLLIDE_TRT>(a, m, storage, s);
+    else launch19c<CHECK, LBM_COLLIDE_BGK>(a, m, storage, s);
 }
 
 static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, const FlowHeader &h,
@@ -631,7 +668,9 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
     LBM_REQUIRE(p->with_rho == 0 || p->with_rho == 1, LBM_E_INVAL, "with_rho must be 0 or 1");
-    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT, LBM_E_INVAL,
+    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT ||
+                    p->collision == LBM_COLLIDE_TRT,
+                LBM_E_INVAL,
                 "unknown collision %d", p->collision);
     st = check_device();
     if (st != LBM_OK) return st;
@@ -910,11 +949,14 @@ static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision,
                       const BlkDesc19 *descs, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
     if (collision == LBM_COLLIDE_MRT) {
-        if (m.nt) k_sweep19b<CHECK, true, true><<<grid, 256, 0, s>>>(a, descs);
-        else k_sweep19b<CHECK, false, true><<<grid, 256, 0, s>>>(a, descs);
+        if (m.nt) k_sweep19b<CHECK, true, LBM_COLLIDE_MRT><<<grid, 256, 0, s>>>(a, descs);
+        else k_sweep19b<CHECK, false, LBM_COLLIDE_MRT><<<grid, 256, 0, s>>>(a, descs);
+    } else if (collision == LBM_COLLIDE_TRT) {
+        if (m.nt) k_sweep19b<CHECK, true, LBM_COLLIDE_TRT><<<grid, 256, 0, s>>>(a, descs);
+        else k_sweep19b<CHECK, false, LBM_COLLIDE_TRT><<<grid, 256, 0, s>>>(a, descs);
     } else {
-        if (m.nt) k_sweep19b<CHECK, true, false><<<grid, 256, 0, s>>>(a, descs);
-        else k_sweep19b<CHECK, false, false><<<grid, 256, 0, s>>>(a, descs);
+        if (m.nt) k_sweep19b<CHECK, true, LBM_COLLIDE_BGK><<<grid, 256, 0, s>>>(a, descs);
+        else k_sweep19b<CHECK, false, LBM_COLLIDE_BGK><<<grid, 256, 0, s>>>(a, descs);
     }
 }
 
@@ -975,7 +1017,9 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 && !p->resume && !p->with_rho, LBM_E_INVAL,
                 "batched solves take binary32 storage, no resume, no density fields");
-    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT, LBM_E_INVAL,
+    LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT ||
+                    p->collision == LBM_COLLIDE_TRT,
+                LBM_E_INVAL,
                 "unknown collision %d", p->collision);
     LBM_REQUIRE((p->variant & ~(kVariantBits | LBM_VARIANT_NOGRAPH)) == 0, LBM_E_INVAL,
                 "unknown variant bits 0x%x", p->variant);

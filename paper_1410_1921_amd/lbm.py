@@ -23,7 +23,7 @@ LBM_WS_FLOW_FP16, LBM_WS_FLOW_FP64 = 4, 5
 LBM_WS_KNUDSEN_D3Q19 = 6
 LBM_LATTICE_D3Q7, LBM_LATTICE_D3Q19 = 0, 1
 LBM_STORE_FP32, LBM_STORE_FP16, LBM_STORE_FP64 = 0, 1, 2
-LBM_COLLIDE_BGK, LBM_COLLIDE_MRT = 0, 1
+LBM_COLLIDE_BGK, LBM_COLLIDE_MRT, LBM_COLLIDE_TRT = 0, 1, 2
 _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
                  LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8

@@ -107,7 +107,7 @@ def test_argument_checks_before_device(lib):
     nbad = (C.c_int32 * 3)(0, 8, 8)
     assert L.lbm_pore_diameter(nbad, dummy, 0, dummy, dummy, 1 << 20, None) == lib.LBM_E_INVAL
     # unknown storage, with_rho and collision values are rejected
-    for storage, wr, col in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 2), (0, 0, -1)):
+    for storage, wr, col in ((3, 0, 0), (-1, 0, 0), (0, 2, 0), (0, 0, 3), (0, 0, -1)):
         p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, storage, 1e-7, 1.0,
                                 0, 0, wr, col)
         assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
@@ -176,7 +176,7 @@ def test_batch_sizes_and_checks(lib):
     # binary16 / binary64 storage, resume, density planes, F_x = 0, tau <= 1/2, unknown
     # variant bits and an empty batch are rejected before any device work
     for kw in (dict(storage=1), dict(storage=2), dict(resume=1), dict(with_rho=1),
-               dict(force=(0, 1e-6, 0)), dict(tau=0.5), dict(variant=2), dict(collision=2),
+               dict(force=(0, 1e-6, 0)), dict(tau=0.5), dict(variant=2), dict(collision=3),
                dict(count=0)):
         assert call(**kw) == lib.LBM_E_INVAL, kw
 

@@ -97,3 +97,70 @@ def test_mrt_resume_needs_the_same_collision():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_flow_solve(g, fixed_steps=20, workspace=a.workspace, resume=True)
     lbm.lbm_flow_solve(g, fixed_steps=20, workspace=a.workspace, resume=True, collision=MRT)
+
+
+# ------------------------------------------------ the same collision in TRT form
+TRT = lbm.LBM_COLLIDE_TRT
+
+
+def test_trt_parity_32_against_the_mrt_oracle(orc):
+    rp = W.SMALL_32["recon"]
+    pore_g, _, _ = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                       rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    pore = pore_g.cpu().numpy()
+    kw = dict(tau=0.8, force=(1e-6, 0, 0), fixed_steps=2000, check_every=100)
+    r = lbm.lbm_flow_solve(pore_g, want_u=True, collision=TRT, **kw)
+    rm = lbm.lbm_flow_solve(pore_g, want_u=True, collision=MRT, **kw)
+    o = orc.flow_solve(pore, collision=orc.MRT, **kw)
+    assert r["k_lattice"] == pytest.approx(o["k_lattice"], rel=1e-4)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= 1e-5 * np.abs(o["u"]).max()
+    # and the GPU's moment-space form, up to binary32 rounding
+    assert r["k_lattice"] == pytest.approx(rm["k_lattice"], rel=1e-5)
+    say("trt k", r["k_lattice"], "mrt", rm["k_lattice"], "oracle", o["k_lattice"])
+
+
+@pytest.mark.parametrize("shape,seed,force", [((13, 21, 10), 3, (1e-5, 2e-6, -3e-6)),
+                                              ((1, 12, 12), 5, (1e-5, 0.0, 0.0))])
+def test_trt_parity_ragged(orc, shape, seed, force):
+    m = W.blob_mask(shape, 0.55, seed)
+    r = lbm.lbm_flow_solve(dev(m), tau=0.7, force=force, fixed_steps=300, check_every=50,
+                           want_u=True, collision=TRT)
+    o = orc.flow_solve(m, tau=0.7, force=force, fixed_steps=300, check_every=50, collision=orc.MRT)
+    u = r.field.cpu().numpy().astype(np.float64)
+    assert np.abs(u - o["u"]).max() <= 1e-5 * np.abs(o["u"]).max()
+
+
+def test_trt_binary64_populations(orc):
+    shape = (12, 10, 14)
+    m = W.blob_mask(shape, 0.5, 7)
+    tau, force = 0.9, (1e-5, -2e-6, 3e-6)
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=force, fixed_steps=200, check_every=100,
+                           storage=lbm.LBM_STORE_FP64, collision=TRT)
+    o = orc.flow_solve(m, tau=tau, force=force, fixed_steps=200, check_every=100, collision=orc.MRT,
+                       want_u=False)
+    vox = np.flatnonzero(m.reshape(-1))
+    f, flag = lbm.lbm_flow_sample(r.workspace, vox)
+    ref = o["f"].reshape(-1, 19)[vox] - W19
+    err = np.abs(f - ref).max()
+    say("trt binary64 populations worst", err)
+    assert flag.all() and err <= 1e-12
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.2])
+def test_trt_slit_is_viscosity_independent(tau):
+    h = 9
+    m = W.slit(4, h + 2, 4, h, axis=1)
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=(1e-6, 0, 0), fixed_steps=40_000, collision=TRT)
+    k = h / (h + 2) * (h * h + 0.5) / 12
+    say("trt slit tau", tau, r["k_lattice"], k)
+    assert r["k_lattice"] == pytest.approx(k, rel=1e-5)
+
+
+def test_trt_batch_equals_single():
+    fl = [dev(W.blob_mask((13, 21, 10), 0.55, 3)), dev(W.blob_mask((16, 16, 64), 0.5, 8))]
+    kw = dict(tau=0.7, force=(1e-5, 2e-6, -1e-6), fixed_steps=150, check_every=50, collision=TRT)
+    _, res, us, _ = lbm.lbm_flow_solve_batch(fl, want_u=True, **kw)
+    for l, m in enumerate(fl):
+        s = lbm.lbm_flow_solve(m, want_u=True, **kw)
+        assert torch.equal(us[l], s.field)
