@@ -579,6 +579,54 @@ static void gather19(int nx, int ny, int nz, const uint8_t *fluid, const double 
     }
 }
 
+/* The equilibrium of Eq. 3 (compressible form) of population i at rho, u. */
+static double feq19(int i, double rho, const double *u) {
+    double eu = E19[i][0] * u[0] + E19[i][1] * u[1] + E19[i][2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return w19(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+/*
+ * Pressure boundaries (Section 3.3) by Guo's non-equilibrium extrapolation: the ghost
+ * node at x = -1 (x = nx) next to boundary node b = (0, y, z) ((nx - 1, y, z)) holds the
+ * post-collision populations f_eq(rho_bc, u_b) + [f(b) - f_eq(rho_b, u_b)], with rho_b,
+ * u_b the moments of b's post-collision state (u_b = (sum f e - F/2) / rho_b, the
+ * velocity of b's collision) and f_eq that of Eq. 3.  The ghost planes continue the
+ * boundary planes' geometry: a ghost beside a solid b is solid (links to it bounce
+ * back), so walls that reach the x faces stay closed.  Population i of the ghost at
+ * (y, z), b fluid.
+ */
+static double ghost19(int nx, int ny, const uint8_t *fluid, const double *f, int xb, int y, int z,
+                      int i, double rho_bc, const double *F) {
+    int64_t b = vidx(xb, y, z, nx, ny);
+    (void)fluid;
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 19; k++) {
+        rho += f[19 * b + k];
+        for (int a = 0; a < 3; a++) j[a] += f[19 * b + k] * E19[k][a];
+    }
+    double u[3];
+    for (int a = 0; a < 3; a++) u[a] = (j[a] - 0.5 * F[a]) / rho;
+    return feq19(i, rho_bc, u) + (f[19 * b + i] - feq19(i, rho, u));
+}
+
+/* gather19 with x open: sources beyond an x face come from the ghost planes */
+static void gather19_p(int nx, int ny, int nz, const uint8_t *fluid, const double *f, int x, int y,
+                       int z, double rho_in, double rho_out, const double *F, double *fin) {
+    int64_t v = vidx(x, y, z, nx, ny);
+    for (int i = 0; i < 19; i++) {
+        int sx = x - E19[i][0], sy = wrap(y - E19[i][1], ny), sz = wrap(z - E19[i][2], nz);
+        if (sx < 0 || sx >= nx) {
+            int xb = sx < 0 ? 0 : nx - 1;
+            if (!fluid[vidx(xb, sy, sz, nx, ny)]) { fin[i] = f[19 * v + opp19(i)]; continue; }
+            fin[i] = ghost19(nx, ny, fluid, f, xb, sy, sz, i, sx < 0 ? rho_in : rho_out, F);
+            continue;
+        }
+        int64_t s = vidx(sx, sy, sz, nx, ny);
+        fin[i] = fluid[s] ? f[19 * s + i] : f[19 * v + opp19(i)];
+    }
+}
+
 /* initial populations: the D3Q19 equilibrium (Eq. 3) at rho = 1 + drho_init and u
  * (u_init planar [3][N^3], drho_init [N^3]; zero where null) */
 void orc_flow_init(int nx, int ny, int nz, const uint8_t *fluid, const double *u_init,
@@ -655,9 +703,11 @@ void orc_collide19_trt(const double *fin, double tau, const double *F, double *f
  *      [6]=sum of rho - n_fluid [7]=converged.
  * u_out (nullable): planar [3][N^3] velocity of the last step (0 at solids).
  */
-int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int collision,
-                   const double *F, int64_t max_steps, int64_t fixed_steps, int check_every,
-                   double tol, const double *u_prev0, double *f, double *u_out, double *out) {
+static int flow_solve_impl(int nx, int ny, int nz, const uint8_t *fluid, double tau,
+                           int collision, const double *F, int pressure, double rho_in,
+                           double rho_out, int64_t max_steps, int64_t fixed_steps,
+                           int check_every, double tol, const double *u_prev0, double *f,
+                           double *u_out, double *out) {
     if (!(tau > 0.5) || check_every < 1) return ORC_E_INVAL;
     int64_t nvox = (int64_t)nx * ny * nz;
     double *f0 = f; /* the caller's buffer: holds the final state on return */
@@ -688,7 +738,8 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int
                         continue;
                     }
                     double fin[19], mom[4];
-                    gather19(nx, ny, nz, fluid, f, x, y, z, fin);
+                    if (pressure) gather19_p(nx, ny, nz, fluid, f, x, y, z, rho_in, rho_out, F, fin);
+                    else gather19(nx, ny, nz, fluid, f, x, y, z, fin);
                     if (collision == 1) orc_collide19_mrt(fin, tau, NULL, F, g + 19 * v, mom);
                     else if (collision == 2) orc_collide19_trt(fin, tau, F, g + 19 * v, mom);
                     else orc_collide19(fin, tau, F, g + 19 * v, mom);
@@ -728,8 +779,11 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int
             if (fluid[v]) for (int a = 0; a < 3; a++) u_out[a * nvox + v] = ucur[a * nvox + v];
     }
     double nu = (tau - 0.5) / 3.0;
+    /* the driving: F_x, plus c_s^2 (rho_in - rho_out) over the distance between the
+       ghost planes (nx + 1) with pressure boundaries */
+    double drive = F[0] + (pressure ? (rho_in - rho_out) / (3.0 * (nx + 1)) : 0.0);
     out[0] = (double)t;
-    out[1] = nu * (sums[2] / (double)nvox) / F[0];
+    out[1] = nu * (sums[2] / (double)nvox) / drive;
     out[2] = resid;
     out[3] = sums[2] / (double)nvox;
     out[4] = sums[3] / (double)nvox;
@@ -740,6 +794,27 @@ int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int
     free(gbuf); free(uprev); free(ucur); free(pl);
     if (diverged) return ORC_E_DIVERGED;
     return status;
+}
+
+int orc_flow_solve(int nx, int ny, int nz, const uint8_t *fluid, double tau, int collision,
+                   const double *F, int64_t max_steps, int64_t fixed_steps, int check_every,
+                   double tol, const double *u_prev0, double *f, double *u_out, double *out) {
+    return flow_solve_impl(nx, ny, nz, fluid, tau, collision, F, 0, 1.0, 1.0, max_steps,
+                           fixed_steps, check_every, tol, u_prev0, f, u_out, out);
+}
+
+/*
+ * The flow solve with pressure boundaries at x = -1 (rho_in) and x = nx (rho_out)
+ * instead of periodic x (ghost planes as in ghost19; F may still add a body force).
+ * k = nu <rho u_x> / (F_x + c_s^2 (rho_in - rho_out) / (nx + 1)), the pressure drop taken
+ * between the ghost planes.  Otherwise as orc_flow_solve.
+ */
+int orc_flow_solve_p(int nx, int ny, int nz, const uint8_t *fluid, double tau, int collision,
+                     const double *F, double rho_in, double rho_out, int64_t max_steps,
+                     int64_t fixed_steps, int check_every, double tol, const double *u_prev0,
+                     double *f, double *u_out, double *out) {
+    return flow_solve_impl(nx, ny, nz, fluid, tau, collision, F, 1, rho_in, rho_out, max_steps,
+                           fixed_steps, check_every, tol, u_prev0, f, u_out, out);
 }
 
 /*

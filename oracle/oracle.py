@@ -82,6 +82,10 @@ def lib():
                                  C.c_int64, C.c_int64, C.c_int, C.c_double, _nullable(_f64p),
                                  _f64p, _nullable(_f64p), _f64p]
     L.orc_flow_solve.restype = C.c_int
+    L.orc_flow_solve_p.argtypes = [C.c_int, C.c_int, C.c_int, _u8p, C.c_double, C.c_int, _f64p,
+                                   C.c_double, C.c_double, C.c_int64, C.c_int64, C.c_int,
+                                   C.c_double, _nullable(_f64p), _f64p, _nullable(_f64p), _f64p]
+    L.orc_flow_solve_p.restype = C.c_int
     L.orc_flow_update_node.argtypes = [_u8p, _f64p, C.c_double, C.c_int, _f64p, _f64p,
                                        _nullable(_f64p)]
     L.orc_flow_update_node.restype = None
@@ -246,9 +250,11 @@ BGK, MRT, TRT = 0, 1, 2
 
 
 def flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
-               check_every=100, tol=1e-7, f=None, u_prev0=None, want_u=True, collision=BGK):
-    """Iterate the D3Q19 flow (see ``orc_flow_solve``) with the BGK or the MRT collision.
-    ``f`` (node-major state) is updated in place when given, else it starts from rest."""
+               check_every=100, tol=1e-7, f=None, u_prev0=None, want_u=True, collision=BGK,
+               pressure=None):
+    """Iterate the D3Q19 flow (see ``orc_flow_solve``) with the BGK, MRT or TRT collision.
+    ``f`` (node-major state) is updated in place when given, else it starts from rest.
+    pressure=(rho_in, rho_out): pressure boundaries in x (``orc_flow_solve_p``)."""
     fluid = np.ascontiguousarray(fluid, np.uint8)
     nz, ny, nx = fluid.shape
     if f is None:
@@ -257,8 +263,13 @@ def flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixe
     u = np.zeros((3,) + fluid.shape, np.float64) if want_u else None
     out = np.zeros(8, np.float64)
     up = None if u_prev0 is None else np.ascontiguousarray(u_prev0, np.float64)
-    st = lib().orc_flow_solve(nx, ny, nz, fluid, tau, int(collision), F, max_steps, fixed_steps,
-                              check_every, tol, up, f, u, out)
+    if pressure is None:
+        st = lib().orc_flow_solve(nx, ny, nz, fluid, tau, int(collision), F, max_steps,
+                                  fixed_steps, check_every, tol, up, f, u, out)
+    else:
+        st = lib().orc_flow_solve_p(nx, ny, nz, fluid, tau, int(collision), F, float(pressure[0]),
+                                    float(pressure[1]), max_steps, fixed_steps, check_every, tol,
+                                    up, f, u, out)
     if st < 0:
         raise OracleError(st, "flow_solve")
     return {"status": st, "steps": int(out[0]), "k_lattice": out[1], "residual": out[2],
