@@ -74,6 +74,17 @@ typedef int32_t lbm_status;
                             S max|F| in [1, 2) (1 when F = 0); collision in binary32 */
 #define LBM_STORE_FP64 2 /* binary64, collision in binary64 */
 
+/* x boundaries of the flow solve */
+#define LBM_BOUNDARY_PERIODIC 0 /* periodic in x (driven by the body force) */
+#define LBM_BOUNDARY_PRESSURE 1 /* pressure boundaries by non-equilibrium extrapolation
+                                   (Section 3.3): ghost planes at x = -1 and x = nx; the
+                                   ghost beside boundary node b holds f_eq(rho_bc, u_b) +
+                                   f(b) - f_eq(rho_b, u_b) (Eq. 3's f_eq, rho_b, u_b the
+                                   moments of b, u_b = (j - F/2)/rho_b), a ghost beside a
+                                   solid b is solid (bounce back); binary32 or binary64
+                                   storage; k = nu <rho u_x> / (F_x + (rho_in - rho_out) /
+                                   (3 (nx + 1))) */
+
 /* collision operator of the flow solve */
 #define LBM_COLLIDE_BGK 0 /* single relaxation time 1/tau (Eq. 1) */
 #define LBM_COLLIDE_MRT 1 /* the paper's MRT (Eqs. 4-7, Appendix A): moments under its Q, rates
@@ -187,8 +198,9 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
 
 /* ------------------------------------------------------------------------------
  * Flow solve (Section 3.1 with BGK, Eqs. 1-3, 8-9; half-way bounce-back at solid
- * links, Section 3.3; periodic in x, y and z).  The flow is driven by the constant
- * body-force density `force` added by Guo's scheme: u = (j + F/2)/rho and the
+ * links, Section 3.3; periodic in y and z, and in x unless `boundary` asks for the
+ * pressure boundaries of Section 3.3, see LBM_BOUNDARY_PRESSURE).  The flow is driven by
+ * the constant body-force density `force` added by Guo's scheme: u = (j + F/2)/rho and the
  * source (1 - 1/(2 tau)) w_i [3 (e_i - u) + 9 (e_i.u) e_i].F.  Starts from rho = 1
  * and u = u_init (or 0).  Every check_every steps (and at the last step) the
  * residual ||u(t) - u(t - n_c)|| / (n_c ||u(t)||) over fluid nodes is formed in
@@ -219,7 +231,9 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  * formed from the collision arithmetic and kept in binary32 (sums in binary64) for
  * every storage.
  * Errors: LBM_E_INVAL (tau <= 1/2, check_every < 1, no fluid node, N > 1024, unknown
- * storage, collision or variant bits), LBM_E_NOMEM, LBM_E_DIVERGED, LBM_E_DEVICE.
+ * storage, collision, boundary or variant bits; pressure boundaries with binary16
+ * storage, non-positive densities or no driving), LBM_E_NOMEM, LBM_E_DIVERGED,
+ * LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
     double tau;
@@ -234,6 +248,9 @@ typedef struct {
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
     int32_t with_rho;     /* 1: u_init / u_out carry rho - 1 as a fourth plane */
     int32_t collision;    /* LBM_COLLIDE_BGK, LBM_COLLIDE_MRT or LBM_COLLIDE_TRT */
+    int32_t boundary;     /* LBM_BOUNDARY_PERIODIC (0) or LBM_BOUNDARY_PRESSURE */
+    int32_t reserved;
+    double rho_in, rho_out; /* densities of the pressure boundaries (p = rho / 3) */
 } lbm_flow_params;
 
 typedef struct {

@@ -30,7 +30,7 @@
 
 namespace lbm {
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5733ull;  // "LBMFLOW3"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5734ull;  // "LBMFLOW4"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -41,8 +41,19 @@ struct FlowHeader {
     double tau, force[3];
     int32_t variant, storage;
     double scale;  // binary16 storage: stored = scale * (f_i - w_i)
-    int32_t collision, reserved;
+    int32_t collision;
+    int32_t boundary;          // LBM_BOUNDARY_*
+    double rho_in, rho_out;    // pressure boundaries
 };
+
+// Pressure boundaries: the populations entering through the inlet (e_x = +1) and the
+// outlet (e_x = -1), five each, and their slot in the ghost-plane buffer
+// [side][slot][ny nz].
+#define LBM_GHOST_TABLES                                                                   \
+    [[maybe_unused]] constexpr int GIN[5] = {1, 7, 9, 11, 13};                             \
+    [[maybe_unused]] constexpr int GOUT[5] = {2, 8, 10, 12, 14};                           \
+    [[maybe_unused]] constexpr int GSLOT[19] = {-1, 0, 0, -1, -1, -1, -1, 1, 1, 2, 2,      \
+                                                3, 3, 4, 4, -1, -1, -1, -1};
 
 // Storage policies: T is the stored type, R the collision arithmetic.
 struct StoreF32 {
@@ -106,6 +117,7 @@ struct FlowWs {
     float *drho[2];  // binary16 storage: the writers' rho - 1 (ping-pong with f)
     float *usnap;
     double *partials;
+    void *ghost;     // pressure boundaries: ghost-plane populations [2][5][ny nz]
     int64_t stride;  // distance between population arrays (elements)
     size_t bytes;
 };
@@ -133,6 +145,7 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage)
     w.drho[1] = c.take<float>(ndr);
     w.usnap = c.take<float>((size_t)3 * w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(blocks_for(nfp)) * kFlowSums);
+    w.ghost = c.take<double>((size_t)10 * g.ny * g.nz);
     w.bytes = c.off;
     return w;
 }
@@ -161,6 +174,7 @@ struct Sweep19 {
     double *__restrict__ partials;
     int update_snap;
     int with_rho;                      // u_out carries a fourth plane, rho - 1
+    const void *__restrict__ ghost;    // pressure boundaries: [2][5][ny nz] ghost populations
 };
 
 // Kernel variants (chosen per solve from the working-set size, or forced):
@@ -291,9 +305,10 @@ __device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
-template <class P, bool CHECK, bool NT, int COLL>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
-                              const int (&ids)[19], double (&acc)[kFlowSums]) {
+                              const int (&ids)[19], const int (&gidx)[19],
+                              double (&acc)[kFlowSums]) {
     using T = typename P::T;
     using R = typename P::R;
     LBM_D3Q19_TABLES
@@ -310,6 +325,13 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; i++) f[i] = from_store<P>(src[off[i]], a.inv_scale);
+    if constexpr (OPEN) {
+        // sources beyond an x face: the ghost planes of the pressure boundaries (-2)
+        const T *__restrict__ gh = static_cast<const T *>(a.ghost);
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            if (EX[i] != 0 && ids[i] == -2) f[i] = from_store<P>(gh[gidx[i]], a.inv_scale);
+    }
     if constexpr (std::is_same<T, _Float16>::value) {
         // add back w_i drho of the writer: the neighbour pulled from, or the node itself
         // for the rest population and bounced ones
@@ -402,15 +424,21 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
 
 // The update of fluid node n (n < a.nf): its coordinates, the 18 pull sources from the
 // rank map (one batch of loads), then node19.
-template <class P, bool CHECK, bool NT, int COLL>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
 __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[kFlowSums]) {
     LBM_D3Q19_TABLES
+    LBM_GHOST_TABLES
     const uint32_t c = a.coords[n];
     const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
     const Grid &g = a.g;
-    // per-axis pieces of the rank word and bit of x-1, x, x+1 (periodic), etc.
+    // per-axis pieces of the rank word and bit of x-1, x, x+1 (periodic, or with pressure
+    // boundaries the node's own x standing in beyond a face), etc.
     int xs[3], ys[3], zs[3];
-    xs[0] = x == 0 ? g.nx - 1 : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    if (OPEN) {
+        xs[0] = x == 0 ? x : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? x : x + 1;
+    } else {
+        xs[0] = x == 0 ? g.nx - 1 : x - 1; xs[1] = x; xs[2] = x == g.nx - 1 ? 0 : x + 1;
+    }
     ys[0] = y == 0 ? g.ny - 1 : y - 1; ys[1] = y; ys[2] = y == g.ny - 1 ? 0 : y + 1;
     zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
     int wx[3], wy[3], wz[3], bx[3];
@@ -425,21 +453,31 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
     RankWord rw[19];
 #pragma unroll
     for (int i = 1; i < 19; i++) rw[i] = a.rank[wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]]];
-    int ids[19];
+    int ids[19], gidx[19];
     ids[0] = 0;
 #pragma unroll
-    for (int i = 1; i < 19; i++) ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
-    node19<P, CHECK, NT, COLL>(a, n, x, y, z, ids, acc);
+    for (int i = 1; i < 19; i++) {
+        ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
+        gidx[i] = 0;
+        if (OPEN && ((EX[i] == 1 && x == 0) || (EX[i] == -1 && x == g.nx - 1))) {
+            // the source is a ghost node; its boundary node (looked up at this x) decides:
+            // fluid -> the ghost's population, solid -> bounce back
+            ids[i] = ids[i] >= 0 ? -2 : -1;
+            const int side = EX[i] == 1 ? 0 : 1;
+            gidx[i] = ((side * 5 + GSLOT[i]) * g.nz + zs[1 - EZ[i]]) * g.ny + ys[1 - EY[i]];
+        }
+    }
+    node19<P, CHECK, NT, COLL, OPEN>(a, n, x, y, z, ids, gidx, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
 // sums of the convergence check and writes the velocity snapshot / field.
-template <class P, bool CHECK, bool NT, int COLL>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
-    if (n < a.nf) sweep19_node<P, CHECK, NT, COLL>(a, n, acc);
+    if (n < a.nf) sweep19_node<P, CHECK, NT, COLL, OPEN>(a, n, acc);
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
@@ -487,9 +525,59 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
         b.usnap = a.usnap + 3 * n0;
         b.u_out = D.u_out;
         const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
-        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, COLL>(b, n, acc);
+        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, COLL, false>(b, n, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
+}
+
+// Pressure boundaries (Section 3.3), Guo's non-equilibrium extrapolation: the ghost node
+// beyond boundary node b (x = 0 or nx - 1, same y, z) holds f(b) + f_eq(rho_bc, u_b) -
+// f_eq(rho_b, u_b), with rho_b, u_b the moments of b's state (u_b = (j - F/2)/rho_b, the
+// velocity of b's collision) and f_eq of Eq. 3; only the five populations entering the
+// domain are kept, as offsets f_i - w_i, in ghost[side][slot][z ny + y].  A ghost beside a
+// solid b is solid (the sweep bounces back) and is not written.
+template <class P>
+__global__ __launch_bounds__(256) void k_ghost19(Grid g, int64_t stride,
+                                                 const RankWord *__restrict__ rank,
+                                                 const typename P::T *__restrict__ src,
+                                                 float inv_scale, float scale,
+                                                 typename P::R Fx, typename P::R Fy,
+                                                 typename P::R Fz, typename P::R drho_in,
+                                                 typename P::R drho_out,
+                                                 typename P::T *__restrict__ ghost) {
+    using R = typename P::R;
+    LBM_D3Q19_TABLES
+    LBM_GHOST_TABLES
+    const int64_t m = (int64_t)g.ny * g.nz;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= 2 * m) return;
+    const int side = (int)(t / m);
+    const int64_t yz = t % m;
+    const int y = (int)(yz % g.ny), z = (int)(yz / g.ny);
+    const int id = node_at(rank, g, side ? g.nx - 1 : 0, y, z);
+    if (id < 0) return;
+    R f[19], drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < 19; i++) {
+        f[i] = from_store<P>(src[(int64_t)i * stride + id], inv_scale);
+        drho += f[i];
+        jx += EX[i] * f[i];
+        jy += EY[i] * f[i];
+        jz += EZ[i] * f[i];
+    }
+    // the density jump from the offsets (rho_bc - 1) - (rho_b - 1): both near 0, so
+    // binary32 keeps it to rounding (rho_bc - rho_b formed near 1 would lose ~1e-7)
+    const R rho = R(1) + drho, jump = (side ? drho_out : drho_in) - drho;
+    const R ux = (jx - R(0.5) * Fx) / rho, uy = (jy - R(0.5) * Fy) / rho, uz = (jz - R(0.5) * Fz) / rho;
+    const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        const int i = side ? GOUT[k] : GIN[k];
+        const R w = i < 7 ? R(1) / R(18) : R(1) / R(36);
+        const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+        const R v = f[i] + w * jump * (R(1) + R(3) * eu + R(4.5) * eu * eu - uu15);
+        ghost[(side * 5 + k) * m + yz] = to_store<P>(v, scale);
+    }
 }
 
 // f - w_i at the equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x,
@@ -571,8 +659,15 @@ static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
 template <class P, bool CHECK, int COLL>
 static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
-    if (m.nt) k_sweep19<P, CHECK, true, COLL><<<grid, 256, 0, s>>>(a);
-    else k_sweep19<P, CHECK, false, COLL><<<grid, 256, 0, s>>>(a);
+    if constexpr (!std::is_same<P, StoreF16>::value) {
+        if (a.ghost) {  // pressure boundaries
+            if (m.nt) k_sweep19<P, CHECK, true, COLL, true><<<grid, 256, 0, s>>>(a);
+            else k_sweep19<P, CHECK, false, COLL, true><<<grid, 256, 0, s>>>(a);
+            return;
+        }
+    }
+    if (m.nt) k_sweep19<P, CHECK, true, COLL, false><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<P, CHECK, false, COLL, false><<<grid, 256, 0, s>>>(a);
 }
 
 template <bool CHECK, int COLL>
@@ -618,11 +713,28 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
     a.partials = w.partials;
     a.update_snap = 1;
     a.with_rho = with_rho;
+    const bool open = h.boundary == LBM_BOUNDARY_PRESSURE;
+    a.ghost = open ? w.ghost : nullptr;
+    const unsigned gblocks = (unsigned)((2 * (int64_t)g.ny * g.nz + 255) / 256);
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
         a.drho_src = w.drho[cur];
         a.drho_dst = w.drho[cur ^ 1];
+        if (open) {  // the ghost planes of this step, from the state it reads
+            if (h.storage == LBM_STORE_FP64)
+                k_ghost19<StoreF64><<<gblocks, 256, 0, s>>>(
+                    g, w.stride, w.rank, static_cast<const double *>(a.src), 1.f, 1.f,
+                    h.force[0], h.force[1], h.force[2], h.rho_in - 1.0, h.rho_out - 1.0,
+                    static_cast<double *>(w.ghost));
+            else
+                k_ghost19<StoreF32><<<gblocks, 256, 0, s>>>(
+                    g, w.stride, w.rank, static_cast<const float *>(a.src), 1.f, 1.f,
+                    (float)h.force[0], (float)h.force[1], (float)h.force[2],
+                    (float)(h.rho_in - 1.0), (float)(h.rho_out - 1.0),
+                    static_cast<float *>(w.ghost));
+            LBM_CHECK_LAUNCH();
+        }
         if (check_last && t == steps - 1)
             launch19<true>(a, m, h.storage, h.collision, s);
         else
@@ -672,6 +784,17 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
                     p->collision == LBM_COLLIDE_TRT,
                 LBM_E_INVAL,
                 "unknown collision %d", p->collision);
+    LBM_REQUIRE(p->boundary == LBM_BOUNDARY_PERIODIC || p->boundary == LBM_BOUNDARY_PRESSURE,
+                LBM_E_INVAL, "unknown boundary %d", p->boundary);
+    if (p->boundary == LBM_BOUNDARY_PRESSURE) {
+        LBM_REQUIRE(p->storage != LBM_STORE_FP16, LBM_E_INVAL,
+                    "pressure boundaries take binary32 or binary64 storage");
+        LBM_REQUIRE(p->rho_in > 0 && p->rho_out > 0 && std::isfinite(p->rho_in) &&
+                        std::isfinite(p->rho_out),
+                    LBM_E_INVAL, "boundary densities must be positive");
+        LBM_REQUIRE(p->force[0] + (p->rho_in - p->rho_out) / (3.0 * (n[0] + 1)) != 0.0,
+                    LBM_E_INVAL, "no driving along x (F_x and rho_in - rho_out)");
+    }
     st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -699,7 +822,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
         LBM_TRY_HIP(hipStreamSynchronize(s));
         LBM_REQUIRE(h.magic == kFlowMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
-                        h.n_fluid == nf && h.storage == p->storage && h.collision == p->collision,
+                        h.n_fluid == nf && h.storage == p->storage &&
+                        h.collision == p->collision && h.boundary == p->boundary,
                     LBM_E_INVAL,
                     "resume: the workspace holds no state for this geometry and storage");
         t0 = h.steps_done;
@@ -714,7 +838,9 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     h.variant = p->variant;
     h.storage = p->storage;
     h.collision = p->collision;
-    h.reserved = 0;
+    h.boundary = p->boundary;
+    h.rho_in = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_in : 1.0;
+    h.rho_out = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_out : 1.0;
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
         // binary16: a power of two S with S max|F| in [1, 2) (1 without a force)
@@ -808,7 +934,12 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     r->residual = resid;
     for (int a = 0; a < 3; a++) r->mean_rho_u[a] = sums[2 + a] / nvox;
     r->mass_dev = sums[5];
-    r->k_lattice = nu * r->mean_rho_u[0] / p->force[0];
+    // the driving: F_x, plus c_s^2 (rho_in - rho_out) over the nx + 1 spacings between the
+    // ghost planes of pressure boundaries
+    const double drive = p->force[0] + (h.boundary == LBM_BOUNDARY_PRESSURE
+                                            ? (h.rho_in - h.rho_out) / (3.0 * (g.nx + 1))
+                                            : 0.0);
+    r->k_lattice = nu * r->mean_rho_u[0] / drive;
     const double dx = p->voxel_nm * 1e-9;
     r->k_m2 = r->k_lattice * dx * dx;
     r->k_mD = r->k_m2 / 9.869233e-16;
@@ -1024,6 +1155,8 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     LBM_REQUIRE((p->variant & ~(kVariantBits | LBM_VARIANT_NOGRAPH)) == 0, LBM_E_INVAL,
                 "unknown variant bits 0x%x", p->variant);
     LBM_REQUIRE(p->force[0] != 0.0, LBM_E_INVAL, "batched solves report k along x: F_x must be nonzero");
+    LBM_REQUIRE(p->boundary == LBM_BOUNDARY_PERIODIC, LBM_E_INVAL,
+                "batched solves are periodic in x (no pressure boundaries)");
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     const BatchWs w = carve_batch(workspace, count, n_h, nf_h);

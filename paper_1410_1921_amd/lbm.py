@@ -24,6 +24,7 @@ LBM_WS_KNUDSEN_D3Q19 = 6
 LBM_LATTICE_D3Q7, LBM_LATTICE_D3Q19 = 0, 1
 LBM_STORE_FP32, LBM_STORE_FP16, LBM_STORE_FP64 = 0, 1, 2
 LBM_COLLIDE_BGK, LBM_COLLIDE_MRT, LBM_COLLIDE_TRT = 0, 1, 2
+LBM_BOUNDARY_PERIODIC, LBM_BOUNDARY_PRESSURE = 0, 1
 _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
                  LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
@@ -60,7 +61,9 @@ class lbm_flow_params(C.Structure):
     _fields_ = [("tau", C.c_double), ("force", C.c_double * 3), ("max_steps", C.c_int64),
                 ("fixed_steps", C.c_int64), ("check_every", C.c_int32), ("storage", C.c_int32),
                 ("tol", C.c_double), ("voxel_nm", C.c_double), ("resume", C.c_int32),
-                ("variant", C.c_int32), ("with_rho", C.c_int32), ("collision", C.c_int32)]
+                ("variant", C.c_int32), ("with_rho", C.c_int32), ("collision", C.c_int32),
+                ("boundary", C.c_int32), ("reserved", C.c_int32), ("rho_in", C.c_double),
+                ("rho_out", C.c_double)]
 
 
 class lbm_flow_result(C.Structure):
@@ -319,9 +322,10 @@ class Solve:
 def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, fixed_steps=0,
                    check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False, u_init=None,
                    workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
-                   storage=LBM_STORE_FP32, with_rho=False, collision=LBM_COLLIDE_BGK):
+                   storage=LBM_STORE_FP32, with_rho=False, collision=LBM_COLLIDE_BGK,
+                   pressure=None):
     """D3Q19 flow solve.  With with_rho the velocity field (want_u) and u_init carry a
-    fourth plane, rho - 1."""
+    fourth plane, rho - 1.  pressure=(rho_in, rho_out): pressure boundaries in x."""
     _vol(fluid, torch.uint8, "fluid")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
@@ -329,9 +333,11 @@ def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, 
         workspace = Workspace(lbm_workspace_size(_WS_FLOW_KIND.get(storage, LBM_WS_FLOW),
                                                  fluid.shape, n_fluid), fluid.device)
     planes = 4 if with_rho else 3
+    bc = LBM_BOUNDARY_PERIODIC if pressure is None else LBM_BOUNDARY_PRESSURE
+    rho_in, rho_out = (1.0, 1.0) if pressure is None else (float(pressure[0]), float(pressure[1]))
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
                         int(storage), tol, voxel_nm, int(bool(resume)), int(variant),
-                        int(bool(with_rho)), int(collision))
+                        int(bool(with_rho)), int(collision), bc, 0, rho_in, rho_out)
     r = lbm_flow_result()
     u = torch.empty((planes,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
         if want_u else None

@@ -112,6 +112,14 @@ def test_argument_checks_before_device(lib):
                                 0, 0, wr, col)
         assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
                                 None) == lib.LBM_E_INVAL
+    # unknown boundaries, pressure boundaries with binary16 storage, non-positive
+    # densities or no driving
+    for storage, bc, rin, rout in ((0, 2, 1.0, 1.0), (1, 1, 1.01, 1.0), (0, 1, 0.0, 1.0),
+                                   (0, 1, 1.0, 1.0)):
+        p = lib.lbm_flow_params(0.8, (C.c_double * 3)(0, 0, 0), 10, 0, 10, storage, 1e-7, 1.0,
+                                0, 0, 0, 0, bc, 0, rin, rout)
+        assert L.lbm_flow_solve(n, dummy, C.byref(p), C.byref(r), None, None, dummy, 1 << 20,
+                                None) == lib.LBM_E_INVAL
     # variant bits other than EXPLICIT | REMAP | NTSTORE are rejected by both solves
     for bad in (2, 16, 1 << 20, -1):
         p = lib.lbm_flow_params(0.8, (C.c_double * 3)(1e-6, 0, 0), 10, 0, 10, 0, 1e-7, 1.0, 0, bad)
@@ -164,18 +172,20 @@ def test_batch_sizes_and_checks(lib):
 
     def call(count=2, **kw):
         a = dict(tau=0.8, force=(1e-6, 0, 0), max_steps=10, fixed_steps=0, check_every=10,
-                 storage=0, tol=1e-7, voxel_nm=1.0, resume=0, variant=0, with_rho=0, collision=0)
+                 storage=0, tol=1e-7, voxel_nm=1.0, resume=0, variant=0, with_rho=0, collision=0,
+                 boundary=0)
         a.update(kw)
         p = lib.lbm_flow_params(a["tau"], (C.c_double * 3)(*a["force"]), a["max_steps"],
                                 a["fixed_steps"], a["check_every"], a["storage"], a["tol"],
                                 a["voxel_nm"], a["resume"], a["variant"], a["with_rho"],
-                                a["collision"])
+                                a["collision"], a["boundary"], 0, 1.01, 1.0)
         return L.lbm_flow_solve_batch(count, n, masks, nf, C.byref(p), None, res, None, dummy,
                                       1 << 30, None)
 
     # binary16 / binary64 storage, resume, density planes, F_x = 0, tau <= 1/2, unknown
     # variant bits and an empty batch are rejected before any device work
     for kw in (dict(storage=1), dict(storage=2), dict(resume=1), dict(with_rho=1),
+               dict(boundary=1),
                dict(force=(0, 1e-6, 0)), dict(tau=0.5), dict(variant=2), dict(collision=3),
                dict(count=0)):
         assert call(**kw) == lib.LBM_E_INVAL, kw
