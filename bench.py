@@ -39,10 +39,10 @@ COUNTERS = {
         workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15338.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="567ff54ea4aac6bc"),
-    "k_sweep19<StoreF32, false, true, 0>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2141860.7, write_kib=2490368.6,
+    "k_sweep19<StoreF32, false, true, 0, false>": dict(
+        workload="recon512_eps0.25_d16", fetch_kib=2141861.5, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="b513f7871dd4d374"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="f2bd968d4fd97a14"),
 }
 
 
@@ -175,7 +175,7 @@ def roofline_512(lbm, W, steps):
     ms_trt = e0.elapsed_time(e1) / steps
     del r, pore
     torch.cuda.empty_cache()
-    name = "k_sweep19<StoreF32, false, true, 0>"
+    name = "k_sweep19<StoreF32, false, true, 0, false>"
     return {"kernel": name, "workload": w["name"], "n_fluid": nf,
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_gb(name, w["name"]),
@@ -183,10 +183,10 @@ def roofline_512(lbm, W, steps):
             "mlups": nf / (ms * 1e3),
             "fp16": {"ms_per_launch": ms16, "mlups": nf / (ms16 * 1e3),
                      "achieved": round(nf * 84 / (ms16 * 1e-3) / 1e9, 1)},
-            "mrt": {"kernel": "k_sweep19<StoreF32, false, true, 1>",
+            "mrt": {"kernel": "k_sweep19<StoreF32, false, true, 1, false>",
                     "ms_per_launch": ms_mrt, "mlups": nf / (ms_mrt * 1e3),
                     "achieved": round(nf * BYTES_D3Q19 / (ms_mrt * 1e-3) / 1e9, 1)},
-            "trt": {"kernel": "k_sweep19<StoreF32, false, true, 2>",
+            "trt": {"kernel": "k_sweep19<StoreF32, false, true, 2, false>",
                     "ms_per_launch": ms_trt, "mlups": nf / (ms_trt * 1e3),
                     "achieved": round(nf * BYTES_D3Q19 / (ms_trt * 1e-3) / 1e9, 1)}}
 
@@ -489,7 +489,7 @@ def main():
     if kn_ms >= fl_ms:
         name, per, bpu, ms = "k_sweep7<false, false>", kn_ms / kn_n, BYTES_D3Q7, kn_ms
     else:
-        name, per, bpu, ms = ("k_sweep19<StoreF32, false, false, 0>", fl_ms / fl_n,
+        name, per, bpu, ms = ("k_sweep19<StoreF32, false, false, 0, false>", fl_ms / fl_n,
                               BYTES_D3Q19, fl_ms)
     achieved = nf * bpu / (per * 1e-3) / 1e9
     roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
