@@ -35,11 +35,11 @@ BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_
 # only while the kernel's sources are those that were profiled (hash of the files).
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 COUNTERS = {
-    "k_sweep7<false, false>": dict(
+    "k_sweep7<false, false, unsigned int>": dict(
         workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15338.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="567ff54ea4aac6bc"),
-    "k_sweep19<StoreF32, false, true, 0, false>": dict(
+    "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
         workload="recon512_eps0.25_d16", fetch_kib=2141861.5, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="f2bd968d4fd97a14"),
@@ -175,7 +175,7 @@ def roofline_512(lbm, W, steps):
     ms_trt = e0.elapsed_time(e1) / steps
     del r, pore
     torch.cuda.empty_cache()
-    name = "k_sweep19<StoreF32, false, true, 0, false>"
+    name = "k_sweep19<StoreF32, false, true, 0, false, unsigned int>"
     return {"kernel": name, "workload": w["name"], "n_fluid": nf,
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic_gb(name, w["name"]),
@@ -183,10 +183,10 @@ def roofline_512(lbm, W, steps):
             "mlups": nf / (ms * 1e3),
             "fp16": {"ms_per_launch": ms16, "mlups": nf / (ms16 * 1e3),
                      "achieved": round(nf * 84 / (ms16 * 1e-3) / 1e9, 1)},
-            "mrt": {"kernel": "k_sweep19<StoreF32, false, true, 1, false>",
+            "mrt": {"kernel": "k_sweep19<StoreF32, false, true, 1, false, unsigned int>",
                     "ms_per_launch": ms_mrt, "mlups": nf / (ms_mrt * 1e3),
                     "achieved": round(nf * BYTES_D3Q19 / (ms_mrt * 1e-3) / 1e9, 1)},
-            "trt": {"kernel": "k_sweep19<StoreF32, false, true, 2, false>",
+            "trt": {"kernel": "k_sweep19<StoreF32, false, true, 2, false, unsigned int>",
                     "ms_per_launch": ms_trt, "mlups": nf / (ms_trt * 1e3),
                     "achieved": round(nf * BYTES_D3Q19 / (ms_trt * 1e-3) / 1e9, 1)}}
 
@@ -352,7 +352,7 @@ def diffusion19_sweeps(lbm, w, steps):
         out[name] = {"ms_per_launch": per, "mlups": round(kr["mlups"], 1),
                      "achieved_gbs": round(kr["n_fluid"] * bpu / (per * 1e-3) / 1e9, 1),
                      "bytes_per_update": bpu}
-    out["d3q19"]["kernel"] = "k_sweep19d<false, false>"
+    out["d3q19"]["kernel"] = "k_sweep19d<false, false, unsigned int>"
     return out
 
 
@@ -487,9 +487,9 @@ def main():
     fl_n = sum(r["flow"]["steps"] for r in runs)
     kn_n = sum(r["knudsen"]["steps"] for r in runs)
     if kn_ms >= fl_ms:
-        name, per, bpu, ms = "k_sweep7<false, false>", kn_ms / kn_n, BYTES_D3Q7, kn_ms
+        name, per, bpu, ms = "k_sweep7<false, false, unsigned int>", kn_ms / kn_n, BYTES_D3Q7, kn_ms
     else:
-        name, per, bpu, ms = ("k_sweep19<StoreF32, false, false, 0, false>", fl_ms / fl_n,
+        name, per, bpu, ms = ("k_sweep19<StoreF32, false, false, 0, false, unsigned int>", fl_ms / fl_n,
                               BYTES_D3Q19, fl_ms)
     achieved = nf * bpu / (per * 1e-3) / 1e9
     roof = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -104,13 +104,20 @@ typedef int32_t lbm_status;
  *   LBM_VARIANT_NTSTORE non-temporal (streaming) population stores
  * All variants compute identical results; they differ only in speed.  Any other bit
  * (2 included) is rejected with LBM_E_INVAL.  A batched solve without
- * LBM_VARIANT_EXPLICIT chooses the variant of each of its groups from the group's size. */
+ * LBM_VARIANT_EXPLICIT chooses the variant of each of its groups from the group's size.
+ * Population offsets (direction x stride + node) are 32-bit while q x stride fits in
+ * 32 bits (stride: the fluid-node count rounded up to 64; q = 19 for the flow and the
+ * D3Q19 mass transport, 7 for D3Q7), which keeps the sweeps' register count down, and
+ * 64-bit beyond, so that a 1024^3 domain of any porosity is solved; LBM_VARIANT_OFF64
+ * asks for the 64-bit kernels on any size (single-lattice solves, with or without
+ * LBM_VARIANT_EXPLICIT; identical results). */
 #define LBM_VARIANT_AUTO 0
 #define LBM_VARIANT_EXPLICIT 1
 #define LBM_VARIANT_REMAP 4
 #define LBM_VARIANT_NTSTORE 8
 #define LBM_VARIANT_NOGRAPH 16 /* batched solves only: launch each step from the host
                                   instead of replaying a captured check interval */
+#define LBM_VARIANT_OFF64 32 /* single-lattice solves only: 64-bit population offsets */
 
 /* ------------------------------------------------------------------------------
  * Reconstruction (Section 2, Steps 1-3): pore spheres with random centres and

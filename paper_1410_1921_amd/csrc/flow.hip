@@ -305,7 +305,7 @@ __device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
-template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
                               const int (&ids)[19], const int (&gidx)[19],
                               double (&acc)[kFlowSums]) {
@@ -317,11 +317,13 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const R omega = par<R>(a.omega, a.omega_d), fpre = par<R>(a.fpre, a.fpre_d);
     const R Fx = par<R>(a.Fx, a.Fd[0]), Fy = par<R>(a.Fy, a.Fd[1]), Fz = par<R>(a.Fz, a.Fd[2]);
-    uint32_t off[19];
-    off[0] = (uint32_t)n;
+    // element offsets i * stride + node: 32-bit while 19 * stride fits (fewer registers),
+    // 64-bit beyond
+    Off off[19];
+    off[0] = (Off)n;
 #pragma unroll
     for (int i = 1; i < 19; i++)
-        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+        off[i] = ids[i] >= 0 ? (Off)(i * a.stride + ids[i]) : (Off)(OPP[i] * a.stride + n);
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; i++) f[i] = from_store<P>(src[off[i]], a.inv_scale);
@@ -424,7 +426,7 @@ __device__ inline void write_partials(double (&acc)[NV], int64_t row, bool valid
 
 // The update of fluid node n (n < a.nf): its coordinates, the 18 pull sources from the
 // rank map (one batch of loads), then node19.
-template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[kFlowSums]) {
     LBM_D3Q19_TABLES
     LBM_GHOST_TABLES
@@ -467,17 +469,17 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
             gidx[i] = ((side * 5 + GSLOT[i]) * g.nz + zs[1 - EZ[i]]) * g.ny + ys[1 - EY[i]];
         }
     }
-    node19<P, CHECK, NT, COLL, OPEN>(a, n, x, y, z, ids, gidx, acc);
+    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
 // sums of the convergence check and writes the velocity snapshot / field.
-template <class P, bool CHECK, bool NT, int COLL, bool OPEN>
+template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __global__ __launch_bounds__(256) void k_sweep19(Sweep19 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kFlowSums] = {0, 0, 0, 0, 0, 0};
-    if (n < a.nf) sweep19_node<P, CHECK, NT, COLL, OPEN>(a, n, acc);
+    if (n < a.nf) sweep19_node<P, CHECK, NT, COLL, OPEN, Off>(a, n, acc);
     if (CHECK) write_partials<kFlowSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
         b.usnap = a.usnap + 3 * n0;
         b.u_out = D.u_out;
         const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
-        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, COLL, false>(b, n, acc);
+        if (n < D.nf) sweep19_node<StoreF32, CHECK, NT, COLL, false, uint32_t>(b, n, acc);
     }
     if (CHECK) write_partials<kFlowSums>(acc, pb, live, a.partials);
 }
@@ -641,10 +643,12 @@ __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
 // cache (XCD-contiguous order, ordinary stores).
 struct Variant19 {
     bool remap, nt;
+    bool wide;  // 64-bit population offsets
 };
 
 static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
     Variant19 m;
+    m.wide = (v & LBM_VARIANT_OFF64) || 19 * stride > (int64_t)UINT32_MAX;
     if (v & LBM_VARIANT_EXPLICIT) {
         m.remap = v & LBM_VARIANT_REMAP;
         m.nt = v & LBM_VARIANT_NTSTORE;
@@ -656,18 +660,24 @@ static Variant19 pick_variant(int32_t v, int64_t stride, int32_t storage) {
     return m;
 }
 
-template <class P, bool CHECK, int COLL>
-static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
+template <class P, bool CHECK, int COLL, class Off>
+static void launch19o(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
     if constexpr (!std::is_same<P, StoreF16>::value) {
         if (a.ghost) {  // pressure boundaries
-            if (m.nt) k_sweep19<P, CHECK, true, COLL, true><<<grid, 256, 0, s>>>(a);
-            else k_sweep19<P, CHECK, false, COLL, true><<<grid, 256, 0, s>>>(a);
+            if (m.nt) k_sweep19<P, CHECK, true, COLL, true, Off><<<grid, 256, 0, s>>>(a);
+            else k_sweep19<P, CHECK, false, COLL, true, Off><<<grid, 256, 0, s>>>(a);
             return;
         }
     }
-    if (m.nt) k_sweep19<P, CHECK, true, COLL, false><<<grid, 256, 0, s>>>(a);
-    else k_sweep19<P, CHECK, false, COLL, false><<<grid, 256, 0, s>>>(a);
+    if (m.nt) k_sweep19<P, CHECK, true, COLL, false, Off><<<grid, 256, 0, s>>>(a);
+    else k_sweep19<P, CHECK, false, COLL, false, Off><<<grid, 256, 0, s>>>(a);
+}
+
+template <class P, bool CHECK, int COLL>
+static void launch19p(const Sweep19 &a, const Variant19 &m, hipStream_t s) {
+    if (m.wide || 19 * a.stride > (int64_t)UINT32_MAX) launch19o<P, CHECK, COLL, int64_t>(a, m, s);
+    else launch19o<P, CHECK, COLL, uint32_t>(a, m, s);
 }
 
 template <bool CHECK, int COLL>
@@ -777,7 +787,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 || p->storage == LBM_STORE_FP16 ||
                     p->storage == LBM_STORE_FP64,
                 LBM_E_INVAL, "unknown storage %d", p->storage);
-    LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
+    LBM_REQUIRE((p->variant & ~kSolveVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
     LBM_REQUIRE(p->with_rho == 0 || p->with_rho == 1, LBM_E_INVAL, "with_rho must be 0 or 1");
     LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT ||
@@ -809,8 +819,6 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     FlowWs w = carve_flow(workspace, g, nf, p->storage);
-    LBM_REQUIRE(19 * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
-                "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
                 "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
                 (long long)nf);

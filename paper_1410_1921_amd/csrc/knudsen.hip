@@ -143,17 +143,18 @@ struct Sweep7 {
 // The update of fluid node n at (x, y, z) with its 6 pull sources resolved: ids[i] is the
 // node at x - e_i, -1 when that voxel is solid (bounce back), -2 beyond an x face (ghost
 // plane).
-template <bool CHECK, bool NT>
+template <bool CHECK, bool NT, class Off>
 __device__ inline void node7(const Sweep7 &a, int64_t n, int x, int y, int z, const int (&ids)[7],
                              double (&acc)[kKnSums]) {
     LBM_D3Q7_TABLES
     const float om = a.omega[n];
     const Shift sh = a.shift[x + 1];
-    uint32_t off[7];
-    off[0] = (uint32_t)n;
+    // element offsets i * stride + node: 32-bit while q * stride fits, 64-bit beyond
+    Off off[7];
+    off[0] = (Off)n;
 #pragma unroll
     for (int i = 1; i < 7; i++)
-        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+        off[i] = ids[i] >= 0 ? (Off)(i * a.stride + ids[i]) : (Off)(OPP[i] * a.stride + n);
     float ai[7];
 #pragma unroll
     for (int i = 0; i < 7; i++) ai[i] = a.src[off[i]];
@@ -206,7 +207,7 @@ __device__ inline void write_partials7(double (&acc)[NV], int64_t row, bool vali
 }
 
 // The update of fluid node n: its 6 pull sources through the rank map.
-template <bool CHECK, bool NT>
+template <bool CHECK, bool NT, class Off>
 __device__ inline void sweep7_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
     const uint32_t c = a.coords[n];
     const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
@@ -229,16 +230,16 @@ __device__ inline void sweep7_node(const Sweep7 &a, int64_t n, double (&acc)[kKn
     for (int i = 1; i < 7; i++) ids[i] = rank_lookup(rw[i], nxs[i] & (kSeg - 1));
     if (xm < 0) ids[1] = -2;
     if (xp >= g.nx) ids[2] = -2;
-    node7<CHECK, NT>(a, n, x, y, z, ids, acc);
+    node7<CHECK, NT, Off>(a, n, x, y, z, ids, acc);
 }
 
 // One step, one fluid node per thread.
-template <bool CHECK, bool NT>
+template <bool CHECK, bool NT, class Off>
 __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
-    if (n < a.nf) sweep7_node<CHECK, NT>(a, n, acc);
+    if (n < a.nf) sweep7_node<CHECK, NT, Off>(a, n, acc);
     if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(256) void k_sweep7(Sweep7 a) {
 // populations with e_x = +1 (at x = 0) or -1 (at x = nx - 1), shifts a_i (t0, tm, tp)
 // from the unscaled tables, BGK with 1/tau_g towards a_i C (the rest population closing
 // the balance of C).
-template <bool CHECK, bool NT>
+template <bool CHECK, bool NT, class Off>
 __device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
     LBM_D3Q19_TABLES
     const uint32_t c = a.coords[n];
@@ -272,11 +273,12 @@ __device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[k
     }
     const float om = a.omega[n];
     const Shift sh = a.shift[x + 1];
-    uint32_t off[19];
-    off[0] = (uint32_t)n;
+    // element offsets i * stride + node: 32-bit while q * stride fits, 64-bit beyond
+    Off off[19];
+    off[0] = (Off)n;
 #pragma unroll
     for (int i = 1; i < 19; i++)
-        off[i] = ids[i] >= 0 ? (uint32_t)(i * a.stride + ids[i]) : (uint32_t)(OPP[i] * a.stride + n);
+        off[i] = ids[i] >= 0 ? (Off)(i * a.stride + ids[i]) : (Off)(OPP[i] * a.stride + n);
     float ai[19];
 #pragma unroll
     for (int i = 0; i < 19; i++) ai[i] = a.src[off[i]];
@@ -333,12 +335,12 @@ __device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[k
     }
 }
 
-template <bool CHECK, bool NT>
+template <bool CHECK, bool NT, class Off>
 __global__ __launch_bounds__(256) void k_sweep19d(Sweep7 a) {
     const int64_t lb = a.chunk ? xcd_block(blockIdx.x, a.chunk) : (int64_t)blockIdx.x;
     const int64_t n = lb * 256 + threadIdx.x;
     double acc[kKnSums] = {0, 0, 0, 0, 0};
-    if (n < a.nf) sweep19d_node<CHECK, NT>(a, n, acc);
+    if (n < a.nf) sweep19d_node<CHECK, NT, Off>(a, n, acc);
     if (CHECK) write_partials7<kKnSums>(acc, lb, lb * 256 < a.nf, a.partials);
 }
 
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void k_sweep7b(Sweep7 a, const KnBlk *__restri
         b.ref_out = a.ref_out + D.sh0;
         b.c_out = D.c_out;
         const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
-        if (n < D.nf) sweep7_node<CHECK, NT>(b, n, acc);
+        if (n < D.nf) sweep7_node<CHECK, NT, uint32_t>(b, n, acc);
     }
     if (CHECK) write_partials7<kKnSums>(acc, pb, live, a.partials);
 }
@@ -658,10 +660,12 @@ static lbm_status kn_next_frame(const KnWs &w, const Grid &g, const KnHeader &h,
 // (XCD-contiguous order) below.
 struct Variant7 {
     bool remap, nt;
+    bool wide;  // 64-bit population offsets
 };
 
 static Variant7 pick_variant7(int32_t v, int64_t stride, int q = 7) {
     Variant7 m;
+    m.wide = (v & LBM_VARIANT_OFF64) || q * stride > (int64_t)UINT32_MAX;
     if (v & LBM_VARIANT_EXPLICIT) {
         m.remap = v & LBM_VARIANT_REMAP;
         m.nt = v & LBM_VARIANT_NTSTORE;
@@ -673,16 +677,22 @@ static Variant7 pick_variant7(int32_t v, int64_t stride, int q = 7) {
     return m;
 }
 
-template <bool CHECK>
-static void launch7(const Sweep7 &a, const Variant7 &m, int32_t lattice, hipStream_t s) {
+template <bool CHECK, class Off>
+static void launch7o(const Sweep7 &a, const Variant7 &m, int32_t lattice, hipStream_t s) {
     const unsigned grid = (unsigned)a.launched;
     if (lattice == LBM_LATTICE_D3Q19) {
-        if (m.nt) k_sweep19d<CHECK, true><<<grid, 256, 0, s>>>(a);
-        else k_sweep19d<CHECK, false><<<grid, 256, 0, s>>>(a);
+        if (m.nt) k_sweep19d<CHECK, true, Off><<<grid, 256, 0, s>>>(a);
+        else k_sweep19d<CHECK, false, Off><<<grid, 256, 0, s>>>(a);
     } else {
-        if (m.nt) k_sweep7<CHECK, true><<<grid, 256, 0, s>>>(a);
-        else k_sweep7<CHECK, false><<<grid, 256, 0, s>>>(a);
+        if (m.nt) k_sweep7<CHECK, true, Off><<<grid, 256, 0, s>>>(a);
+        else k_sweep7<CHECK, false, Off><<<grid, 256, 0, s>>>(a);
     }
+}
+
+template <bool CHECK>
+static void launch7(const Sweep7 &a, const Variant7 &m, int32_t lattice, hipStream_t s) {
+    if (m.wide || kn_q(lattice) * a.stride > (int64_t)UINT32_MAX) launch7o<CHECK, int64_t>(a, m, lattice, s);
+    else launch7o<CHECK, uint32_t>(a, m, lattice, s);
 }
 
 // `steps` sweeps; the first one moves the state into the pending frame if there is one.
@@ -781,7 +791,7 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
     LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
                 "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
-    LBM_REQUIRE((p->variant & ~kVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
+    LBM_REQUIRE((p->variant & ~kSolveVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
     LBM_REQUIRE(p->lattice == LBM_LATTICE_D3Q7 || p->lattice == LBM_LATTICE_D3Q19, LBM_E_INVAL,
                 "unknown lattice %d", p->lattice);
@@ -799,8 +809,6 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     if (st != LBM_OK) return st;
     LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
     KnWs w = carve_kn(workspace, g, nf, q);
-    LBM_REQUIRE(q * w.stride <= (int64_t)UINT32_MAX, LBM_E_INVAL,
-                "%lld fluid nodes exceed the 32-bit population offsets", (long long)nf);
     LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
                 "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
                 (long long)nf);

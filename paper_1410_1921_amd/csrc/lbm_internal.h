@@ -95,6 +95,8 @@ __host__ __device__ inline uint32_t pack_xyz(int x, int y, int z) {
 
 // Variant bits a solve accepts (a batched solve also LBM_VARIANT_NOGRAPH).
 constexpr int32_t kVariantBits = LBM_VARIANT_EXPLICIT | LBM_VARIANT_REMAP | LBM_VARIANT_NTSTORE;
+// ... and a single-lattice solve also LBM_VARIANT_OFF64.
+constexpr int32_t kSolveVariantBits = kVariantBits | LBM_VARIANT_OFF64;
 
 // ---------------------------------------------------------------- XCD-aware mapping
 // Workgroups are dealt to the 8 XCDs round robin (workgroup b runs on XCD b % 8).

@@ -29,6 +29,7 @@ _WS_FLOW_KIND = {LBM_STORE_FP32: LBM_WS_FLOW, LBM_STORE_FP16: LBM_WS_FLOW_FP16,
                  LBM_STORE_FP64: LBM_WS_FLOW_FP64}
 LBM_VARIANT_AUTO, LBM_VARIANT_EXPLICIT, LBM_VARIANT_REMAP, LBM_VARIANT_NTSTORE = 0, 1, 4, 8
 LBM_VARIANT_NOGRAPH = 16
+LBM_VARIANT_OFF64 = 32  # single-lattice solves: 64-bit population offsets on any size
 
 _STATUS = {0: "OK", 1: "W_NOT_CONVERGED", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVICE",
            -4: "E_RECON_STALL", -5: "E_DIVERGED"}
