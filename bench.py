@@ -36,13 +36,13 @@ BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 COUNTERS = {
     "k_sweep7<false, false, unsigned int>": dict(
-        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15338.1, write_kib=22966.8,
+        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15338.2, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="567ff54ea4aac6bc"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="21487cbf763b3e72"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2141861.5, write_kib=2490368.6,
+        workload="recon512_eps0.25_d16", fetch_kib=2141859.0, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="f2bd968d4fd97a14"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="c830731e08b60114"),
 }
 
 
@@ -377,6 +377,41 @@ def copy_ceiling(lbm, nbytes=1 << 30, reps=5):
     return round(best, 1)
 
 
+def copy_sizes(lbm, sizes_mb=(8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 2048), reps=50):
+    """Copy rate of the library's copy kernel against the working-set size: `reps` copies
+    of each size captured in one HIP graph, replayed 4 times, timed with HIP events
+    (read + write bytes per second).  Sizes up to 256 MB each way fit in the Infinity
+    Cache."""
+    import torch
+    out = {}
+    for mb in sizes_mb:
+        n = mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        lbm.lbm_copy_probe(dst, src)
+        torch.cuda.synchronize()
+        k = reps if mb <= 256 else 10
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(k):
+                lbm.lbm_copy_probe(dst, src)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(4):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / (4 * k)
+        assert torch.equal(dst, src)
+        out[mb] = {"us": round(us, 2), "gbs": round(2 * n / (us * 1e-6) / 1e9, 1)}
+        log("copy", mb, "MB each way", out[mb])
+        del src, dst, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(W, w, steps):
     """The FP64 oracle on a bounded sample of the workload: the whole geometry stage plus
     `steps` steps of each lattice (instead of running to convergence)."""
@@ -426,6 +461,8 @@ def main():
     ap.add_argument("--only-knudsen", type=int, default=0, metavar="STEPS",
                     help="only the geometry stages and STEPS Knudsen sweeps of the workload, "
                          "after the same copy calibration (profiling runs)")
+    ap.add_argument("--only-copy-sizes", action="store_true",
+                    help="only the copy rate against working-set size (cache vs HBM)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
@@ -444,6 +481,10 @@ def main():
         print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
                           "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
                           "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
+        return
+    if args.only_copy_sizes:
+        print(json.dumps({"copy_sizes_mb": copy_sizes(lbm), "copy_kernel": "k_copy_probe"}),
+              flush=True)
         return
     if args.only_batch:
         print(json.dumps({"batch": batch_throughput(lbm, W, args.batch_steps, args.batch_steps),
