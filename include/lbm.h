@@ -230,7 +230,9 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  *             rho - 1 (else rho = 1).
  * workspace : LBM_WS_FLOW (_FP16, _FP64 for those storages) bytes for the fluid
  *             count; it also keeps the state for lbm_flow_step / lbm_flow_sample /
- *             resume (a resume must use the storage of the solve that left it).
+ *             resume (a resume must use the storage, collision and boundary of the
+ *             solve that left it; one refused with LBM_E_INVAL leaves that state
+ *             usable).
  * With binary16 storage a check interval without any change is reported as a stall
  * (LBM_W_NOT_CONVERGED, converged = 0): the rounded iteration has reached a fixed point
  * short of steady state.
@@ -368,7 +370,7 @@ lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t
  *                the five links with e_x = +1 per node).
  * workspace    : LBM_WS_KNUDSEN (LBM_WS_KNUDSEN_D3Q19 for that lattice) bytes.
  * Errors: LBM_E_INVAL (tau_g <= 1/2 anywhere, C_in == C_out, unknown lattice, a resume
- * with another lattice, ...), LBM_E_NOMEM,
+ * with another lattice, ...; a refused resume leaves the stored state usable), LBM_E_NOMEM,
  * LBM_E_DIVERGED, LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_seg_count(Grid g, const uint8_t *__rest
         r.lo = (uint32_t)ball;
         r.hi = (uint32_t)(ball >> 32);
         r.base = (uint32_t)__popcll(ball);
-        r.pad = 0;
+        r.base_hi = 0;
         rank[sg] = r;
     }
 }
@@ -151,12 +151,15 @@ __global__ __launch_bounds__(1024) void k_seg_scan(RankWord *__restrict__ rank, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_seg_fill(Grid g, const RankWord *__restrict__ rank,
+// One wave per row segment: the id of the first fluid node of the word's upper half, and
+// the packed coordinates of the segment's nodes.
+__global__ __launch_bounds__(256) void k_seg_fill(Grid g, RankWord *__restrict__ rank,
                                                   uint32_t *__restrict__ coords) {
     const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (sg >= g.nsegs()) return;
     const RankWord w = rank[sg];
+    if (lane == 0) rank[sg].base_hi = w.base + (uint32_t)__popc(w.lo);
     const uint64_t bits = (uint64_t)w.hi << 32 | w.lo;
     if (!((bits >> lane) & 1)) return;
     const int sx = (int)(sg % g.nseg);
@@ -219,7 +222,7 @@ std::vector<BatchGroup> form_groups(const std::vector<int32_t> &act,
     return groups;
 }
 
-lbm_status layout_fill(const Grid &g, const RankWord *rank, uint32_t *coords, hipStream_t s) {
+lbm_status layout_fill(const Grid &g, RankWord *rank, uint32_t *coords, hipStream_t s) {
     k_seg_fill<<<(unsigned)((g.nsegs() + 3) / 4), 256, 0, s>>>(g, rank, coords);
     LBM_CHECK_LAUNCH();
     return LBM_OK;

@@ -452,14 +452,15 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
         bx[k] = xs[k] & (kSeg - 1);
     }
     // the 18 rank words are loaded as one batch, then the 19 populations as another
-    RankWord rw[19];
+    RankHalf rh[19];
 #pragma unroll
-    for (int i = 1; i < 19; i++) rw[i] = a.rank[wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]]];
+    for (int i = 1; i < 19; i++)
+        rh[i] = rank_half(a.rank, wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]], bx[1 - EX[i]]);
     int ids[19], gidx[19];
     ids[0] = 0;
 #pragma unroll
     for (int i = 1; i < 19; i++) {
-        ids[i] = rank_lookup(rw[i], bx[1 - EX[i]]);
+        ids[i] = half_lookup(rh[i], bx[1 - EX[i]]);
         gidx[i] = 0;
         if (OPEN && ((EX[i] == 1 && x == 0) || (EX[i] == -1 && x == g.nx - 1))) {
             // the source is a ghost node; its boundary node (looked up at this x) decides:
@@ -815,20 +816,15 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
-    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
-    if (st != LBM_OK) return st;
-    LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
-    FlowWs w = carve_flow(workspace, g, nf, p->storage);
-    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
-                "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
-                (long long)nf);
-
     FlowHeader h;
     int64_t t0 = 0;
     int cur = 0;
     if (p->resume) {
-        LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
-        LBM_TRY_HIP(hipStreamSynchronize(s));
+        // checked against a plain count of the mask before the rank map is rebuilt, so
+        // that a refused resume leaves the stored state usable
+        LBM_TRY_HIP(hipMemcpyAsync(&h, w0.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+        st = count_nonzero(g, fluid, w0.counter, &nf, s);
+        if (st != LBM_OK) return st;
         LBM_REQUIRE(h.magic == kFlowMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
                         h.n_fluid == nf && h.storage == p->storage &&
                         h.collision == p->collision && h.boundary == p->boundary,
@@ -837,6 +833,13 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         t0 = h.steps_done;
         cur = h.cur;
     }
+    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
+    if (st != LBM_OK) return st;
+    LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
+    FlowWs w = carve_flow(workspace, g, nf, p->storage);
+    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
+                "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
+                (long long)nf);
     st = layout_fill(g, w.rank, w.coords, s);
     if (st != LBM_OK) return st;
     h.magic = kFlowMagic;

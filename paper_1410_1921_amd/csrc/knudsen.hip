@@ -805,19 +805,15 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_REQUIRE(ws_bytes >= (size_t)((char *)w0.coords - (char *)workspace), LBM_E_NOMEM,
                 "workspace of %zu bytes is below the grid part", ws_bytes);
     int64_t nf = 0;
-    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
-    if (st != LBM_OK) return st;
-    LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
-    KnWs w = carve_kn(workspace, g, nf, q);
-    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
-                "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
-                (long long)nf);
     KnHeader h;
     int64_t t0 = 0;
     int cur = 0;
     if (p->resume) {
-        LBM_TRY_HIP(hipMemcpyAsync(&h, w.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
-        LBM_TRY_HIP(hipStreamSynchronize(s));
+        // checked against a plain count of the mask before the rank map is rebuilt, so
+        // that a refused resume leaves the stored state usable
+        LBM_TRY_HIP(hipMemcpyAsync(&h, w0.hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+        st = count_nonzero(g, fluid, w0.counter, &nf, s);
+        if (st != LBM_OK) return st;
         LBM_REQUIRE(h.magic == kKnMagic && h.nx == n[0] && h.ny == n[1] && h.nz == n[2] &&
                         h.n_fluid == nf && h.c_in == p->c_in && h.c_out == p->c_out &&
                         h.lattice == p->lattice,
@@ -827,6 +823,13 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     } else {
         h.frame = 0;
     }
+    st = layout_count(g, fluid, w0.rank, w0.total, &nf, s);
+    if (st != LBM_OK) return st;
+    LBM_REQUIRE(nf > 0, LBM_E_INVAL, "the fluid mask is empty");
+    KnWs w = carve_kn(workspace, g, nf, q);
+    LBM_REQUIRE(ws_bytes >= w.bytes, LBM_E_NOMEM,
+                "workspace of %zu bytes; %zu needed for %lld fluid nodes", ws_bytes, w.bytes,
+                (long long)nf);
     h.variant = p->variant;
     h.lattice = p->lattice;
     h.pad = 0;
