@@ -196,7 +196,11 @@ struct BatchRes {
         LBM_TRY_HIP(hipStreamWaitEvent(caller, join, 0));
         return LBM_OK;
     }
+    // On an error return the caller's stream was not joined: wait here for the work
+    // already issued, so that none of it can touch the workspace after the call
+    // returns (on success the solve has synchronised at its last check already).
     ~BatchRes() {
+        if (s) (void)hipStreamSynchronize(s);
         reset_graphs(0);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
