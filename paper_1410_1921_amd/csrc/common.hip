@@ -53,26 +53,42 @@ lbm_status count_nonzero(const Grid &g, const uint8_t *mask, unsigned long long 
 }
 
 // ---------------------------------------------------------------- fixed-order reduction
+// One block of 256 threads: thread t adds rows t, t + 256, ... in that order, then a fixed
+// halving tree over the threads.  All nv sums go through one pass (their loads in flight
+// together); each sum is added in the same order as it would be alone, so the result does
+// not depend on nv or on the unrolling.
+constexpr int kMaxSums = 8;
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ p,
                                                          int64_t nblocks, int nv,
                                                          double *__restrict__ res) {
-    __shared__ double lds[256];
-    for (int k = 0; k < nv; k++) {
-        double a = 0.0;
-        for (int64_t b = threadIdx.x; b < nblocks; b += 256) a += p[b * nv + k];
-        lds[threadIdx.x] = a;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) lds[threadIdx.x] += lds[threadIdx.x + w];
-            __syncthreads();
+    __shared__ double lds[kMaxSums][256];
+    double a[kMaxSums];
+#pragma unroll
+    for (int k = 0; k < kMaxSums; k++) a[k] = 0.0;
+#pragma unroll 4
+    for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+        const double *row = p + b * nv;
+#pragma unroll
+        for (int k = 0; k < kMaxSums; k++)
+            if (k < nv) a[k] += row[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxSums; k++) lds[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < kMaxSums; k++)
+                if (k < nv) lds[k][threadIdx.x] += lds[k][threadIdx.x + w];
         }
-        if (threadIdx.x == 0) res[k] = lds[0];
         __syncthreads();
     }
+    if ((int)threadIdx.x < nv) res[threadIdx.x] = lds[threadIdx.x][0];
 }
 
 lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, double *res,
                            hipStream_t s) {
+    LBM_REQUIRE(nv >= 1 && nv <= kMaxSums, LBM_E_INVAL, "reduce_partials: %d sums", nv);
     k_reduce_partials<<<1, 256, 0, s>>>(partials, nblocks, nv, res);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
