@@ -419,6 +419,10 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
     paper's D3Q19 lattice."""
     _vol(fluid, torch.uint8, "fluid")
     _vol(pore_diam, torch.float64, "pore_diam")
+    if pore_diam.shape != fluid.shape:
+        raise ValueError("pore_diam and fluid shapes differ")
+    if c_init is not None and _vol(c_init, torch.float32, "c_init").shape != fluid.shape:
+        raise ValueError("c_init and fluid shapes differ")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
     if workspace is None:

@@ -36,6 +36,20 @@ class View:
         return self.t.shape[0]
 
 
+def _need(ok, what):
+    if not ok:
+        raise ValueError(what)
+
+
+def _nv(shape):
+    nz, ny, nx = shape
+    return nz * ny * nx
+
+
+def _len(t, n):
+    return t is None or t.numel() == n
+
+
 def _bf(t):
     if t is None:
         return C.c_void_p(0)
@@ -53,6 +67,9 @@ def _f32(t):
 
 
 def lbm_nn_conv3d(shape, x, cin, w, bias, y, cout, flags):
+    _need(x.nvox == y.nvox == _nv(shape) and cin <= x.c and cout <= y.c,
+          "lbm_nn_conv3d: views do not hold the grid's voxels and channels")
+    _need(w.numel() == 27 * cin * cout and _len(bias, cout), "lbm_nn_conv3d: weight sizes")
     _check(load().lbm_nn_conv3d(_n3(shape), x.ptr, x.cs, cin, _bf(w), _f32(bias), y.ptr, y.cs,
                                 cout, flags, _stream()), "lbm_nn_conv3d")
 
@@ -62,37 +79,50 @@ def lbm_nn_wgrad_workspace(shape, cin, cout):
 
 
 def lbm_nn_conv3d_wgrad(shape, x, cin, g, cout, dw, db, ws, accumulate=False):
+    _need(x.nvox == g.nvox == _nv(shape) and cin <= x.c and cout <= g.c,
+          "lbm_nn_conv3d_wgrad: views do not hold the grid's voxels and channels")
+    _need(dw.numel() == 27 * cin * cout and _len(db, cout), "lbm_nn_conv3d_wgrad: gradient sizes")
     _check(load().lbm_nn_conv3d_wgrad(_n3(shape), x.ptr, x.cs, cin, g.ptr, g.cs, cout, _f32(dw),
                                       _f32(db), int(accumulate), _ptr(ws), ws.numel(), _stream()),
            "lbm_nn_conv3d_wgrad")
 
 
 def lbm_nn_transpose_weights(w, cout, cin, wt):
+    _need(w.numel() == wt.numel() == 27 * cin * cout, "lbm_nn_transpose_weights: sizes")
     _check(load().lbm_nn_transpose_weights(_bf(w), cout, cin, _bf(wt), _stream()),
            "lbm_nn_transpose_weights")
 
 
 def lbm_nn_pool2(shape_fine, c, x, y, accumulate=False):
+    _need(x.nvox == _nv(shape_fine) and 8 * y.nvox == _nv(shape_fine) and c <= min(x.c, y.c),
+          "lbm_nn_pool2: views do not hold the fine and coarse grids")
     _check(load().lbm_nn_pool2(_n3(shape_fine), c, x.ptr, x.cs, y.ptr, y.cs, int(accumulate),
                                _stream()), "lbm_nn_pool2")
 
 
 def lbm_nn_pool2_bwd(shape_fine, c, gy, gx, accumulate=False):
+    _need(8 * gy.nvox == _nv(shape_fine) and gx.nvox == _nv(shape_fine) and c <= min(gy.c, gx.c),
+          "lbm_nn_pool2_bwd: views do not hold the coarse and fine grids")
     _check(load().lbm_nn_pool2_bwd(_n3(shape_fine), c, gy.ptr, gy.cs, gx.ptr, gx.cs,
                                    int(accumulate), _stream()), "lbm_nn_pool2_bwd")
 
 
 def lbm_nn_up2(shape_fine, c, x, y):
+    _need(8 * x.nvox == _nv(shape_fine) and y.nvox == _nv(shape_fine) and c <= min(x.c, y.c),
+          "lbm_nn_up2: views do not hold the coarse and fine grids")
     _check(load().lbm_nn_up2(_n3(shape_fine), c, x.ptr, x.cs, y.ptr, y.cs, _stream()),
            "lbm_nn_up2")
 
 
 def lbm_nn_up2_bwd(shape_fine, c, gy, gx):
+    _need(gy.nvox == _nv(shape_fine) and 8 * gx.nvox == _nv(shape_fine) and c <= min(gy.c, gx.c),
+          "lbm_nn_up2_bwd: views do not hold the fine and coarse grids")
     _check(load().lbm_nn_up2_bwd(_n3(shape_fine), c, gy.ptr, gy.cs, gx.ptr, gx.cs, _stream()),
            "lbm_nn_up2_bwd")
 
 
 def lbm_nn_relu_bwd(c, y, gy, g):
+    _need(y.nvox == gy.nvox == g.nvox and c <= min(y.c, gy.c, g.c), "lbm_nn_relu_bwd: views differ")
     _check(load().lbm_nn_relu_bwd(y.nvox, c, y.ptr, y.cs, gy.ptr, gy.cs, g.ptr, g.cs, _stream()),
            "lbm_nn_relu_bwd")
 
@@ -104,6 +134,10 @@ def lbm_nn_head_workspace(nvox, no):
 def lbm_nn_head(x, no, wh, bh, out=None, target=None, mask=None, wt=None, n_mask=0.0, gx=None,
                 gwh=None, gbh=None, ws=None):
     """Returns the loss (with a target) or None."""
+    nv = x.nvox
+    _need(x.c >= 16 and wh.numel() == 16 * no and _len(bh, no) and _len(out, no * nv)
+          and _len(target, no * nv) and _len(mask, nv) and _len(wt, no)
+          and (gx is None or (gx.nvox == nv and gx.c >= 16)), "lbm_nn_head: sizes")
     loss = C.c_double(0.0)
     _check(load().lbm_nn_head(x.nvox, x.ptr, x.cs, no, _f32(wh), _f32(bh), _f32(out), _f32(target),
                               _ptr(mask), _f32(wt), float(n_mask),
@@ -115,11 +149,14 @@ def lbm_nn_head(x, no, wh, bh, out=None, target=None, mask=None, wt=None, n_mask
 
 
 def lbm_nn_adam(w, g, m, v, w_bf16, lr, beta1, beta2, eps, step):
+    _need(g.numel() == m.numel() == v.numel() == w.numel() and _len(w_bf16, w.numel()),
+          "lbm_nn_adam: sizes")
     _check(load().lbm_nn_adam(w.numel(), _f32(w), _f32(g), _f32(m), _f32(v), _bf(w_bf16), lr, beta1,
                               beta2, eps, step, _stream()), "lbm_nn_adam")
 
 
 def lbm_nn_to_bf16(src, dst):
+    _need(dst.numel() == src.numel(), "lbm_nn_to_bf16: sizes")
     _check(load().lbm_nn_to_bf16(src.numel(), _f32(src), _bf(dst), _stream()), "lbm_nn_to_bf16")
 
 
@@ -133,5 +170,7 @@ def lbm_nn_make_input(mask, diam, d_scale, x):
 
 def lbm_nn_to_fields(out, mask, scale, fields):
     nk = out.shape[0]
+    _need(out.numel() == nk * mask.numel() and fields.numel() >= nk * mask.numel()
+          and scale.numel() >= nk, "lbm_nn_to_fields: sizes")
     _check(load().lbm_nn_to_fields(mask.numel(), nk, _f32(out), _ptr(mask), _f32(scale),
                                    _f32(fields), _stream()), "lbm_nn_to_fields")

@@ -349,3 +349,29 @@ def test_max_volume_1024_knudsen_d3q7_sampled(orc):
     _transport_sampled(orc, m, mask_at, shape, lbm.LBM_LATTICE_D3Q7, 31, 600)
     del m, flat
     torch.cuda.empty_cache()
+
+
+def test_binding_refuses_mismatched_shapes():
+    # the C ABI takes bare pointers: the binding checks that companion arrays cover the
+    # grid before any call reaches the library
+    from paper_1410_1921_amd import nn
+    from paper_1410_1921_amd.nn import View
+    m = dev(W.blob_mask((8, 9, 10), 0.6, 3))
+    with pytest.raises(ValueError):
+        lbm.lbm_knudsen_solve(m, torch.ones((8, 9, 9), dtype=torch.float64, device="cuda"),
+                              fixed_steps=10)
+    with pytest.raises(ValueError):
+        lbm.lbm_knudsen_solve(m, torch.ones((8, 9, 10), dtype=torch.float64, device="cuda"),
+                              fixed_steps=10, c_init=torch.zeros((8, 9, 9), device="cuda"))
+    with pytest.raises(ValueError):
+        lbm.lbm_flow_solve(m, fixed_steps=10, u_init=torch.zeros((3, 8, 9, 9), device="cuda"))
+    shape = (16, 16, 16)
+    x = View(torch.zeros((16 * 16 * 16, 16), dtype=torch.bfloat16, device="cuda"))
+    y_small = View(torch.zeros((16 * 16 * 8, 16), dtype=torch.bfloat16, device="cuda"))
+    w = torch.zeros(27 * 16 * 16, dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(ValueError):
+        nn.lbm_nn_conv3d(shape, x, 16, w, None, y_small, 16, 0)
+    with pytest.raises(ValueError):
+        nn.lbm_nn_conv3d(shape, x, 16, w[:-1], None, x, 16, 0)
+    with pytest.raises(ValueError):
+        nn.lbm_nn_pool2(shape, 16, x, x)
