@@ -575,7 +575,7 @@ def main():
             "inference_s": round(wr["t"]["inference"], 4),
             "k_rel_diff": abs(wr["flow"]["k_lattice"] / last["flow"]["k_lattice"] - 1),
             "deff_rel_diff": abs(wr["knudsen"]["Deff_lattice"] / last["knudsen"]["Deff_lattice"] - 1),
-            "network": "U-Net 16-128 ch, trained on 400 solves of 96^3 geometries",
+            "network": "U-Net 16-128 ch, trained 25 epochs on 400 solves of 96^3 geometries",
             "applied_to": "Knudsen C (the flow starts from rest)"}
     if not args.no_batch:
         log("batch workload")
