@@ -1,7 +1,7 @@
 """Train the warm-start U-Net on solutions of the solver itself, then compare solves
 from rest with warm-started solves on held-out geometries.
 
-    python -m paper_1410_1921_amd.train_warmstart --train 400 --epochs 8 \\
+    python -m paper_1410_1921_amd.train_warmstart --train 400 --epochs 25 \\
         --out paper_1410_1921_amd/weights/unet_warmstart.npz --eval 50 --eval-json eval.json
 
 Training targets are the converged (u, rho - 1, C) of the flow and Knudsen solves from
@@ -17,7 +17,7 @@ import time
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=400, help="training geometries (seeds 5000+)")
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=25)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-6, help="residual of the training targets")
     ap.add_argument("--workers", type=int, default=16, help="concurrent solves for the data")
