@@ -465,8 +465,8 @@ def main():
                     help="only the copy rate against working-set size (cache vs HBM)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's multi-GPU "
-              "decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's multi-GPU "
+              "decomposition is a design, not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
