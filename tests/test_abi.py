@@ -76,6 +76,23 @@ def test_workspace_sizes(lib):
         lib.lbm_workspace_size(lib.LBM_WS_FLOW, (8, 8, 8), 10_000)
 
 
+def test_workspace_sizes_at_the_largest_volume(lib):
+    # 1024^3, every voxel fluid: 2^30 nodes, population arrays far beyond 2^32 elements;
+    # the sizes come out in 64-bit arithmetic, at least the population bytes, and grow
+    # with the storage width
+    n = (1024, 1024, 1024)
+    nf = 1024 ** 3
+    per_node = {lib.LBM_WS_FLOW: 2 * 19 * 4, lib.LBM_WS_FLOW_FP16: 2 * (19 * 2 + 4),
+                lib.LBM_WS_FLOW_FP64: 2 * 19 * 8, lib.LBM_WS_KNUDSEN: 2 * 7 * 4,
+                lib.LBM_WS_KNUDSEN_D3Q19: 2 * 19 * 4}
+    for kind, b in per_node.items():
+        size = lib.lbm_workspace_size(kind, n, nf)
+        assert b * nf <= size < (b + 64) * nf, kind
+    assert lib.lbm_workspace_size(lib.LBM_WS_FLOW_FP64, n, nf) > 2 ** 38
+    assert lib.lbm_workspace_size(lib.LBM_WS_LABEL, n) >= 2 * nf
+    assert lib.lbm_workspace_size(lib.LBM_WS_PORE_DIAM, n) >= 12 * nf
+
+
 def test_argument_checks_before_device(lib):
     L = lib.load()
     n = (C.c_int32 * 3)(8, 8, 8)
