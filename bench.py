@@ -38,11 +38,11 @@ COUNTERS = {
     "k_sweep7<false, false, unsigned int>": dict(
         workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15335.4, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="ce344c67e846c285"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="d2970070c1eb2cab"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2142164.8, write_kib=2490368.6,
+        workload="recon512_eps0.25_d16", fetch_kib=2142158.8, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="f81b584631a4dfae"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="61294fa64a918e36"),
 }
 
 

@@ -53,43 +53,47 @@ lbm_status count_nonzero(const Grid &g, const uint8_t *mask, unsigned long long 
 }
 
 // ---------------------------------------------------------------- fixed-order reduction
-// One block of 256 threads: thread t adds rows t, t + 256, ... in that order, then a fixed
-// halving tree over the threads.  All nv sums go through one pass (their loads in flight
-// together); each sum is added in the same order as it would be alone, so the result does
-// not depend on nv or on the unrolling.
+// One block of 1024 threads (enough loads in flight to read the rows at cache speed):
+// thread t adds rows t, t + 1024, ... in that order, each wave folds its 64 lanes with a
+// fixed shuffle tree, and thread k < nv adds the 16 wave sums of sum k in wave order.
+// All nv sums go through one pass; the order of every addition is fixed, so the result
+// is bitwise reproducible.
 constexpr int kMaxSums = 8;
-__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ p,
-                                                         int64_t nblocks, int nv,
-                                                         double *__restrict__ res) {
-    __shared__ double lds[kMaxSums][256];
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partials(const double *__restrict__ p,
+                                                                    int64_t nblocks, int nv,
+                                                                    double *__restrict__ res) {
+    __shared__ double lds[kMaxSums][kReduceThreads / 64];
     double a[kMaxSums];
 #pragma unroll
     for (int k = 0; k < kMaxSums; k++) a[k] = 0.0;
 #pragma unroll 4
-    for (int64_t b = threadIdx.x; b < nblocks; b += 256) {
+    for (int64_t b = threadIdx.x; b < nblocks; b += kReduceThreads) {
         const double *row = p + b * nv;
 #pragma unroll
         for (int k = 0; k < kMaxSums; k++)
             if (k < nv) a[k] += row[k];
     }
 #pragma unroll
-    for (int k = 0; k < kMaxSums; k++) lds[k][threadIdx.x] = a[k];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
+    for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-            for (int k = 0; k < kMaxSums; k++)
-                if (k < nv) lds[k][threadIdx.x] += lds[k][threadIdx.x + w];
-        }
-        __syncthreads();
+        for (int k = 0; k < kMaxSums; k++) a[k] += __shfl_down(a[k], off, 64);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < kMaxSums; k++) lds[k][wave] = a[k];
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceThreads / 64; w++) t += lds[threadIdx.x][w];
+        res[threadIdx.x] = t;
     }
-    if ((int)threadIdx.x < nv) res[threadIdx.x] = lds[threadIdx.x][0];
 }
 
 lbm_status reduce_partials(const double *partials, int64_t nblocks, int nv, double *res,
                            hipStream_t s) {
     LBM_REQUIRE(nv >= 1 && nv <= kMaxSums, LBM_E_INVAL, "reduce_partials: %d sums", nv);
-    k_reduce_partials<<<1, 256, 0, s>>>(partials, nblocks, nv, res);
+    k_reduce_partials<<<1, kReduceThreads, 0, s>>>(partials, nblocks, nv, res);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
