@@ -412,6 +412,35 @@ def copy_sizes(lbm, sizes_mb=(8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 204
     return out
 
 
+def flow_sizes(lbm, edges=(256, 320, 384, 448, 512), steps=30):
+    """Time per fluid-node update of the binary32 flow sweep against lattice size
+    (reconstructions drawn like the 512^3 workload: porosity 0.25, N(16, 4) spheres,
+    overlap tolerance 0.7, seed 3), from HIP events over `steps` launches, best of 2."""
+    import torch
+    s = torch.cuda.current_stream()
+    out = {}
+    for n in edges:
+        pore, _, st = lbm.lbm_reconstruct((n, n, n), 0.25, 16.0, 4.0, 1.0, 0.7, 0.5, 3)
+        nf = st["n_pore"]
+        r = lbm.lbm_flow_solve(pore, tau=0.8, force=(1e-6, 0, 0), fixed_steps=20,
+                               check_every=100, n_fluid=nf)
+        best = 1e9
+        for _ in range(2):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            lbm.lbm_flow_step(r.workspace, steps)
+            e1.record(s)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / steps)
+        out[n] = {"n_fluid": nf, "workspace_gb": round(r.workspace.nbytes / 1e9, 2),
+                  "ms_per_launch": round(best, 4), "ps_per_update": round(best * 1e9 / nf, 2)}
+        log("flow size", n, out[n])
+        del r, pore
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(W, w, steps):
     """The FP64 oracle on a bounded sample of the workload: the whole geometry stage plus
     `steps` steps of each lattice (instead of running to convergence)."""
@@ -463,6 +492,8 @@ def main():
                          "after the same copy calibration (profiling runs)")
     ap.add_argument("--only-copy-sizes", action="store_true",
                     help="only the copy rate against working-set size (cache vs HBM)")
+    ap.add_argument("--only-flow-sizes", action="store_true",
+                    help="only the flow sweep's time per update against lattice size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's multi-GPU "
@@ -481,6 +512,9 @@ def main():
         print(json.dumps({"roofline_512": roofline_512(lbm, W, args.roofline_steps),
                           "copy_kernel": "k_copy_probe", "copy_bytes_each_way": 1 << 31,
                           "copy_copies": 4, "copy_gbs": ceiling}), flush=True)
+        return
+    if args.only_flow_sizes:
+        print(json.dumps({"flow_sizes": flow_sizes(lbm)}), flush=True)
         return
     if args.only_copy_sizes:
         print(json.dumps({"copy_sizes_mb": copy_sizes(lbm), "copy_kernel": "k_copy_probe"}),
