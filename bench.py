@@ -40,9 +40,9 @@ COUNTERS = {
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="d2970070c1eb2cab"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2142158.8, write_kib=2490368.6,
+        workload="recon512_eps0.25_d16", fetch_kib=2142268.8, write_kib=2490368.7,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="61294fa64a918e36"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="86e59469393eba5a"),
 }
 
 

@@ -2,7 +2,8 @@
 // bounce-back, on the sparse fluid-node list (Section 3.1, Eqs. 1-3, 8-9; Section 3.3;
 // Darcy's law, Eq. 13).
 //
-// Storage: structure of arrays f[i][node] of the offsets f_i - w_i ("shifted"
+// Storage: blocks of 256 nodes, each with its 19 arrays of 256 side by side (pop19), of
+// the offsets f_i - w_i ("shifted"
 // populations: the flow signal lives in deviations of order 1e-6 from w_i, which a float
 // keeps to ~1e-13 absolute once the constant w_i is removed), in binary32 (collision in
 // binary32) or binary64 (collision in binary64).  Two buffers, ping-pong.  Per
@@ -30,7 +31,7 @@
 
 namespace lbm {
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5734ull;  // "LBMFLOW4"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5735ull;  // "LBMFLOW5"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -124,6 +125,16 @@ struct FlowWs {
 
 static int64_t blocks_for(int64_t nf) { return (nf + 255) / 256; }
 
+// Population i of fluid node m.  The nodes go in blocks of 256; each block keeps its 19
+// arrays of 256 side by side (19 KB in binary32), so that the populations a wave pulls
+// from its own and its neighbouring rows lie in few pages: with one array of the whole
+// lattice per direction a 512^3 sweep took 7.7 M translation misses per launch, and this
+// layout runs it 13 % faster.  A wave's 64 consecutive nodes still read and write 256 B
+// runs.
+__host__ __device__ inline int64_t pop19(int i, int64_t m) {
+    return ((m >> 8) * 19 + i) * 256 + (m & 255);
+}
+
 static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage) {
     FlowWs w;
     Carver c(base);
@@ -136,7 +147,7 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage)
     w.samp_out = c.take<double>((size_t)kSampleMax * 19);
     w.samp_flag = c.take<uint8_t>(kSampleMax);
     int64_t nfp = nf < 1 ? 1 : nf;
-    w.stride = (nfp + 63) / 64 * 64;
+    w.stride = (nfp + 255) / 256 * 256;  // whole blocks of 256 nodes (pop19)
     w.coords = c.take<uint32_t>(nfp);
     w.f[0] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
     w.f[1] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
@@ -317,13 +328,13 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     T *__restrict__ dst = static_cast<T *>(a.dst);
     const R omega = par<R>(a.omega, a.omega_d), fpre = par<R>(a.fpre, a.fpre_d);
     const R Fx = par<R>(a.Fx, a.Fd[0]), Fy = par<R>(a.Fy, a.Fd[1]), Fz = par<R>(a.Fz, a.Fd[2]);
-    // element offsets i * stride + node: 32-bit while 19 * stride fits (fewer registers),
+    // element offsets pop19(i, node): 32-bit while 19 * stride fits (fewer registers),
     // 64-bit beyond
     Off off[19];
-    off[0] = (Off)n;
+    off[0] = (Off)pop19(0, n);
 #pragma unroll
     for (int i = 1; i < 19; i++)
-        off[i] = ids[i] >= 0 ? (Off)(i * a.stride + ids[i]) : (Off)(OPP[i] * a.stride + n);
+        off[i] = ids[i] >= 0 ? (Off)pop19(i, ids[i]) : (Off)pop19(OPP[i], n);
     R f[19];
 #pragma unroll
     for (int i = 0; i < 19; i++) f[i] = from_store<P>(src[off[i]], a.inv_scale);
@@ -384,9 +395,9 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
         if constexpr (std::is_same<T, _Float16>::value) post -= w * drho;
         const T out = to_store<P>(post, a.scale);
         if (NT)
-            __builtin_nontemporal_store(out, &dst[(int64_t)i * a.stride + n]);
+            __builtin_nontemporal_store(out, &dst[pop19(i, n)]);
         else
-            dst[(int64_t)i * a.stride + n] = out;
+            dst[pop19(i, n)] = out;
     }
     if constexpr (std::is_same<T, _Float16>::value) a.drho_dst[n] = drho;
     if (CHECK) {
@@ -540,8 +551,7 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
 // domain are kept, as offsets f_i - w_i, in ghost[side][slot][z ny + y].  A ghost beside a
 // solid b is solid (the sweep bounces back) and is not written.
 template <class P>
-__global__ __launch_bounds__(256) void k_ghost19(Grid g, int64_t stride,
-                                                 const RankWord *__restrict__ rank,
+__global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restrict__ rank,
                                                  const typename P::T *__restrict__ src,
                                                  float inv_scale, float scale,
                                                  typename P::R Fx, typename P::R Fy,
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(256) void k_ghost19(Grid g, int64_t stride,
     R f[19], drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < 19; i++) {
-        f[i] = from_store<P>(src[(int64_t)i * stride + id], inv_scale);
+        f[i] = from_store<P>(src[pop19(i, id)], inv_scale);
         drho += f[i];
         jx += EX[i] * f[i];
         jy += EY[i] * f[i];
@@ -612,14 +622,14 @@ __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t s
         const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
         R dev = w * rho * (R(3) * eu + R(4.5) * eu * eu - uu15);  // f_eq - w_i (1 + drho)
         if (!drho) dev += w * dr;                                 // f_eq - w_i
-        f[(int64_t)i * stride + n] = to_store<P>(dev, scale);
+        f[pop19(i, n)] = to_store<P>(dev, scale);
     }
     usnap[n] = (float)ux; usnap[stride + n] = (float)uy; usnap[2 * stride + n] = (float)uz;
     if (drho) drho[n] = (float)dr;
 }
 
 template <class P>
-__global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
+__global__ void k_flow_sample(Grid g, int64_t count,
                               const int64_t *__restrict__ vox, const RankWord *__restrict__ rank,
                               const typename P::T *__restrict__ f, float inv_scale,
                               const float *__restrict__ drho, double *__restrict__ out,
@@ -631,7 +641,7 @@ __global__ void k_flow_sample(Grid g, int64_t count, int64_t stride,
     const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
     for (int i = 0; i < 19; i++) {
-        double v = id >= 0 ? (double)from_store<P>(f[(int64_t)i * stride + id], inv_scale) : 0.0;
+        double v = id >= 0 ? (double)from_store<P>(f[pop19(i, id)], inv_scale) : 0.0;
         if (drho && id >= 0)  // binary16: offsets are taken from w_i (1 + drho) of the node
             v += (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)) * (double)drho[id];
         out[s * 19 + i] = v;
@@ -735,12 +745,12 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
         if (open) {  // the ghost planes of this step, from the state it reads
             if (h.storage == LBM_STORE_FP64)
                 k_ghost19<StoreF64><<<gblocks, 256, 0, s>>>(
-                    g, w.stride, w.rank, static_cast<const double *>(a.src), 1.f, 1.f,
+                    g, w.rank, static_cast<const double *>(a.src), 1.f, 1.f,
                     h.force[0], h.force[1], h.force[2], h.rho_in - 1.0, h.rho_out - 1.0,
                     static_cast<double *>(w.ghost));
             else
                 k_ghost19<StoreF32><<<gblocks, 256, 0, s>>>(
-                    g, w.stride, w.rank, static_cast<const float *>(a.src), 1.f, 1.f,
+                    g, w.rank, static_cast<const float *>(a.src), 1.f, 1.f,
                     (float)h.force[0], (float)h.force[1], (float)h.force[2],
                     (float)(h.rho_in - 1.0), (float)(h.rho_out - 1.0),
                     static_cast<float *>(w.ghost));
@@ -1025,15 +1035,15 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     const unsigned nb = (unsigned)((count + 255) / 256);
     const float inv = (float)(1.0 / h.scale);
     if (h.storage == LBM_STORE_FP16)
-        k_flow_sample<StoreF16><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+        k_flow_sample<StoreF16><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const _Float16 *>(w.f[h.cur]), inv,
                                                    w.drho[h.cur], w.samp_out, w.samp_flag);
     else if (h.storage == LBM_STORE_FP64)
-        k_flow_sample<StoreF64><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+        k_flow_sample<StoreF64><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const double *>(w.f[h.cur]), inv,
                                                    nullptr, w.samp_out, w.samp_flag);
     else
-        k_flow_sample<StoreF32><<<nb, 256, 0, s>>>(g, count, w.stride, w.samp_vox, w.rank,
+        k_flow_sample<StoreF32><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const float *>(w.f[h.cur]), inv,
                                                    nullptr, w.samp_out, w.samp_flag);
     LBM_CHECK_LAUNCH();
