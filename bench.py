@@ -36,11 +36,11 @@ BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 COUNTERS = {
     "k_sweep7<false, false, unsigned int>": dict(
-        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15335.4, write_kib=22966.8,
+        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15341.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="d2970070c1eb2cab"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="a17accb569da7dfc"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2142268.8, write_kib=2490368.7,
+        workload="recon512_eps0.25_d16", fetch_kib=2142213.7, write_kib=2490369.4,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="86e59469393eba5a"),
 }
