@@ -3,11 +3,12 @@
 // links, periodic in y and z, equilibrium ghost planes at x = -1 and x = nx (Section
 // 3.3), and the outlet-plane flux of Eq. 14.
 //
-// Storage: s[i][node] = g_i - w_i C_ref(x) in binary32, where C_ref(x) is a reference
-// profile along x (the "frame" of the state): the mean concentration of plane x at the
-// latest convergence check (ghost planes: C_ref(-1) = C_in, C_ref(nx) = C_out).  The
-// collision is carried out on these deviations, so rounding acts on numbers far smaller
-// than g itself: both the transient front and the steady state keep binary32 errors
+// Storage: s_i(node) = g_i - w_i C_ref(x) in binary32, at element popq(q, i, node)
+// below, where C_ref(x) is a reference profile along x (the "frame" of the state): the
+// mean concentration of plane x at the latest convergence check (ghost planes:
+// C_ref(-1) = C_in, C_ref(nx) = C_out).  The collision is carried out on these
+// deviations, so rounding acts on numbers far smaller than g itself: both the
+// transient front and the steady state keep binary32 errors
 // near 1e-7 relative, where storing g directly freezes the iteration (per-step changes
 // below half an ulp) up to ~1e-3 away from its steady state on long channels.
 // A new frame costs no extra pass: the first sweep after a check reads the state in the
