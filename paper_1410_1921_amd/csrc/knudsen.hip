@@ -875,6 +875,19 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     LBM_REQUIRE(bad == 0, LBM_E_INVAL, "%llu fluid nodes have tau_g <= 1/2 (pore diameter <= 0)", bad);
     if (c_field) LBM_TRY_HIP(hipMemsetAsync(c_field, 0, sizeof(float) * g.nvox(), s));
 
+    // The check sums land in pinned host memory, copied right after their reduction, so
+    // the frame update that follows runs while the host reads them and queues the next
+    // interval (the same kernels in the same order as without the copy moved forward).
+    struct Pinned {
+        double *p = nullptr;
+        hipEvent_t got = nullptr;
+        ~Pinned() {
+            if (got) (void)hipEventDestroy(got);
+            if (p) (void)hipHostFree(p);
+        }
+    } pin;
+    LBM_TRY_HIP(hipHostMalloc((void **)&pin.p, sizeof(double) * kKnSums, hipHostMallocDefault));
+    LBM_TRY_HIP(hipEventCreateWithFlags(&pin.got, hipEventDisableTiming));
     hipEvent_t e0, e1;
     LBM_TRY_HIP(hipEventCreate(&e0));
     LBM_TRY_HIP(hipEventCreate(&e1));
@@ -895,11 +908,13 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         LBM_TRY_HIP(hipEventRecord(e1, s));
         out = reduce_partials(w.partials, kn_blocks(nf), kKnSums, w.res, s);
         if (out != LBM_OK) break;
+        LBM_TRY_HIP(hipMemcpyAsync(pin.p, w.res, sizeof(sums), hipMemcpyDeviceToHost, s));
+        LBM_TRY_HIP(hipEventRecord(pin.got, s));
         out = kn_next_frame(w, g, h, s);
         if (out != LBM_OK) break;
         pending = true;
-        LBM_TRY_HIP(hipMemcpyAsync(sums, w.res, sizeof(sums), hipMemcpyDeviceToHost, s));
-        LBM_TRY_HIP(hipStreamSynchronize(s));
+        LBM_TRY_HIP(hipEventSynchronize(pin.got));
+        std::memcpy(sums, pin.p, sizeof(sums));
         float ms = 0.f;
         LBM_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
         sweep_ms += ms;
