@@ -239,10 +239,11 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  * The convergence residual, the velocity snapshot it compares against and u_out are
  * formed from the collision arithmetic and kept in binary32 (sums in binary64) for
  * every storage.
- * Errors: LBM_E_INVAL (tau <= 1/2, check_every < 1, no fluid node, N > 1024, unknown
- * storage, collision, boundary or variant bits; pressure boundaries with binary16
- * storage, non-positive densities or no driving), LBM_E_NOMEM, LBM_E_DIVERGED,
- * LBM_E_DEVICE.
+ * Errors: LBM_E_INVAL (tau <= 1/2, a non-finite force, voxel size <= 0 or non-finite,
+ * check_every < 1, no fluid node, N > 1024, unknown storage, collision, boundary or
+ * variant bits; pressure boundaries with binary16 storage, non-positive densities or no
+ * driving), LBM_E_NOMEM, LBM_E_DIVERGED (NaN/Inf in a check, e.g. from a u_init that
+ * holds one), LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
     double tau;
@@ -369,9 +370,10 @@ lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t
  *                links with both ends fluid (ghost planes count as fluid; on D3Q19
  *                the five links with e_x = +1 per node).
  * workspace    : LBM_WS_KNUDSEN (LBM_WS_KNUDSEN_D3Q19 for that lattice) bytes.
- * Errors: LBM_E_INVAL (tau_g <= 1/2 anywhere, C_in == C_out, unknown lattice, a resume
- * with another lattice, ...; a refused resume leaves the stored state usable), LBM_E_NOMEM,
- * LBM_E_DIVERGED, LBM_E_DEVICE.
+ * Errors: LBM_E_INVAL (tau_g <= 1/2 or NaN anywhere, C_in == C_out, a non-finite C_in,
+ * C_out, tau_ref, d_ref_nm or voxel_nm, unknown lattice, a resume with another lattice,
+ * ...; a refused resume leaves the stored state usable), LBM_E_NOMEM, LBM_E_DIVERGED
+ * (NaN/Inf in a check, e.g. from a c_init that holds one), LBM_E_DEVICE.
  * ---------------------------------------------------------------------------- */
 typedef struct {
     double tau_ref;       /* tau_g at d_ref (the paper: 1.0) */

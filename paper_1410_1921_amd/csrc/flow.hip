@@ -793,6 +793,9 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     if (st != LBM_OK) return st;
     LBM_REQUIRE(fluid && p && r && workspace, LBM_E_INVAL, "lbm_flow_solve: null argument");
     LBM_REQUIRE(p->tau > 0.5 && std::isfinite(p->tau), LBM_E_INVAL, "tau must exceed 1/2");
+    LBM_REQUIRE(std::isfinite(p->force[0]) && std::isfinite(p->force[1]) &&
+                    std::isfinite(p->force[2]) && p->voxel_nm > 0 && std::isfinite(p->voxel_nm),
+                LBM_E_INVAL, "the force must be finite and the voxel size positive and finite");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 || p->storage == LBM_STORE_FP16 ||
@@ -1165,6 +1168,9 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         LBM_REQUIRE(fluid[l] && nf_h[l] >= 1, LBM_E_INVAL, "lattice %d: no fluid mask or node", l);
     }
     LBM_REQUIRE(p->tau > 0.5 && std::isfinite(p->tau), LBM_E_INVAL, "tau must exceed 1/2");
+    LBM_REQUIRE(std::isfinite(p->force[0]) && std::isfinite(p->force[1]) &&
+                    std::isfinite(p->force[2]) && p->voxel_nm > 0 && std::isfinite(p->voxel_nm),
+                LBM_E_INVAL, "the force must be finite and the voxel size positive and finite");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 && !p->resume && !p->with_rho, LBM_E_INVAL,

@@ -795,9 +795,13 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
                 "lbm_knudsen_solve: null argument");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(std::isfinite(p->c_in) && std::isfinite(p->c_out), LBM_E_INVAL,
+                "C_in and C_out must be finite");
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
-    LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
-                "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
+    LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0 &&
+                    std::isfinite(p->tau_ref) && std::isfinite(p->d_ref_nm) &&
+                    std::isfinite(p->voxel_nm),
+                LBM_E_INVAL, "tau_ref must exceed 1/2 and d_ref, voxel size be positive (all finite)");
     LBM_REQUIRE((p->variant & ~kSolveVariantBits) == 0, LBM_E_INVAL, "unknown variant bits 0x%x",
                 p->variant);
     LBM_REQUIRE(p->lattice == LBM_LATTICE_D3Q7 || p->lattice == LBM_LATTICE_D3Q19, LBM_E_INVAL,
@@ -1190,9 +1194,13 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     }
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(std::isfinite(p->c_in) && std::isfinite(p->c_out), LBM_E_INVAL,
+                "C_in and C_out must be finite");
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
-    LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0, LBM_E_INVAL,
-                "tau_ref must exceed 1/2 and d_ref, voxel size be positive");
+    LBM_REQUIRE(p->tau_ref > 0.5 && p->d_ref_nm > 0 && p->voxel_nm > 0 &&
+                    std::isfinite(p->tau_ref) && std::isfinite(p->d_ref_nm) &&
+                    std::isfinite(p->voxel_nm),
+                LBM_E_INVAL, "tau_ref must exceed 1/2 and d_ref, voxel size be positive (all finite)");
     LBM_REQUIRE(!p->resume, LBM_E_INVAL, "batched solves do not resume");
     LBM_REQUIRE(p->lattice == LBM_LATTICE_D3Q7, LBM_E_INVAL,
                 "batched solves run the D3Q7 lattice only");

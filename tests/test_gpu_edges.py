@@ -10,6 +10,8 @@
 * Sizes beyond the limit are refused before any launch.
 * Degenerate lattices: a single-voxel domain, a fluid voxel walled in on every side,
   fluid that reaches neither x face, and no fluid at all.
+* Non-finite parameters are refused before any launch; a NaN in the starting field is
+  reported as divergence by the first check.
 """
 import sys
 
@@ -375,3 +377,46 @@ def test_binding_refuses_mismatched_shapes():
         nn.lbm_nn_conv3d(shape, x, 16, w[:-1], None, x, 16, 0)
     with pytest.raises(ValueError):
         nn.lbm_nn_pool2(shape, 16, x, x)
+
+
+def small_problem():
+    m = W.blob_mask((16, 16, 16), 0.5, 3)
+    return m, np.where(m > 0, 4.0, 0.0)
+
+
+@pytest.mark.parametrize("bad", [dict(c_in=float("nan")), dict(c_out=float("inf")),
+                                 dict(tau_ref=float("inf")), dict(d_ref_nm=float("inf")),
+                                 dict(voxel_nm=float("nan"))])
+def test_knudsen_non_finite_parameters_refused(bad):
+    m, d = small_problem()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_knudsen_solve(dev(m), dev(d), fixed_steps=10, **bad)
+    assert e.value.status == lbm.LBM_E_INVAL
+
+
+@pytest.mark.parametrize("bad", [dict(force=(float("nan"), 0.0, 0.0)),
+                                 dict(force=(1e-6, float("inf"), 0.0)),
+                                 dict(voxel_nm=0.0), dict(voxel_nm=float("inf"))])
+def test_flow_non_finite_parameters_refused(bad):
+    m, _ = small_problem()
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_flow_solve(dev(m), fixed_steps=10, **bad)
+    assert e.value.status == lbm.LBM_E_INVAL
+
+
+@pytest.mark.parametrize("lattice", ["D3Q7", "D3Q19"])
+def test_knudsen_nan_start_reported_as_diverged(lattice):
+    # a NaN in the initial concentration reaches the first check's sums, which report it;
+    # a later solve of the same problem is unaffected
+    lat = getattr(lbm, "LBM_LATTICE_" + lattice)
+    m, d = small_problem()
+    c0 = np.zeros(m.shape, np.float32)
+    fl = np.flatnonzero(m)
+    c0.flat[fl[len(fl) // 2]] = np.nan
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_knudsen_solve(dev(m), dev(d), max_steps=1000, check_every=100, c_init=dev(c0),
+                              lattice=lat)
+    assert e.value.status == lbm.LBM_E_DIVERGED
+    r = lbm.lbm_knudsen_solve(dev(m), dev(d), fixed_steps=200, check_every=100, lattice=lat)
+    say(lattice, "after a diverged solve: D_eff", r["Deff_lattice"], "steps", r["steps"])
+    assert np.isfinite(r["Deff_lattice"]) and r["steps"] == 200
