@@ -38,7 +38,7 @@ COUNTERS = {
     "k_sweep7<false, false, unsigned int>": dict(
         workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15341.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="e51c1951bbfac874"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="53f1b7130853c28f"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
         workload="recon512_eps0.25_d16", fetch_kib=2142213.7, write_kib=2490369.4,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",

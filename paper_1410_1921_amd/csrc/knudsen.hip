@@ -882,19 +882,22 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     // The check sums land in pinned host memory, copied right after their reduction, so
     // the frame update that follows runs while the host reads them and queues the next
     // interval (the same kernels in the same order as without the copy moved forward).
+    // (Buffer and events are released on every return.)
     struct Pinned {
         double *p = nullptr;
-        hipEvent_t got = nullptr;
+        hipEvent_t got = nullptr, e0 = nullptr, e1 = nullptr;
         ~Pinned() {
+            if (e1) (void)hipEventDestroy(e1);
+            if (e0) (void)hipEventDestroy(e0);
             if (got) (void)hipEventDestroy(got);
             if (p) (void)hipHostFree(p);
         }
     } pin;
     LBM_TRY_HIP(hipHostMalloc((void **)&pin.p, sizeof(double) * kKnSums, hipHostMallocDefault));
     LBM_TRY_HIP(hipEventCreateWithFlags(&pin.got, hipEventDisableTiming));
-    hipEvent_t e0, e1;
-    LBM_TRY_HIP(hipEventCreate(&e0));
-    LBM_TRY_HIP(hipEventCreate(&e1));
+    LBM_TRY_HIP(hipEventCreate(&pin.e0));
+    LBM_TRY_HIP(hipEventCreate(&pin.e1));
+    const hipEvent_t e0 = pin.e0, e1 = pin.e1;
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     double sums[kKnSums] = {0, 0, 0, 0, 0};
@@ -935,8 +938,6 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (out != LBM_OK) return out;
     // a pending frame that no sweep entered is dropped: the state stays in h.frame
     h.cur = cur;
