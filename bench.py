@@ -42,7 +42,7 @@ COUNTERS = {
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
         workload="recon512_eps0.25_d16", fetch_kib=2142213.7, write_kib=2490369.4,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="af582e6fa1b0b28d"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="557d46a9c7df684c"),
 }
 
 

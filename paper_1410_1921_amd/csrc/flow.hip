@@ -894,9 +894,16 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     if (u_out)
         LBM_TRY_HIP(hipMemsetAsync(u_out, 0, sizeof(float) * (p->with_rho ? 4 : 3) * g.nvox(), s));
 
-    hipEvent_t e0, e1;
-    LBM_TRY_HIP(hipEventCreate(&e0));
-    LBM_TRY_HIP(hipEventCreate(&e1));
+    struct Events {  // released on every return
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Events() {
+            if (e1) (void)hipEventDestroy(e1);
+            if (e0) (void)hipEventDestroy(e0);
+        }
+    } ev;
+    LBM_TRY_HIP(hipEventCreate(&ev.e0));
+    LBM_TRY_HIP(hipEventCreate(&ev.e1));
+    const hipEvent_t e0 = ev.e0, e1 = ev.e1;
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     double sums[kFlowSums] = {0, 0, 0, 0, 0, 0};
@@ -941,8 +948,6 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (out != LBM_OK) return out;
     h.cur = cur;
     h.steps_done = t0 + t;
