@@ -38,11 +38,11 @@ COUNTERS = {
     "k_sweep7<false, false, unsigned int>": dict(
         workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15341.1, write_kib=22966.8,
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="53f1b7130853c28f"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="dfc6c486c8137a23"),
     "k_sweep19<StoreF32, false, true, 0, false, unsigned int>": dict(
         workload="recon512_eps0.25_d16", fetch_kib=2142213.7, write_kib=2490369.4,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="557d46a9c7df684c"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="2bd94a8b945f1f9e"),
 }
 
 

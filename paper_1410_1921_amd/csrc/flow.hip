@@ -1314,7 +1314,10 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
                                  true, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
-                if (st != LBM_OK) return st;
+                if (st != LBM_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return st;
+                }
                 LBM_TRY_HIP(ec);
                 R.graph[gi * BatchRes::kKeys + cur] = graph;
                 LBM_TRY_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));

@@ -1365,7 +1365,10 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
                 st = kn_batch_steps(w, a, group_mode(groups[gi]), groups[gi], qc, chunk, true, p, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
-                if (st != LBM_OK) return st;
+                if (st != LBM_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return st;
+                }
                 LBM_TRY_HIP(ec);
                 R.graph[gi * BatchRes::kKeys + key] = graph;
                 LBM_TRY_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
