@@ -1161,6 +1161,37 @@ double orc_k_kozeny_carman(double d, double eps) {
     return d * d / 180.0 * eps * eps * eps / ((1.0 - eps) * (1.0 - eps));
 }
 
+/* ======================================================================
+ * Section 3.2 and Eq. 15: the lattice diffusivity of a mass-transport
+ * lattice, D_L = c_s^2 (tau - 1/2), with c_s^2 = 1/4 on D3Q7 (rest weight
+ * 1/4, face weights 1/8) and 1/3 on D3Q19.  Eq. 15 ties the lattice to
+ * physical units through the reference pore: a pore of diameter d_ref
+ * relaxes at tau_ref and diffuses at D_K(d_ref) (Eq. 11), so one time step
+ * lasts dt = D_L(tau_ref) dx^2 / D_K,ref and a lattice diffusivity D turns
+ * into D dx^2 / dt = D D_K,ref / D_L(tau_ref).
+ * ====================================================================== */
+double orc_lattice_diffusivity(double cs2, double tau) { return cs2 * (tau - 0.5); }
+
+double orc_time_step(double cs2, double tau_ref, double dx_m, double dk_ref) {
+    return orc_lattice_diffusivity(cs2, tau_ref) * dx_m * dx_m / dk_ref;
+}
+
+double orc_deff_physical(double deff_lattice, double cs2, double tau_ref, double dk_ref) {
+    return deff_lattice * dk_ref / orc_lattice_diffusivity(cs2, tau_ref);
+}
+
+/* Eq. 16 (Bruggeman form D_eff = (eps / tau) D): tortuosity from the effective
+ * and the free diffusivity at the same reference, both in lattice units. */
+double orc_tortuosity(double eps, double d_free, double deff) { return eps * d_free / deff; }
+
+/* Section 4.2: the exponent of D_eff / D = eps^alpha */
+double orc_bruggeman_alpha(double deff_over_d, double eps) { return log(deff_over_d) / log(eps); }
+
+/* Eq. 15 for the flow lattice: lengths scale with dx, so k (an area) with dx^2;
+ * one millidarcy is 9.869233e-16 m^2 */
+double orc_k_physical(double k_lattice, double dx_m) { return k_lattice * dx_m * dx_m; }
+double orc_m2_to_mD(double k_m2) { return k_m2 / 9.869233e-16; }
+
 /* the number of OpenMP threads the per-voxel loops use */
 #ifdef _OPENMP
 #include <omp.h>

@@ -125,6 +125,11 @@ def lib():
     L.orc_fc_dgm.restype = C.c_double
     L.orc_k_kozeny_carman.argtypes = [C.c_double] * 2
     L.orc_k_kozeny_carman.restype = C.c_double
+    for name, nargs in (("orc_lattice_diffusivity", 2), ("orc_time_step", 4),
+                        ("orc_deff_physical", 4), ("orc_tortuosity", 3),
+                        ("orc_bruggeman_alpha", 2), ("orc_k_physical", 2), ("orc_m2_to_mD", 1)):
+        getattr(L, name).argtypes = [C.c_double] * nargs
+        getattr(L, name).restype = C.c_double
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = C.c_int
     _lib = L
@@ -435,3 +440,38 @@ def fc_dgm(Deff, mu, k, P):
 
 def k_kozeny_carman(d, eps):
     return lib().orc_k_kozeny_carman(d, eps)
+
+
+# ---------------------------------------------------------------- Section 4 relations, Eq. 15
+def lattice_diffusivity(cs2, tau):
+    """D_L = c_s^2 (tau - 1/2) (Section 3.2)."""
+    return lib().orc_lattice_diffusivity(cs2, tau)
+
+
+def time_step(cs2, tau_ref, dx_m, dk_ref):
+    """Eq. 15: seconds per lattice step when a pore of tau_ref diffuses at dk_ref."""
+    return lib().orc_time_step(cs2, tau_ref, dx_m, dk_ref)
+
+
+def deff_physical(deff_lattice, cs2, tau_ref, dk_ref):
+    """Eq. 15: a lattice diffusivity in m^2/s."""
+    return lib().orc_deff_physical(deff_lattice, cs2, tau_ref, dk_ref)
+
+
+def tortuosity(eps, d_free, deff):
+    """Eq. 16: eps D / D_eff."""
+    return lib().orc_tortuosity(eps, d_free, deff)
+
+
+def bruggeman_alpha(deff_over_d, eps):
+    """Section 4.2: alpha of D_eff / D = eps^alpha."""
+    return lib().orc_bruggeman_alpha(deff_over_d, eps)
+
+
+def k_physical(k_lattice, dx_m):
+    """Eq. 15: permeability in m^2."""
+    return lib().orc_k_physical(k_lattice, dx_m)
+
+
+def m2_to_mD(k_m2):
+    return lib().orc_m2_to_mD(k_m2)
