@@ -67,12 +67,13 @@ typedef int32_t lbm_status;
 #define LBM_LATTICE_D3Q7 0  /* rest weight 1/4, face weights 1/8, c_s^2 = 1/4 */
 #define LBM_LATTICE_D3Q19 1 /* the paper's: a_i = 1/3, 1/18, 1/36, c_s^2 = 1/3 */
 
-/* population storage of the flow solve: the offsets f_i - w_i are stored in */
-#define LBM_STORE_FP32 0 /* binary32, collision in binary32 */
-#define LBM_STORE_FP16 1 /* binary16 offsets from w_i (1 + drho_w), drho_w = rho - 1 of the
-                            writing node (kept in binary32), times S = 2^k with
-                            S max|F| in [1, 2) (1 when F = 0); collision in binary32 */
-#define LBM_STORE_FP64 2 /* binary64, collision in binary64 */
+/* population storage of the flow solve */
+#define LBM_STORE_FP32 0 /* binary32 offsets f_i - w_i (1 + r_s), r_s a reference density
+                            (rho - 1) per 64-voxel row segment s: the segment mean of rho - 1
+                            at the last convergence check; collision in binary32 */
+#define LBM_STORE_FP16 1 /* binary16 of S (f_i - w_i (1 + r_s)), S = 2^k with S max|F| in
+                            [1, 2) (1 when F = 0); collision in binary32 */
+#define LBM_STORE_FP64 2 /* binary64 offsets f_i - w_i, collision in binary64 */
 
 /* x boundaries of the flow solve */
 #define LBM_BOUNDARY_PERIODIC 0 /* periodic in x (driven by the body force) */
@@ -212,7 +213,9 @@ lbm_status lbm_count(const int32_t n[3], const uint8_t *mask, int64_t *count_h, 
  * and u = u_init (or 0).  Every check_every steps (and at the last step) the
  * residual ||u(t) - u(t - n_c)|| / (n_c ||u(t)||) over fluid nodes is formed in
  * FP64; with fixed_steps > 0 exactly that many steps run, otherwise the solve stops
- * at the first check with residual < tol or at max_steps (LBM_W_NOT_CONVERGED).
+ * at the first check with residual < tol (and, with steady_tol > 0, an estimated distance
+ * to steady state at or below steady_tol; Section 3.4 takes k at steady state, and the
+ * residual alone bounds only the change per step) or at max_steps (LBM_W_NOT_CONVERGED).
  * Darcy (Eq. 13): k = nu <rho u_x> / F_x with nu = (tau - 1/2)/3 and the average
  * over the whole box; k_m2 = k voxel^2 (Eq. 15).
  *
@@ -261,6 +264,8 @@ typedef struct {
     int32_t boundary;     /* LBM_BOUNDARY_PERIODIC (0) or LBM_BOUNDARY_PRESSURE */
     int32_t reserved;
     double rho_in, rho_out; /* densities of the pressure boundaries (p = rho / 3) */
+    double steady_tol;    /* > 0: a check also needs the estimated distance to steady state
+                             (steady_dist of the result) at or below this; 0: residual only */
 } lbm_flow_params;
 
 typedef struct {
@@ -273,8 +278,10 @@ typedef struct {
     double sweep_ms;      /* GPU time of the stream-collide kernels (HIP events) */
     double mlups;         /* fluid-node updates per microsecond of sweep_ms */
     double gbps;          /* algorithmic bytes per second of sweep_ms: 152 per update
-                             (binary32), 304 (binary64), 84 (binary16: 76 + the writer
-                             density store and load) */
+                             (binary32), 304 (binary64), 76 (binary16) */
+    double steady_dist;   /* estimated ||u - u_steady|| / ||u|| at the last check: r n_c rho /
+                             (1 - rho), rho the mean decay ratio of the residual r over the
+                             last (up to) 5 check intervals; +inf while r does not decay */
 } lbm_flow_result;
 
 lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid, const lbm_flow_params *p,
@@ -286,9 +293,9 @@ lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid, const lbm_fl
 lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t steps, void *stream);
 
 /* Read the post-collision populations of `count` voxels from the state in
- * `workspace`: f_h[count][19] receives f_i - w_i (double: exact copies of the stored
- * values; for binary16 storage the stored offset divided by S plus w_i drho of the
- * node), fluid_h[count] whether the voxel is a fluid node (rows of solid voxels are 0).
+ * `workspace`: f_h[count][19] receives f_i - w_i (double: the stored value, divided by S
+ * for binary16 storage, plus w_i r_s of the node's segment for binary32 and binary16),
+ * fluid_h[count] whether the voxel is a fluid node (rows of solid voxels are 0).
  * count <= 65536. */
 lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_h, int64_t count,
                            double *f_h, uint8_t *fluid_h, void *stream);
@@ -355,7 +362,11 @@ lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h, const uint8_t
  * w_i C_out at x = nx (every population arriving from beyond an x face, diagonal ones
  * included, takes the ghost's value).  Starts from C = c_init (or 0); checks as in the
  * flow solve
- * with C as the field.  Eq. 14 on the lattice: D_eff = Phi_out / (ny nz) *
+ * with C as the field; with steady_tol > 0 a check with residual < tol also needs the
+ * spread (max - min)/|mean| of the link-plane fluxes at or below steady_tol (the mean
+ * taken as at least 1e-6 of the flux of an open box at tau_ref, so that a medium with no
+ * path between the faces, whose steady fluxes all vanish, can converge too).
+ * Eq. 14 on the lattice: D_eff = Phi_out / (ny nz) *
  * (nx + 1)/(C_in - C_out), Phi_out the net flux into the outlet ghost plane of the
  * last step's post-collision state.  Reported: D_eff / D_K,ref with D_K,ref =
  * c_s^2 (tau_ref - 1/2) in lattice units; D_eff in m^2/s via Eq. 11 at d_ref, T,
@@ -388,6 +399,9 @@ typedef struct {
     double tol;
     int32_t variant;      /* LBM_VARIANT_* (0: automatic) */
     int32_t lattice;      /* LBM_LATTICE_D3Q7 (0) or LBM_LATTICE_D3Q19 */
+    double steady_tol;    /* > 0: a check with residual < tol also needs the spread of the
+                             link-plane fluxes at or below this (at steady state every plane
+                             carries the same flux); 0: residual only */
 } lbm_knudsen_params;
 
 typedef struct {
@@ -399,6 +413,7 @@ typedef struct {
     double residual, sum_c;
     double sweep_ms, mlups, gbps;        /* gbps with 60 (D3Q7) or 156 (D3Q19) algorithmic
                                             bytes per update */
+    double steady_dist;                  /* as in lbm_flow_result, for C */
 } lbm_knudsen_result;
 
 lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid, const double *pore_diam,

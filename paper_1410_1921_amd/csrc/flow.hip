@@ -2,25 +2,29 @@
 // bounce-back, on the sparse fluid-node list (Section 3.1, Eqs. 1-3, 8-9; Section 3.3;
 // Darcy's law, Eq. 13).
 //
-// Storage: blocks of 256 nodes, each with its 19 arrays of 256 side by side (pop19), of
-// the offsets f_i - w_i ("shifted"
-// populations: the flow signal lives in deviations of order 1e-6 from w_i, which a float
-// keeps to ~1e-13 absolute once the constant w_i is removed), in binary32 (collision in
-// binary32) or binary64 (collision in binary64).  Two buffers, ping-pong.  Per
-// fluid-node update the method moves 19 loads + 19 stores of 4 or 8 bytes.
+// Storage: blocks of 256 nodes, each with its 19 arrays of 256 side by side (pop19).  Two
+// buffers, ping-pong.  Per fluid-node update the method moves 19 loads + 19 stores of 8,
+// 4 or 2 bytes.
 //
-// binary16 storage (collision in binary32) keeps each outgoing population as an offset
-// from the equilibrium weight times the writing node's own density,
-// h_i = S (f_i - w_i (1 + drho_w)), with drho_w = rho - 1 of the writer kept once per
-// node in binary32 (ping-pong like the populations), and S = 2^k with S max|F| in [1, 2).
-// Offsets from w_i alone fail in low-permeability media: where the body force is held by
-// pressure (dead ends, tortuous paths) the density part w_i drho exceeds the velocity
-// part by up to four decades and binary16's 11-bit significand loses u entirely.
-// Relative to the writer's density the stored values carry only the velocity and
-// non-equilibrium parts (Stokes flow is linear in F, so S h_i is of order one to a few
-// hundred).  A reader adds back w_i drho of the node it pulled from.  Per update: 19 + 19
-// populations of 2 bytes, one drho store and 19 drho gathers (cache resident, one value
-// per node).
+// binary64 (collision in binary64) stores the offsets f_i - w_i.  binary32 and binary16
+// (collision in binary32) store offsets from the equilibrium at rest of a reference
+// density per row segment: h_i = S (f_i - w_i (1 + r_s)), with r_s one binary32 value per
+// 64-voxel row segment s of the node (the segments of the rank map) and S = 1 for
+// binary32, S = 2^k with S max|F| in [1, 2) for binary16.  In low-permeability media the
+// body force is held by pressure (dead ends, tortuous paths), and the density part
+// w_i (rho - 1) of f_i - w_i exceeds the velocity part by up to four decades: stored
+// relative to w_i alone, binary32 loses ~1e-3 of k on the 128^3 crop of the 512^3 workload
+// and binary16 loses u entirely.  The pressure field is smooth on the scale of a
+// segment, so relative to r_s the stored values carry the velocity and non-equilibrium
+// parts and the small density variation within the segment.  The collision itself runs
+// on offsets from the node's own segment reference (a pulled value is moved there by
+// w_i (r_source - r_own), exact when the two references are within a factor two), with
+// rho = 1 + r_own + sum_i h_i; Eq. 3's f_eq and the MRT equilibrium moments are linear
+// in the density, so only the density offset changes.  The references are segment means
+// of rho - 1 taken at each convergence check; the first sweep of the next check interval
+// reads the state relative to the old references and writes it relative to the new ones
+// (two reference arrays, ping-pong).  The references cost one cache-resident 4-byte
+// gather per pull (8.4 MB at 512^3 against 33.5 MB of rank map).
 #include <algorithm>
 #include <vector>
 #include <cmath>
@@ -31,7 +35,7 @@
 
 namespace lbm {
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5735ull;  // "LBMFLOW5"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5736ull;  // "LBMFLOW6"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -45,6 +49,11 @@ struct FlowHeader {
     int32_t collision;
     int32_t boundary;          // LBM_BOUNDARY_*
     double rho_in, rho_out;    // pressure boundaries
+    int32_t sref;              // 1: offsets from per-segment reference densities
+    int32_t sframe;            // the reference array the stored state is relative to
+    int32_t sref_pending;      // 1: sref[sframe ^ 1] holds references of the last check
+                               // that the next sweep moves the state to
+    int32_t pad;
 };
 
 // Pressure boundaries: the populations entering through the inlet (e_x = +1) and the
@@ -74,11 +83,8 @@ static int pop_bytes(int32_t storage) {
     return storage == LBM_STORE_FP16 ? 2 : (storage == LBM_STORE_FP64 ? 8 : 4);
 }
 
-// Algorithmic HBM bytes per fluid-node update: 19 population loads and stores, plus the
-// writer densities for binary16 (one 4-byte store, and one 4-byte load per node).
-static double flow_bytes_per_update(int32_t storage) {
-    return 38.0 * pop_bytes(storage) + (storage == LBM_STORE_FP16 ? 8.0 : 0.0);
-}
+// Algorithmic HBM bytes per fluid-node update: 19 population loads and stores.
+static double flow_bytes_per_update(int32_t storage) { return 38.0 * pop_bytes(storage); }
 
 template <class P>
 __device__ inline typename P::R from_store(typename P::T v, float inv_scale) {
@@ -115,7 +121,8 @@ struct FlowWs {
     uint8_t *samp_flag;
     uint32_t *coords;
     void *f[2];
-    float *drho[2];  // binary16 storage: the writers' rho - 1 (ping-pong with f)
+    float *sref[2];  // per-segment reference densities rho - 1 (binary32, binary16)
+    float *dsnap;    // rho - 1 per node at the last check (the next references)
     float *usnap;
     double *partials;
     void *ghost;     // pressure boundaries: ghost-plane populations [2][5][ny nz]
@@ -143,6 +150,9 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage)
     w.res = c.take<double>(32);
     w.total = c.take<int32_t>(1);
     w.rank = c.take<RankWord>(g.nsegs());
+    const size_t nref = storage == LBM_STORE_FP64 ? 0 : (size_t)g.nsegs();
+    w.sref[0] = c.take<float>(nref);
+    w.sref[1] = c.take<float>(nref);
     w.samp_vox = c.take<int64_t>(kSampleMax);
     w.samp_out = c.take<double>((size_t)kSampleMax * 19);
     w.samp_flag = c.take<uint8_t>(kSampleMax);
@@ -151,9 +161,7 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage)
     w.coords = c.take<uint32_t>(nfp);
     w.f[0] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
     w.f[1] = c.take<char>((size_t)19 * w.stride * pop_bytes(storage));
-    const size_t ndr = storage == LBM_STORE_FP16 ? (size_t)w.stride : 0;
-    w.drho[0] = c.take<float>(ndr);
-    w.drho[1] = c.take<float>(ndr);
+    w.dsnap = c.take<float>(storage == LBM_STORE_FP64 ? 0 : (size_t)w.stride);
     w.usnap = c.take<float>((size_t)3 * w.stride);
     w.partials = c.take<double>((size_t)xcd_launch(blocks_for(nfp)) * kFlowSums);
     w.ghost = c.take<double>((size_t)10 * g.ny * g.nz);
@@ -173,8 +181,10 @@ struct Sweep19 {
     const RankWord *__restrict__ rank;
     const void *__restrict__ src;
     void *__restrict__ dst;
-    const float *__restrict__ drho_src;  // binary16 storage only
-    float *__restrict__ drho_dst;
+    const float *__restrict__ sref_src;  // segment references of the state read
+    const float *__restrict__ sref_dst;  // ... and of the state written (when reframe)
+    int reframe;                         // 1: sref_dst differs from sref_src
+    float *__restrict__ dsnap;           // check variant: rho - 1 per node
     float omega, fpre, Fx, Fy, Fz, sq; // collision parameters for binary32 arithmetic
     double omega_d, fpre_d, Fd[3], sq_d;  // and for binary64 (sq: the MRT rate s_q)
     float scale, inv_scale;            // binary16 storage scale
@@ -315,11 +325,13 @@ __device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
 }
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
-// the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back).
+// the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back); rs[i] the
+// reference density of the source's segment (rs[0]: the node's own), binary32 and
+// binary16 storage.
 template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
-                              const int (&ids)[19], const int (&gidx)[19],
-                              double (&acc)[kFlowSums]) {
+                              const int (&ids)[19], const int (&gidx)[19], const float (&rs)[19],
+                              int64_t seg_own, double (&acc)[kFlowSums]) {
     using T = typename P::T;
     using R = typename P::R;
     LBM_D3Q19_TABLES
@@ -345,17 +357,18 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
         for (int i = 1; i < 19; i++)
             if (EX[i] != 0 && ids[i] == -2) f[i] = from_store<P>(gh[gidx[i]], a.inv_scale);
     }
-    if constexpr (std::is_same<T, _Float16>::value) {
-        // add back w_i drho of the writer: the neighbour pulled from, or the node itself
-        // for the rest population and bounced ones
-        float dr[19];
-        dr[0] = a.drho_src[n];
+    constexpr bool kRef = !std::is_same<T, double>::value;
+    if constexpr (kRef) {
+        // move pulled values to offsets from the node's own segment reference (sources in
+        // another segment; a ghost value is relative to its boundary node's segment,
+        // which rs[i] holds); the rest population and bounced ones are the node's own
 #pragma unroll
-        for (int i = 1; i < 19; i++) dr[i] = a.drho_src[ids[i] >= 0 ? ids[i] : n];
-#pragma unroll
-        for (int i = 0; i < 19; i++) f[i] += (i == 0 ? W0 : (i < 7 ? W1 : W2)) * dr[i];
+        for (int i = 1; i < 19; i++)
+            if (ids[i] >= 0 || (OPEN && ids[i] == -2))  // one rounding, in every variant
+                f[i] = __builtin_fmaf(i < 7 ? 1.f / 18.f : 1.f / 36.f, rs[i] - rs[0], f[i]);
     }
 
+    // drho: the density offset from 1 + rs[0] (from 1 for binary64)
     R drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < 19; i++) {
@@ -364,7 +377,7 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
         if (EY[i]) jy += EY[i] > 0 ? f[i] : -f[i];
         if (EZ[i]) jz += EZ[i] > 0 ? f[i] : -f[i];
     }
-    const R rho = R(1) + drho;
+    const R rho = kRef ? (R(1) + R(rs[0])) + drho : R(1) + drho;
     const R inv = R(1) / rho;
     const R mx = jx + R(0.5) * Fx, my = jy + R(0.5) * Fy, mz = jz + R(0.5) * Fz;
     const R ux = mx * inv, uy = my * inv, uz = mz * inv;
@@ -388,19 +401,23 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
             posts[i] = f[i] - omega * (f[i] - feq) + srcf;
         }
     }
+    R shift = 0;  // the first sweep of a check interval moves to the new references
+    if constexpr (kRef)
+        if (a.reframe) shift = R(rs[0]) - R(a.sref_dst[seg_own]);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
         R post = posts[i];
-        if constexpr (std::is_same<T, _Float16>::value) post -= w * drho;
+        if constexpr (kRef) post = __builtin_fmaf(w, shift, post);
         const T out = to_store<P>(post, a.scale);
         if (NT)
             __builtin_nontemporal_store(out, &dst[pop19(i, n)]);
         else
             dst[pop19(i, n)] = out;
     }
-    if constexpr (std::is_same<T, _Float16>::value) a.drho_dst[n] = drho;
     if (CHECK) {
+        const R drho_abs = kRef ? R(rs[0]) + drho : drho;  // rho - 1
+        if constexpr (kRef) a.dsnap[n] = (float)drho_abs;
         const double dux = (double)ux - (double)a.usnap[n];
         const double duy = (double)uy - (double)a.usnap[a.stride + n];
         const double duz = (double)uz - (double)a.usnap[2 * a.stride + n];
@@ -409,7 +426,7 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
         acc[2] += (double)jx + 0.5 * (double)Fx;
         acc[3] += (double)jy + 0.5 * (double)Fy;
         acc[4] += (double)jz + 0.5 * (double)Fz;
-        acc[5] += drho;
+        acc[5] += kRef ? (double)rs[0] + (double)drho : (double)drho;
         if (a.update_snap) {
             a.usnap[n] = (float)ux;
             a.usnap[a.stride + n] = (float)uy;
@@ -420,7 +437,7 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
             a.u_out[v] = (float)ux;
             a.u_out[nv + v] = (float)uy;
             a.u_out[2 * nv + v] = (float)uz;
-            if (a.with_rho) a.u_out[3 * nv + v] = (float)drho;
+            if (a.with_rho) a.u_out[3 * nv + v] = (float)drho_abs;
         }
     }
 }
@@ -462,11 +479,20 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
         wz[k] = zs[k] * (g.ny * g.nseg);
         bx[k] = xs[k] & (kSeg - 1);
     }
-    // the 18 rank words are loaded as one batch, then the 19 populations as another
+    // the 18 rank words (and segment references) are loaded as one batch, then the 19
+    // populations as another
     RankHalf rh[19];
+    float rs[19];
+    const int64_t seg_own = (int64_t)wx[1] + wy[1] + wz[1];
 #pragma unroll
-    for (int i = 1; i < 19; i++)
-        rh[i] = rank_half(a.rank, wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]], bx[1 - EX[i]]);
+    for (int i = 1; i < 19; i++) {
+        const int64_t sg = (int64_t)wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]];
+        rh[i] = rank_half(a.rank, sg, bx[1 - EX[i]]);
+        if constexpr (!std::is_same<P, StoreF64>::value) rs[i] = a.sref_src[sg];
+        else rs[i] = 0.f;
+    }
+    if constexpr (!std::is_same<P, StoreF64>::value) rs[0] = a.sref_src[seg_own];
+    else rs[0] = 0.f;
     int ids[19], gidx[19];
     ids[0] = 0;
 #pragma unroll
@@ -481,7 +507,7 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
             gidx[i] = ((side * 5 + GSLOT[i]) * g.nz + zs[1 - EZ[i]]) * g.ny + ys[1 - EY[i]];
         }
     }
-    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, acc);
+    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, rs, seg_own, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
@@ -536,6 +562,9 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
         b.rank = a.rank + D.rk0;
         b.src = static_cast<const float *>(a.src) + 19 * n0;
         b.dst = static_cast<float *>(a.dst) + 19 * n0;
+        b.sref_src = a.sref_src + D.rk0;
+        b.sref_dst = a.sref_dst + D.rk0;
+        b.dsnap = a.dsnap + n0;
         b.usnap = a.usnap + 3 * n0;
         b.u_out = D.u_out;
         const int64_t n = (pb - D.b0) * 256 + threadIdx.x;
@@ -548,11 +577,13 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
 // beyond boundary node b (x = 0 or nx - 1, same y, z) holds f(b) + f_eq(rho_bc, u_b) -
 // f_eq(rho_b, u_b), with rho_b, u_b the moments of b's state (u_b = (j - F/2)/rho_b, the
 // velocity of b's collision) and f_eq of Eq. 3; only the five populations entering the
-// domain are kept, as offsets f_i - w_i, in ghost[side][slot][z ny + y].  A ghost beside a
-// solid b is solid (the sweep bounces back) and is not written.
+// domain are kept, as offsets from w_i (1 + r) with r the reference density of b's
+// segment (sref, null for binary64 storage), in ghost[side][slot][z ny + y].  A ghost
+// beside a solid b is solid (the sweep bounces back) and is not written.
 template <class P>
 __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restrict__ rank,
                                                  const typename P::T *__restrict__ src,
+                                                 const float *__restrict__ sref,
                                                  float inv_scale, float scale,
                                                  typename P::R Fx, typename P::R Fy,
                                                  typename P::R Fz, typename P::R drho_in,
@@ -567,9 +598,11 @@ __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restr
     const int side = (int)(t / m);
     const int64_t yz = t % m;
     const int y = (int)(yz % g.ny), z = (int)(yz / g.ny);
-    const int id = node_at(rank, g, side ? g.nx - 1 : 0, y, z);
+    const int xb = side ? g.nx - 1 : 0;
+    const int id = node_at(rank, g, xb, y, z);
     if (id < 0) return;
-    R f[19], drho = 0, jx = 0, jy = 0, jz = 0;
+    const R ref = sref ? R(sref[g.seg(xb, y, z)]) : R(0);
+    R f[19], drho = 0, jx = 0, jy = 0, jz = 0;  // drho: offset from 1 + ref
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         f[i] = from_store<P>(src[pop19(i, id)], inv_scale);
@@ -580,7 +613,7 @@ __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restr
     }
     // the density jump from the offsets (rho_bc - 1) - (rho_b - 1): both near 0, so
     // binary32 keeps it to rounding (rho_bc - rho_b formed near 1 would lose ~1e-7)
-    const R rho = R(1) + drho, jump = (side ? drho_out : drho_in) - drho;
+    const R rho = (R(1) + ref) + drho, jump = ((side ? drho_out : drho_in) - ref) - drho;
     const R ux = (jx - R(0.5) * Fx) / rho, uy = (jy - R(0.5) * Fy) / rho, uz = (jz - R(0.5) * Fz) / rho;
     const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
@@ -593,46 +626,78 @@ __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restr
     }
 }
 
-// f - w_i at the equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x,
-// u_y, u_z and, with with_rho, rho - 1; rest and rho = 1 without it); the snapshot
-// starts at that u.
+// rho - 1 of the initial state per node: the fourth plane of u_init with with_rho, else 0
+// (the first segment references are its segment means).
+__global__ __launch_bounds__(256) void k_flow_drho0(Grid g, int64_t nf,
+                                                    const uint32_t *__restrict__ coords,
+                                                    const float *__restrict__ u_init, int with_rho,
+                                                    float *__restrict__ dsnap) {
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nf) return;
+    float dr = 0.f;
+    if (u_init && with_rho) {
+        const uint32_t c = coords[n];
+        dr = u_init[3 * g.nvox() + g.lin(c & 1023, (c >> 10) & 1023, c >> 20)];
+    }
+    dsnap[n] = dr;
+}
+
+// The reference density of each row segment: the mean of rho - 1 over its fluid nodes
+// (dsnap[id], the segment's ids are consecutive from its base), 0 without any.
+__global__ __launch_bounds__(256) void k_seg_ref(int64_t nsegs, const RankWord *__restrict__ rank,
+                                                 const float *__restrict__ dsnap,
+                                                 float *__restrict__ sref) {
+    const int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (sg >= nsegs) return;
+    const RankWord w = rank[sg];
+    const int c = __popc(w.lo) + __popc(w.hi);
+    double sum = 0.0;
+    for (int k = 0; k < c; k++) sum += (double)dsnap[w.base + k];
+    sref[sg] = c ? (float)(sum / c) : 0.f;
+}
+
+// The equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x, u_y, u_z and,
+// with with_rho, rho - 1; rest and rho = 1 without it), stored as offsets from
+// w_i (1 + r) with r the segment reference (sref; null: 0, binary64); the snapshot starts
+// at that u.
 template <class P>
 __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t stride,
                                                    const uint32_t *__restrict__ coords,
                                                    const float *__restrict__ u_init, int with_rho,
                                                    typename P::T *__restrict__ f, float scale,
-                                                   float *__restrict__ drho,
+                                                   const float *__restrict__ sref,
                                                    float *__restrict__ usnap) {
     using R = typename P::R;
     LBM_D3Q19_TABLES
     const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (n >= nf) return;
+    const uint32_t c = coords[n];
+    const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
     R ux = 0, uy = 0, uz = 0, dr = 0;
     if (u_init) {
-        const uint32_t c = coords[n];
-        const int64_t v = g.lin(c & 1023, (c >> 10) & 1023, c >> 20), nv = g.nvox();
+        const int64_t v = g.lin(x, y, z), nv = g.nvox();
         ux = u_init[v]; uy = u_init[nv + v]; uz = u_init[2 * nv + v];
         if (with_rho) dr = u_init[3 * nv + v];
     }
+    const R ref = sref ? R(sref[g.seg(x, y, z)]) : R(0);
     const R rho = R(1) + dr;
     const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         const R w = i == 0 ? R(1) / R(3) : (i < 7 ? R(1) / R(18) : R(1) / R(36));
         const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-        R dev = w * rho * (R(3) * eu + R(4.5) * eu * eu - uu15);  // f_eq - w_i (1 + drho)
-        if (!drho) dev += w * dr;                                 // f_eq - w_i
+        // f_eq - w_i (1 + drho), plus w_i (drho - ref)
+        const R dev = w * rho * (R(3) * eu + R(4.5) * eu * eu - uu15) + w * (dr - ref);
         f[pop19(i, n)] = to_store<P>(dev, scale);
     }
     usnap[n] = (float)ux; usnap[stride + n] = (float)uy; usnap[2 * stride + n] = (float)uz;
-    if (drho) drho[n] = (float)dr;
 }
 
 template <class P>
 __global__ void k_flow_sample(Grid g, int64_t count,
                               const int64_t *__restrict__ vox, const RankWord *__restrict__ rank,
                               const typename P::T *__restrict__ f, float inv_scale,
-                              const float *__restrict__ drho, double *__restrict__ out,
+                              const float *__restrict__ sref, double *__restrict__ out,
                               uint8_t *__restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
@@ -640,10 +705,11 @@ __global__ void k_flow_sample(Grid g, int64_t count,
     const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
     const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
+    const double ref = sref && id >= 0 ? (double)sref[g.seg(x, y, z)] : 0.0;
     for (int i = 0; i < 19; i++) {
         double v = id >= 0 ? (double)from_store<P>(f[pop19(i, id)], inv_scale) : 0.0;
-        if (drho && id >= 0)  // binary16: offsets are taken from w_i (1 + drho) of the node
-            v += (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)) * (double)drho[id];
+        if (id >= 0)  // offsets are taken from w_i (1 + r) of the node's segment
+            v += (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)) * ref;
         out[s * 19 + i] = v;
     }
 }
@@ -706,7 +772,11 @@ static void launch19(const Sweep19 &a, const Variant19 &m, int32_t storage, int3
     else launch19c<CHECK, LBM_COLLIDE_BGK>(a, m, storage, s);
 }
 
-static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, const FlowHeader &h,
+// `steps` sweeps from buffer cur; the last one checks when check_last.  When the last check
+// left new references (h.sref_pending), the first sweep moves the state to them, whichever
+// entry point runs it, so that a solve split into steps and resumes goes through the same
+// arithmetic as one run.
+static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, FlowHeader &h,
                                 const Variant19 &m, int &cur, int64_t steps, bool check_last,
                                 float *u_out, int with_rho, hipStream_t s) {
     Sweep19 a;
@@ -734,23 +804,29 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
     a.partials = w.partials;
     a.update_snap = 1;
     a.with_rho = with_rho;
+    a.dsnap = w.dsnap;
     const bool open = h.boundary == LBM_BOUNDARY_PRESSURE;
     a.ghost = open ? w.ghost : nullptr;
     const unsigned gblocks = (unsigned)((2 * (int64_t)g.ny * g.nz + 255) / 256);
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
-        a.drho_src = w.drho[cur];
-        a.drho_dst = w.drho[cur ^ 1];
+        a.reframe = 0;
+        a.sref_src = a.sref_dst = h.sref ? w.sref[h.sframe] : nullptr;
+        if (h.sref && h.sref_pending) {
+            a.sref_dst = w.sref[h.sframe ^ 1];
+            a.reframe = 1;
+            h.sref_pending = 0;
+        }
         if (open) {  // the ghost planes of this step, from the state it reads
             if (h.storage == LBM_STORE_FP64)
                 k_ghost19<StoreF64><<<gblocks, 256, 0, s>>>(
-                    g, w.rank, static_cast<const double *>(a.src), 1.f, 1.f,
+                    g, w.rank, static_cast<const double *>(a.src), nullptr, 1.f, 1.f,
                     h.force[0], h.force[1], h.force[2], h.rho_in - 1.0, h.rho_out - 1.0,
                     static_cast<double *>(w.ghost));
             else
                 k_ghost19<StoreF32><<<gblocks, 256, 0, s>>>(
-                    g, w.rank, static_cast<const float *>(a.src), 1.f, 1.f,
+                    g, w.rank, static_cast<const float *>(a.src), a.sref_src, 1.f, 1.f,
                     (float)h.force[0], (float)h.force[1], (float)h.force[2],
                     (float)(h.rho_in - 1.0), (float)(h.rho_out - 1.0),
                     static_cast<float *>(w.ghost));
@@ -762,7 +838,19 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, cons
             launch19<false>(a, m, h.storage, h.collision, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
+        if (a.reframe) h.sframe ^= 1;
     }
+    return LBM_OK;
+}
+
+// After a check interval: the segment means of the checked rho - 1 become the references
+// the next interval moves to.
+static lbm_status flow_next_refs(const FlowWs &w, const Grid &g, FlowHeader &h, hipStream_t s) {
+    if (!h.sref) return LBM_OK;
+    k_seg_ref<<<(unsigned)((g.nsegs() + 255) / 256), 256, 0, s>>>(g.nsegs(), w.rank, w.dsnap,
+                                                                   w.sref[h.sframe ^ 1]);
+    LBM_CHECK_LAUNCH();
+    h.sref_pending = 1;
     return LBM_OK;
 }
 
@@ -798,6 +886,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
                 LBM_E_INVAL, "the force must be finite and the voxel size positive and finite");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->steady_tol >= 0.0 && std::isfinite(p->steady_tol), LBM_E_INVAL,
+                "steady_tol must be finite and >= 0");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 || p->storage == LBM_STORE_FP16 ||
                     p->storage == LBM_STORE_FP64,
                 LBM_E_INVAL, "unknown storage %d", p->storage);
@@ -843,6 +933,12 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
                         h.collision == p->collision && h.boundary == p->boundary,
                     LBM_E_INVAL,
                     "resume: the workspace holds no state for this geometry and storage");
+        // the state continues only under the parameters it was computed with
+        const bool press = p->boundary == LBM_BOUNDARY_PRESSURE;
+        LBM_REQUIRE(h.tau == p->tau && h.force[0] == p->force[0] && h.force[1] == p->force[1] &&
+                        h.force[2] == p->force[2] &&
+                        (!press || (h.rho_in == p->rho_in && h.rho_out == p->rho_out)),
+                    LBM_E_INVAL, "resume: tau, force or boundary densities differ from the state's");
         t0 = h.steps_done;
         cur = h.cur;
     }
@@ -865,6 +961,9 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     h.boundary = p->boundary;
     h.rho_in = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_in : 1.0;
     h.rho_out = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_out : 1.0;
+    h.sref = p->storage != LBM_STORE_FP64;
+    if (!p->resume) h.sframe = h.sref_pending = 0;
+    h.pad = 0;
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
         // binary16: a power of two S with S max|F| in [1, 2) (1 without a force)
@@ -877,10 +976,18 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         const unsigned nb = (unsigned)blocks_for(nf);
         const float sc = (float)h.scale;
         const int wr = p->with_rho;
+        if (h.sref) {
+            // the first references: segment means of the initial density
+            k_flow_drho0<<<nb, 256, 0, s>>>(g, nf, w.coords, u_init, wr, w.dsnap);
+            LBM_CHECK_LAUNCH();
+            k_seg_ref<<<(unsigned)((g.nsegs() + 255) / 256), 256, 0, s>>>(g.nsegs(), w.rank,
+                                                                           w.dsnap, w.sref[0]);
+            LBM_CHECK_LAUNCH();
+        }
         if (h.storage == LBM_STORE_FP16)
             k_flow_init<StoreF16><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<_Float16 *>(w.f[0]), sc,
-                                                     w.drho[0], w.usnap);
+                                                     w.sref[0], w.usnap);
         else if (h.storage == LBM_STORE_FP64)
             k_flow_init<StoreF64><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<double *>(w.f[0]), sc,
@@ -888,7 +995,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         else
             k_flow_init<StoreF32><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<float *>(w.f[0]), sc,
-                                                     nullptr, w.usnap);
+                                                     w.sref[0], w.usnap);
         LBM_CHECK_LAUNCH();
     }
     if (u_out)
@@ -908,6 +1015,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     const int nc = p->check_every;
     double sums[kFlowSums] = {0, 0, 0, 0, 0, 0};
     double resid = INFINITY, sweep_ms = 0.0;
+    SteadyEst est;
     bool converged = false, diverged = false, stalled = false;
     int64_t t = 0;
     lbm_status out = LBM_OK;
@@ -920,6 +1028,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         out = launch_sweeps(w, g, nf, h, mode, cur, chunk, true, u_out, p->with_rho, s);
         if (out != LBM_OK) break;
         LBM_TRY_HIP(hipEventRecord(e1, s));
+        out = flow_next_refs(w, g, h, s);
+        if (out != LBM_OK) break;
         out = reduce_partials(w.partials, blocks_for(nf), kFlowSums, w.res, s);
         if (out != LBM_OK) break;
         LBM_TRY_HIP(hipMemcpyAsync(sums, w.res, sizeof(sums), hipMemcpyDeviceToHost, s));
@@ -934,6 +1044,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         }
         if ((t0 + t) % nc == 0) {
             resid = std::sqrt(sums[0]) / ((double)nc * std::sqrt(sums[1]));
+            est.push(resid);
             // binary16: a check interval with no change at all is a fixed point of the
             // rounded iteration (every per-step increment below half an ulp), not steady
             // state; the solve stops and says so
@@ -942,7 +1053,8 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
                 stalled = true;
                 break;
             }
-            if (p->fixed_steps <= 0 && resid < p->tol) {
+            if (p->fixed_steps <= 0 && resid < p->tol &&
+                (p->steady_tol <= 0.0 || est.dist(nc) <= p->steady_tol)) {
                 converged = true;
                 break;
             }
@@ -961,6 +1073,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     r->n_fluid = nf;
     r->converged = converged;
     r->residual = resid;
+    r->steady_dist = est.dist(nc);
     for (int a = 0; a < 3; a++) r->mean_rho_u[a] = sums[2 + a] / nvox;
     r->mass_dev = sums[5];
     // the driving: F_x, plus c_s^2 (rho_in - rho_out) over the nx + 1 spacings between the
@@ -1045,7 +1158,7 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     if (h.storage == LBM_STORE_FP16)
         k_flow_sample<StoreF16><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const _Float16 *>(w.f[h.cur]), inv,
-                                                   w.drho[h.cur], w.samp_out, w.samp_flag);
+                                                   w.sref[h.sframe], w.samp_out, w.samp_flag);
     else if (h.storage == LBM_STORE_FP64)
         k_flow_sample<StoreF64><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const double *>(w.f[h.cur]), inv,
@@ -1053,7 +1166,7 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     else
         k_flow_sample<StoreF32><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const float *>(w.f[h.cur]), inv,
-                                                   nullptr, w.samp_out, w.samp_flag);
+                                                   w.sref[h.sframe], w.samp_out, w.samp_flag);
     LBM_CHECK_LAUNCH();
     LBM_TRY_HIP(hipMemcpyAsync(f_h, w.samp_out, sizeof(double) * 19 * count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(fluid_h, w.samp_flag, count, hipMemcpyDeviceToHost, s));
@@ -1072,6 +1185,8 @@ struct BatchWs {
     RankWord *rank;
     uint32_t *coords;
     float *f[2];
+    float *sref[2];  // per-segment reference densities (rank-map order)
+    float *dsnap;
     float *usnap;
     double *partials;
     int64_t stride, nblk, nrank;
@@ -1095,9 +1210,12 @@ static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int6
     w.total = c.take<int32_t>(count);
     w.res = c.take<double>((size_t)count * kFlowSums);
     w.rank = c.take<RankWord>(w.nrank);
+    w.sref[0] = c.take<float>(w.nrank);
+    w.sref[1] = c.take<float>(w.nrank);
     w.coords = c.take<uint32_t>(w.stride);
     w.f[0] = c.take<float>((size_t)19 * w.stride);
     w.f[1] = c.take<float>((size_t)19 * w.stride);
+    w.dsnap = c.take<float>(w.stride);
     w.usnap = c.take<float>((size_t)3 * w.stride);
     w.partials = c.take<double>((size_t)w.nblk * kFlowSums);
     w.bytes = c.off;
@@ -1120,11 +1238,19 @@ static void launch19b(const Sweep19 &a, const Variant19 &m, int32_t collision,
     }
 }
 
-// `steps` sweeps of the lattices of group g from buffer cur; the last one checks, then
-// the group's per-lattice sums go to w.res.
+// A lattice's place in the batch, for the per-lattice passes on the host side.
+struct LatRef {
+    int64_t nsegs, rk0, n0;
+};
+
+// `steps` sweeps of the lattices of group g from buffer cur and reference frame sframe;
+// with `pending` the first one moves the state to the references of the last check; the
+// last one checks, then the group's per-lattice sums go to w.res and the segment means of
+// each lattice's rho - 1 become its next references (as in the single solve).
 static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, int32_t collision,
-                              const BatchGroup &g, int cur, int64_t steps, bool check_last,
-                              hipStream_t s) {
+                              const BatchGroup &g, int cur, int sframe, bool pending,
+                              int64_t steps, bool check_last, const std::vector<LatRef> &lr,
+                              const std::vector<int32_t> &lat_ids_h, hipStream_t s) {
     const int64_t n_live = g.n_blk;
     a.launched_live = n_live;
     a.chunk = m.remap ? (n_live + kXcd - 1) / kXcd : 0;
@@ -1133,21 +1259,35 @@ static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, i
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
+        a.sref_src = a.sref_dst = w.sref[sframe];
+        a.reframe = 0;
+        if (pending && t == 0) {
+            a.sref_dst = w.sref[sframe ^ 1];
+            a.reframe = 1;
+        }
         if (check_last && t == steps - 1) launch19b<true>(a, m, collision, descs, s);
         else launch19b<false>(a, m, collision, descs, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
+        if (a.reframe) sframe ^= 1;
     }
     if (check_last) {
         k_lat_reduce<kFlowSums><<<(unsigned)g.n_lat, 256, 0, s>>>(w.partials, w.lats,
                                                                   w.lat_ids + g.lat_off, w.res);
         LBM_CHECK_LAUNCH();
+        if (steps > 0)
+            for (int32_t k = 0; k < g.n_lat; k++) {
+                const LatRef &L = lr[lat_ids_h[g.lat_off + k]];
+                k_seg_ref<<<(unsigned)((L.nsegs + 255) / 256), 256, 0, s>>>(
+                    L.nsegs, w.rank + L.rk0, w.dsnap + L.n0, w.sref[sframe ^ 1] + L.rk0);
+                LBM_CHECK_LAUNCH();
+            }
     }
     return LBM_OK;
 }
 
-// Binary32 flow state per fluid node: two population buffers, coordinate, snapshot.
-constexpr double kBatchFlowNodeBytes = 2 * 19 * 4 + 4 + 12;
+// Binary32 flow state per fluid node: two population buffers, coordinate, snapshots.
+constexpr double kBatchFlowNodeBytes = 2 * 19 * 4 + 4 + 12 + 4;
 
 }  // namespace lbm
 
@@ -1178,6 +1318,8 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
                 LBM_E_INVAL, "the force must be finite and the voxel size positive and finite");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->steady_tol >= 0.0 && std::isfinite(p->steady_tol), LBM_E_INVAL,
+                "steady_tol must be finite and >= 0");
     LBM_REQUIRE(p->storage == LBM_STORE_FP32 && !p->resume && !p->with_rho, LBM_E_INVAL,
                 "batched solves take binary32 storage, no resume, no density fields");
     LBM_REQUIRE(p->collision == LBM_COLLIDE_BGK || p->collision == LBM_COLLIDE_MRT ||
@@ -1209,6 +1351,7 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     std::vector<BatchLat> bl(count);
     std::vector<BlkDesc19> blk(w.nblk);  // the record of each physical block
     std::vector<double> nvox(count);
+    std::vector<LatRef> lref(count);
     int64_t n0 = 0, rk0 = 0, b0 = 0;
     for (int l = 0; l < count; l++) {
         const Grid g = make_grid(n_h + 3 * l);
@@ -1220,10 +1363,13 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         st = layout_fill(g, w.rank + rk0, w.coords + n0, s);
         if (st != LBM_OK) return st;
         const int64_t b1 = b0 + blocks_for(nf), span = (b1 - b0) * 256;
+        // from rest: every reference density 0
+        LBM_TRY_HIP(hipMemsetAsync(w.sref[0] + rk0, 0, sizeof(float) * g.nsegs(), s));
         k_flow_init<StoreF32><<<(unsigned)blocks_for(nf), 256, 0, s>>>(
-            g, nf, span, w.coords + n0, nullptr, 0, w.f[0] + 19 * n0, 1.f, nullptr,
+            g, nf, span, w.coords + n0, nullptr, 0, w.f[0] + 19 * n0, 1.f, w.sref[0] + rk0,
             w.usnap + 3 * n0);
         LBM_CHECK_LAUNCH();
+        lref[l] = LatRef{g.nsegs(), rk0, n0};
         float *uo = u_out ? u_out[l] : nullptr;
         if (uo) LBM_TRY_HIP(hipMemsetAsync(uo, 0, sizeof(float) * 3 * g.nvox(), s));
         lats[l] = LatDesc{b0, b1};
@@ -1276,13 +1422,15 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     a.scale = 1.f;
     a.inv_scale = 1.f;
     a.usnap = w.usnap;
+    a.dsnap = w.dsnap;
     a.partials = w.partials;
     a.update_snap = 1;
 
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
-    int cur = 0;
+    int cur = 0, sframe = 0;
+    bool pending = false;  // references of a check not yet entered (none before the first)
     int64_t t = 0;
     double sweep_ms = 0.0, updates = 0.0, tune_ms = 0.0;
 
@@ -1300,18 +1448,21 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     std::vector<double> res((size_t)count * kFlowSums, 0.0), sums_l((size_t)count * kFlowSums, 0.0);
     std::vector<int64_t> steps_l(count, 0);
     std::vector<double> resid_l(count, INFINITY);
+    std::vector<SteadyEst> est_l(count);
     std::vector<int> conv_l(count, 0);
     bool diverged = false;
     while (t < limit && !act.empty()) {
         const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
-        if (use_graph && chunk == nc) {
-            // capture what is missing first, so that the timed region holds kernels only
+        if (use_graph && chunk == nc && pending) {
+            // capture what is missing first, so that the timed region holds kernels only;
+            // one graph per group and (buffer, reference frame) at the start of the interval
+            const int key = cur * 2 + sframe;
             for (size_t gi = 0; gi < groups.size(); gi++) {
-                hipGraphExec_t &ex = R.exec[gi * BatchRes::kKeys + cur];
+                hipGraphExec_t &ex = R.exec[gi * BatchRes::kKeys + key];
                 if (ex) continue;
                 LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                st = batch_steps(w, a, group_mode(groups[gi]), p->collision, groups[gi], cur, chunk,
-                                 true, s);
+                st = batch_steps(w, a, group_mode(groups[gi]), p->collision, groups[gi], cur,
+                                 sframe, true, chunk, true, lref, lat_ids_h, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (st != LBM_OK) {
@@ -1319,16 +1470,17 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
                     return st;
                 }
                 LBM_TRY_HIP(ec);
-                R.graph[gi * BatchRes::kKeys + cur] = graph;
+                R.graph[gi * BatchRes::kKeys + key] = graph;
                 LBM_TRY_HIP(hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0));
             }
             LBM_TRY_HIP(hipEventRecord(R.e0, s));
             for (size_t gi = 0; gi < groups.size(); gi++)
-                LBM_TRY_HIP(hipGraphLaunch(R.exec[gi * BatchRes::kKeys + cur], s));
+                LBM_TRY_HIP(hipGraphLaunch(R.exec[gi * BatchRes::kKeys + key], s));
         } else {
             LBM_TRY_HIP(hipEventRecord(R.e0, s));
             for (const BatchGroup &g : groups) {
-                st = batch_steps(w, a, group_mode(g), p->collision, g, cur, chunk, true, s);
+                st = batch_steps(w, a, group_mode(g), p->collision, g, cur, sframe, pending,
+                                 chunk, true, lref, lat_ids_h, s);
                 if (st != LBM_OK) return st;
             }
         }
@@ -1353,6 +1505,8 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
             regroup_now = tune_k < kBatchBudgets || budget != cand[kBatchBudgets - 1];
         }
         cur ^= (int)(chunk & 1);
+        if (pending) sframe ^= 1;  // the interval moved to the last check's references
+        pending = true;            // and its check formed the next ones
         t += chunk;
         std::vector<int32_t> keep;
         for (int l : act) {
@@ -1366,7 +1520,9 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
             bool done = false;
             if (t % nc == 0) {
                 resid_l[l] = std::sqrt(sm[0]) / ((double)nc * std::sqrt(sm[1]));
-                if (p->fixed_steps <= 0 && resid_l[l] < p->tol) {
+                est_l[l].push(resid_l[l]);
+                if (p->fixed_steps <= 0 && resid_l[l] < p->tol &&
+                    (p->steady_tol <= 0.0 || est_l[l].dist(nc) <= p->steady_tol)) {
                     conv_l[l] = 1;
                     done = true;
                 }
@@ -1404,6 +1560,7 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         r.n_fluid = nf_h[l];
         r.converged = conv_l[l];
         r.residual = resid_l[l];
+        r.steady_dist = est_l[l].dist(nc);
         for (int k = 0; k < 3; k++) r.mean_rho_u[k] = sm[2 + k] / nvox[l];
         r.mass_dev = sm[5];
         r.k_lattice = nu * r.mean_rho_u[0] / p->force[0];

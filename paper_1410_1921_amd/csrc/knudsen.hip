@@ -27,7 +27,7 @@ namespace lbm {
 // D3Q7: rest, then +x, -x, +y, -y, +z, -z.
 #define LBM_D3Q7_TABLES [[maybe_unused]] constexpr int OPP[7] = {0, 2, 1, 4, 3, 6, 5};
 
-constexpr uint64_t kKnMagic = 0x4c424d4b4e554434ull;  // "LBMKNUD4"
+constexpr uint64_t kKnMagic = 0x4c424d4b4e554435ull;  // "LBMKNUD5"
 constexpr int kKnSums = 5;  // |dC|^2, C^2, Phi_out, Phi_in, C
 constexpr int kKnSampleMax = 65536;
 constexpr float kW0 = 0.25f, kW1 = 0.125f;
@@ -46,6 +46,7 @@ struct KnHeader {
     int32_t variant;  // LBM_VARIANT_* of the solve
     int32_t lattice;  // LBM_LATTICE_*
     int32_t pad;
+    double tau_ref, d_ref;  // Eq. 12 parameters the relaxation times were formed with
 };
 
 // Populations per node and the weights of a lattice: D3Q7 (rest 1/4, faces 1/8) or the
@@ -84,6 +85,7 @@ struct KnWs {
     Shift *steady[2];  // shifts within each frame (t0 = 0)
     Shift *trans;      // shifts from the current frame to the other one
     double *part;      // plane-mean partial sums [nx][kPlaneParts][2]
+    double *fpart;     // link-plane flux partial sums [nx + 1][kPlaneParts]
     int64_t stride;
     size_t bytes;
 };
@@ -114,6 +116,7 @@ static KnWs carve_kn(void *base, const Grid &g, int64_t nf, int q) {
     for (int f = 0; f < 2; f++) w.steady[f] = c.take<Shift>(kMaxEdge + 2);
     w.trans = c.take<Shift>(kMaxEdge + 2);
     w.part = c.take<double>((size_t)kMaxEdge * kPlaneParts * 2);
+    w.fpart = c.take<double>((size_t)(kMaxEdge + 1) * kPlaneParts);
     int64_t nfp = nf < 1 ? 1 : nf;
     w.stride = (nfp + 255) / 256 * 256;  // whole blocks of 256 nodes (popq)
     w.coords = c.take<uint32_t>(nfp);
@@ -573,18 +576,20 @@ __global__ __launch_bounds__(1024) void k_frame_next_b(const int32_t *__restrict
                ref_next + L.sh0, steady_next + L.sh0, trans + L.sh0, 0.125);
 }
 
-// Net +x flux through the link plane x = px - 1/2 (px = 0..nx), one block per plane,
-// over links with both ends fluid (ghost planes count as fluid).  g_{+x}(left) -
-// g_{-x}(right) in the frame of `right` is s_{+x}(left) + tm(right) - s_{-x}(right); the
-// ghost planes hold zero deviation.
+// Net +x flux through the link plane x = px - 1/2 (px = 0..nx) over links with both ends
+// fluid (ghost planes count as fluid), kPlaneParts workgroups per plane (blockIdx.y = px),
+// each summing every kPlaneParts-th run of 256 rows into part[px][blockIdx.x].
+// g_{+x}(left) - g_{-x}(right) in the frame of `right` is s_{+x}(left) + tm(right) -
+// s_{-x}(right); the ghost planes hold zero deviation.
 __global__ __launch_bounds__(256) void k_plane_flux(Grid g, const RankWord *__restrict__ rank,
                                                     const float *__restrict__ gcur,
                                                     const Shift *__restrict__ steady,
-                                                    double *__restrict__ plane) {
-    const int px = blockIdx.x;
+                                                    double *__restrict__ part) {
+    const int px = blockIdx.y;
     const int left = px - 1, right = px;
     double acc[1] = {0.0};
-    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < (int64_t)g.ny * g.nz;
+         k += 256 * kPlaneParts) {
         const int y = (int)(k % g.ny), z = (int)(k / g.ny);
         const int il = left >= 0 ? node_at(rank, g, left, y, z) : -2;
         const int ir = right < g.nx ? node_at(rank, g, right, y, z) : -2;
@@ -596,7 +601,7 @@ __global__ __launch_bounds__(256) void k_plane_flux(Grid g, const RankWord *__re
     __shared__ double lds[4];
     double out[1];
     block_sum<1>(acc, lds, out);
-    if (threadIdx.x == 0) plane[px] = out[0];
+    if (threadIdx.x == 0) part[px * kPlaneParts + blockIdx.x] = out[0];
 }
 
 // The same on D3Q19: over the five directions with e_x = +1, the links from
@@ -605,13 +610,14 @@ __global__ __launch_bounds__(256) void k_plane_flux(Grid g, const RankWord *__re
 __global__ __launch_bounds__(256) void k_plane_flux19(Grid g, const RankWord *__restrict__ rank,
                                                       const float *__restrict__ gcur,
                                                       const Shift *__restrict__ steady,
-                                                      double *__restrict__ plane) {
+                                                      double *__restrict__ part) {
     LBM_D3Q19_TABLES
-    const int px = blockIdx.x;
+    const int px = blockIdx.y;
     const int left = px - 1, right = px;
     const double tm = (double)steady[right + 1].tm;
     double acc[1] = {0.0};
-    for (int64_t k = threadIdx.x; k < (int64_t)g.ny * g.nz; k += 256) {
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < (int64_t)g.ny * g.nz;
+         k += 256 * kPlaneParts) {
         const int y = (int)(k % g.ny), z = (int)(k / g.ny);
         const int ir = right < g.nx ? node_at(rank, g, right, y, z) : -2;
         if (ir == -1) continue;
@@ -628,7 +634,41 @@ __global__ __launch_bounds__(256) void k_plane_flux19(Grid g, const RankWord *__
     __shared__ double lds[4];
     double out[1];
     block_sum<1>(acc, lds, out);
-    if (threadIdx.x == 0) plane[px] = out[0];
+    if (threadIdx.x == 0) part[px * kPlaneParts + blockIdx.x] = out[0];
+}
+
+// plane[px] = the sum of the kPlaneParts partials of link plane px, in a fixed order.
+__global__ __launch_bounds__(256) void k_plane_flux_sum(int planes, const double *__restrict__ part,
+                                                        double *__restrict__ plane) {
+    const int px = blockIdx.x * 256 + threadIdx.x;
+    if (px >= planes) return;
+    double s = 0.0;
+    for (int p = 0; p < kPlaneParts; p++) s += part[px * kPlaneParts + p];
+    plane[px] = s;
+}
+
+// The nx + 1 link-plane fluxes of the state gcur (in the frame whose steady shifts are
+// `steady`) into plane[0..nx]; part holds (nx + 1) kPlaneParts doubles.
+static lbm_status kn_plane_fluxes(const Grid &g, const RankWord *rank, const float *gcur,
+                                  const Shift *steady, double *part, double *plane, int32_t lattice,
+                                  hipStream_t s) {
+    const dim3 grid(kPlaneParts, (unsigned)(g.nx + 1));
+    if (lattice == LBM_LATTICE_D3Q19)
+        k_plane_flux19<<<grid, 256, 0, s>>>(g, rank, gcur, steady, part);
+    else
+        k_plane_flux<<<grid, 256, 0, s>>>(g, rank, gcur, steady, part);
+    LBM_CHECK_LAUNCH();
+    k_plane_flux_sum<<<(unsigned)((g.nx + 1 + 255) / 256), 256, 0, s>>>(g.nx + 1, part, plane);
+    LBM_CHECK_LAUNCH();
+    return LBM_OK;
+}
+
+// Denominator floor of the flux spread: 1e-6 of the flux an open box (every voxel fluid,
+// tau_g = tau_ref) carries between the ghost planes.
+static double kn_spread_floor(const Grid &g, const lbm_knudsen_params *p, int32_t lattice) {
+    const double cs2 = lattice == LBM_LATTICE_D3Q19 ? 1.0 / 3.0 : 0.25;
+    return 1e-6 * cs2 * (p->tau_ref - 0.5) * (double)g.ny * g.nz *
+           std::fabs(p->c_in - p->c_out) / (double)(g.nx + 1);
 }
 
 __global__ void k_kn_sample(Grid g, int64_t count, const int64_t *__restrict__ vox,
@@ -795,6 +835,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
                 "lbm_knudsen_solve: null argument");
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->steady_tol >= 0.0 && std::isfinite(p->steady_tol), LBM_E_INVAL,
+                "steady_tol must be finite and >= 0");
     LBM_REQUIRE(std::isfinite(p->c_in) && std::isfinite(p->c_out), LBM_E_INVAL,
                 "C_in and C_out must be finite");
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
@@ -829,6 +871,9 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
                         h.n_fluid == nf && h.c_in == p->c_in && h.c_out == p->c_out &&
                         h.lattice == p->lattice,
                     LBM_E_INVAL, "resume: the workspace holds no state for this problem");
+        // the relaxation times are formed again from pore_diam: only under the same Eq. 12
+        LBM_REQUIRE(h.tau_ref == p->tau_ref && h.d_ref == p->d_ref_nm / p->voxel_nm, LBM_E_INVAL,
+                    "resume: tau_ref or d_ref / voxel size differ from the state's");
         t0 = h.steps_done;
         cur = h.cur;
     } else {
@@ -853,6 +898,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.c_in = p->c_in;
     h.c_out = p->c_out;
     const double d_ref = p->d_ref_nm / p->voxel_nm;
+    h.tau_ref = p->tau_ref;
+    h.d_ref = d_ref;
     LBM_TRY_HIP(hipMemsetAsync(w.counter, 0, sizeof(unsigned long long), s));
     k_kn_init<<<(unsigned)kn_blocks(nf), 256, 0, s>>>(g, nf, w.stride, w.coords, pore_diam, d_ref,
                                                       p->tau_ref, c_init, w.g[cur], w.omega,
@@ -902,6 +949,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     const int nc = p->check_every;
     double sums[kKnSums] = {0, 0, 0, 0, 0};
     double resid = INFINITY, sweep_ms = 0.0;
+    SteadyEst est;
+    const double spread_floor = kn_spread_floor(g, p, h.lattice);
     bool converged = false, diverged = false;
     int64_t t = 0;
     lbm_status out = LBM_OK;
@@ -932,9 +981,23 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
         }
         if ((t0 + t) % nc == 0) {
             resid = std::sqrt(sums[0]) / ((double)nc * std::sqrt(sums[1]));
+            est.push(resid);
             if (p->fixed_steps <= 0 && resid < p->tol) {
                 converged = true;
-                break;
+                if (p->steady_tol > 0.0) {
+                    // steady state: the same flux through every link plane (the state is
+                    // still in frame h.frame; the pending frame only enters with the next
+                    // sweep)
+                    out = kn_plane_fluxes(g, w.rank, w.g[cur], w.steady[h.frame], w.fpart,
+                                          w.plane, h.lattice, s);
+                    if (out != LBM_OK) break;
+                    double pl[kMaxEdge + 1];
+                    LBM_TRY_HIP(hipMemcpyAsync(pl, w.plane, sizeof(double) * (g.nx + 1),
+                                               hipMemcpyDeviceToHost, s));
+                    LBM_TRY_HIP(hipStreamSynchronize(s));
+                    converged = plane_spread(pl, g.nx + 1, spread_floor) <= p->steady_tol;
+                }
+                if (converged) break;
             }
         }
     }
@@ -944,13 +1007,8 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
     h.steps_done = t0 + t;
     LBM_TRY_HIP(hipMemcpyAsync(w.hdr, &h, sizeof(h), hipMemcpyHostToDevice, s));
     // link-plane fluxes of the final state
-    if (h.lattice == LBM_LATTICE_D3Q19)
-        k_plane_flux19<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.rank, w.g[cur],
-                                                            w.steady[h.frame], w.plane);
-    else
-        k_plane_flux<<<(unsigned)(g.nx + 1), 256, 0, s>>>(g, w.rank, w.g[cur],
-                                                          w.steady[h.frame], w.plane);
-    LBM_CHECK_LAUNCH();
+    st = kn_plane_fluxes(g, w.rank, w.g[cur], w.steady[h.frame], w.fpart, w.plane, h.lattice, s);
+    if (st != LBM_OK) return st;
     double planes[kMaxEdge + 1];
     LBM_TRY_HIP(hipMemcpyAsync(planes, w.plane, sizeof(double) * (g.nx + 1), hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipStreamSynchronize(s));
@@ -958,6 +1016,7 @@ extern "C" lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid
 
     kn_result(r, p, g, nf, t, converged, resid, sums, sum_tau, planes, sweep_ms,
               (double)nf * (double)t, h.lattice);
+    r->steady_dist = est.dist(nc);
     if (diverged) {
         set_error("Knudsen solve diverged (NaN/Inf) by step %lld", (long long)(t0 + t));
         return LBM_E_DIVERGED;
@@ -1055,6 +1114,7 @@ struct KnBatchWs {
     Shift *steady[2];
     Shift *trans;
     double *part;
+    double *fpart;  // link-plane flux partials, kPlaneParts per table row
     int64_t stride, nblk, nrank, ntab, nplane;
     size_t bytes;
 };
@@ -1091,6 +1151,7 @@ static KnBatchWs carve_kn_batch(void *base, int count, const int32_t *n_h, const
     for (int f = 0; f < 2; f++) w.steady[f] = c.take<Shift>(w.ntab);
     w.trans = c.take<Shift>(w.ntab);
     w.part = c.take<double>((size_t)w.nplane * kPlaneParts * 2);
+    w.fpart = c.take<double>((size_t)w.ntab * kPlaneParts);
     w.bytes = c.off;
     return w;
 }
@@ -1195,6 +1256,8 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     }
     LBM_REQUIRE(p->check_every >= 1, LBM_E_INVAL, "check_every must be >= 1");
     LBM_REQUIRE(p->fixed_steps > 0 || p->max_steps > 0, LBM_E_INVAL, "no step limit given");
+    LBM_REQUIRE(p->steady_tol >= 0.0 && std::isfinite(p->steady_tol), LBM_E_INVAL,
+                "steady_tol must be finite and >= 0");
     LBM_REQUIRE(std::isfinite(p->c_in) && std::isfinite(p->c_out), LBM_E_INVAL,
                 "C_in and C_out must be finite");
     LBM_REQUIRE(p->c_in != p->c_out, LBM_E_INVAL, "C_in equals C_out: no driving difference");
@@ -1349,7 +1412,9 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     std::vector<double> res((size_t)count * kKnSums, 0.0), sums_l((size_t)count * kKnSums, 0.0);
     std::vector<int64_t> steps_l(count, 0);
     std::vector<double> resid_l(count, INFINITY);
+    std::vector<SteadyEst> est_l(count);
     std::vector<int> conv_l(count, 0), cur_l(count, 0), frame_l(count, 0);
+    std::vector<double> planes(w.ntab);
     bool diverged = false;
     while (t < limit && !act.empty()) {
         const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
@@ -1405,7 +1470,7 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
             regroup_now = tune_k < kBatchBudgets || budget != cand[kBatchBudgets - 1];
         }
         t += chunk;
-        std::vector<int32_t> keep;
+        std::vector<int32_t> keep, below;
         for (int l : act) {
             const double *sm = res.data() + (size_t)l * kKnSums;
             std::copy(sm, sm + kKnSums, sums_l.begin() + (size_t)l * kKnSums);
@@ -1416,17 +1481,37 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
                 diverged = true;
                 continue;
             }
-            bool done = false;
             if (t % nc == 0) {
                 resid_l[l] = std::sqrt(sm[0]) / ((double)nc * std::sqrt(sm[1]));
-                if (p->fixed_steps <= 0 && resid_l[l] < p->tol) {
-                    conv_l[l] = 1;
-                    done = true;
-                }
+                est_l[l].push(resid_l[l]);
+                if (p->fixed_steps <= 0 && resid_l[l] < p->tol) below.push_back(l);
+            }
+        }
+        if (diverged) break;
+        if (!below.empty() && p->steady_tol > 0.0) {
+            // the steady-state test of the single solve, for the lattices below tol
+            for (int l : below) {
+                const KnLat &L = lats[l];
+                st = kn_plane_fluxes(L.g, w.rank + L.rk0, w.g[q.cur] + 7 * L.b0 * 256,
+                                     w.steady[q.frame] + L.sh0, w.fpart + L.sh0 * kPlaneParts,
+                                     w.plane + L.sh0, LBM_LATTICE_D3Q7, s);
+                if (st != LBM_OK) return st;
+            }
+            LBM_TRY_HIP(hipMemcpyAsync(planes.data(), w.plane, sizeof(double) * w.ntab,
+                                       hipMemcpyDeviceToHost, s));
+            LBM_TRY_HIP(hipStreamSynchronize(s));
+        }
+        for (int l : act) {
+            bool done = false;
+            if (std::find(below.begin(), below.end(), l) != below.end()) {
+                done = p->steady_tol <= 0.0 ||
+                       plane_spread(planes.data() + lats[l].sh0, lats[l].g.nx + 1,
+                                    kn_spread_floor(lats[l].g, p, LBM_LATTICE_D3Q7)) <=
+                           p->steady_tol;
+                conv_l[l] = done;
             }
             if (!done) keep.push_back(l);
         }
-        if (diverged) break;
         if (keep.size() != act.size()) {
             act = keep;
             live_nodes = 0.0;
@@ -1447,13 +1532,12 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
     }
 
     // link-plane fluxes of each lattice's final state, then the results
-    std::vector<double> planes(w.ntab);
     for (int l = 0; l < count; l++) {
         const KnLat &L = lats[l];
-        k_plane_flux<<<(unsigned)(L.g.nx + 1), 256, 0, s>>>(
-            L.g, w.rank + L.rk0, w.g[cur_l[l]] + 7 * L.b0 * 256,
-            w.steady[frame_l[l]] + L.sh0, w.plane + L.sh0);
-        LBM_CHECK_LAUNCH();
+        st = kn_plane_fluxes(L.g, w.rank + L.rk0, w.g[cur_l[l]] + 7 * L.b0 * 256,
+                             w.steady[frame_l[l]] + L.sh0, w.fpart + L.sh0 * kPlaneParts,
+                             w.plane + L.sh0, LBM_LATTICE_D3Q7, s);
+        if (st != LBM_OK) return st;
     }
     LBM_TRY_HIP(hipMemcpyAsync(planes.data(), w.plane, sizeof(double) * w.ntab,
                                hipMemcpyDeviceToHost, s));
@@ -1464,6 +1548,7 @@ extern "C" lbm_status lbm_knudsen_solve_batch(int32_t count, const int32_t *n_h,
         kn_result(r_h + l, p, lats[l].g, nf_h[l], steps_l[l], conv_l[l], resid_l[l],
                   sums_l.data() + (size_t)l * kKnSums, tau_sum[l], planes.data() + lats[l].sh0,
                   sweep_ms, updates, LBM_LATTICE_D3Q7);
+        r_h[l].steady_dist = est_l[l].dist(nc);
     }
     if (diverged) {
         set_error("batched Knudsen solve diverged (NaN/Inf) by step %lld", (long long)t);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <vector>
@@ -113,6 +114,51 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t chunk) {
 inline int64_t xcd_launch(int64_t blocks, int64_t chunk = 1) {
     const int64_t g = kXcd * (chunk > 0 ? chunk : 1);
     return (blocks + g - 1) / g * g;
+}
+
+// ---------------------------------------------------------------- steady state
+// Distance of a converging field to its steady state, estimated from the decay of the
+// convergence residual (Section 3.4 asks for the steady state; the residual alone bounds
+// only the change per step).  When the field approaches its limit as a e^(-lambda t),
+// the residual r = ||phi(t) - phi(t - n_c)|| / (n_c ||phi(t)||) falls by rho =
+// e^(-lambda n_c) from one check to the next, and ||phi(t) - phi_inf|| / ||phi(t)|| =
+// r n_c rho / (1 - rho).  rho is the geometric-mean ratio over the last kSteadyWindow
+// check intervals (fewer at the start); no decay (rho >= 1) means no estimate (+inf).
+constexpr int kSteadyWindow = 5;
+struct SteadyEst {
+    double r[kSteadyWindow + 1];
+    int n = 0;
+    void push(double v) {
+        if (n == kSteadyWindow + 1) {
+            for (int k = 0; k < kSteadyWindow; k++) r[k] = r[k + 1];
+            n--;
+        }
+        r[n++] = v;
+    }
+    double dist(int nc) const {
+        if (n < 1) return INFINITY;
+        const double last = r[n - 1];
+        if (last == 0.0) return 0.0;  // no change at all over the last interval
+        if (n < 2 || !(last > 0.0) || !(r[0] > 0.0)) return INFINITY;
+        const double rho = std::pow(last / r[0], 1.0 / (n - 1));
+        if (!(rho < 1.0)) return INFINITY;
+        return last * (double)nc * rho / (1.0 - rho);
+    }
+};
+
+// Spread of the link-plane fluxes, (max - min) / |mean|: zero at steady state, where the
+// same flux crosses every plane.  `floor` bounds the denominator from below (a medium
+// without a path between the faces carries no steady flux at all).
+inline double plane_spread(const double *planes, int count, double floor) {
+    double mn = planes[0], mx = planes[0], mean = 0.0;
+    for (int k = 0; k < count; k++) {
+        mn = planes[k] < mn ? planes[k] : mn;
+        mx = planes[k] > mx ? planes[k] : mx;
+        mean += planes[k];
+    }
+    mean = std::fabs(mean / count);
+    const double den = mean > floor ? mean : floor;
+    return den > 0.0 ? (mx - mn) / den : INFINITY;
 }
 
 // ---------------------------------------------------------------- reductions

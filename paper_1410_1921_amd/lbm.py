@@ -64,7 +64,7 @@ class lbm_flow_params(C.Structure):
                 ("tol", C.c_double), ("voxel_nm", C.c_double), ("resume", C.c_int32),
                 ("variant", C.c_int32), ("with_rho", C.c_int32), ("collision", C.c_int32),
                 ("boundary", C.c_int32), ("reserved", C.c_int32), ("rho_in", C.c_double),
-                ("rho_out", C.c_double)]
+                ("rho_out", C.c_double), ("steady_tol", C.c_double)]
 
 
 class lbm_flow_result(C.Structure):
@@ -72,7 +72,7 @@ class lbm_flow_result(C.Structure):
                 ("reserved", C.c_int32), ("k_lattice", C.c_double), ("k_m2", C.c_double),
                 ("k_mD", C.c_double), ("residual", C.c_double), ("mean_rho_u", C.c_double * 3),
                 ("mass_dev", C.c_double), ("sweep_ms", C.c_double), ("mlups", C.c_double),
-                ("gbps", C.c_double)]
+                ("gbps", C.c_double), ("steady_dist", C.c_double)]
 
 
 class lbm_knudsen_params(C.Structure):
@@ -80,7 +80,7 @@ class lbm_knudsen_params(C.Structure):
                 ("c_in", C.c_double), ("c_out", C.c_double), ("T_K", C.c_double),
                 ("M_kg_mol", C.c_double), ("max_steps", C.c_int64), ("fixed_steps", C.c_int64),
                 ("check_every", C.c_int32), ("resume", C.c_int32), ("tol", C.c_double),
-                ("variant", C.c_int32), ("lattice", C.c_int32)]
+                ("variant", C.c_int32), ("lattice", C.c_int32), ("steady_tol", C.c_double)]
 
 
 class lbm_knudsen_result(C.Structure):
@@ -90,7 +90,8 @@ class lbm_knudsen_result(C.Structure):
                 ("DK_ref_m2s", C.c_double), ("tortuosity", C.c_double),
                 ("tortuosity_local", C.c_double), ("phi_in", C.c_double), ("phi_out", C.c_double),
                 ("flux_spread", C.c_double), ("residual", C.c_double), ("sum_c", C.c_double),
-                ("sweep_ms", C.c_double), ("mlups", C.c_double), ("gbps", C.c_double)]
+                ("sweep_ms", C.c_double), ("mlups", C.c_double), ("gbps", C.c_double),
+                ("steady_dist", C.c_double)]
 
 
 class lbm_props_params(C.Structure):
@@ -324,9 +325,10 @@ def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, 
                    check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False, u_init=None,
                    workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
                    storage=LBM_STORE_FP32, with_rho=False, collision=LBM_COLLIDE_BGK,
-                   pressure=None):
+                   pressure=None, steady_tol=0.0):
     """D3Q19 flow solve.  With with_rho the velocity field (want_u) and u_init carry a
-    fourth plane, rho - 1.  pressure=(rho_in, rho_out): pressure boundaries in x."""
+    fourth plane, rho - 1.  pressure=(rho_in, rho_out): pressure boundaries in x.
+    steady_tol > 0: convergence also needs the estimated distance to steady state."""
     _vol(fluid, torch.uint8, "fluid")
     if n_fluid is None:
         n_fluid = lbm_count(fluid)
@@ -338,7 +340,8 @@ def lbm_flow_solve(fluid, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000, 
     rho_in, rho_out = (1.0, 1.0) if pressure is None else (float(pressure[0]), float(pressure[1]))
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
                         int(storage), tol, voxel_nm, int(bool(resume)), int(variant),
-                        int(bool(with_rho)), int(collision), bc, 0, rho_in, rho_out)
+                        int(bool(with_rho)), int(collision), bc, 0, rho_in, rho_out,
+                        float(steady_tol))
     r = lbm_flow_result()
     u = torch.empty((planes,) + tuple(fluid.shape), dtype=torch.float32, device=fluid.device) \
         if want_u else None
@@ -380,7 +383,7 @@ def lbm_flow_batch_workspace(shapes, n_fluids):
 def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_000_000,
                          fixed_steps=0, check_every=100, tol=1e-7, voxel_nm=1.0, want_u=False,
                          n_fluids=None, variant=LBM_VARIANT_AUTO, collision=LBM_COLLIDE_BGK,
-                         group_bytes=0, workspace=None):
+                         group_bytes=0, workspace=None, steady_tol=0.0):
     """D3Q19 flow solves of several lattices in one batch (binary32 storage).
     group_bytes: 0 autotuned, < 0 one group, > 0 the group budget.  Returns (status, list
     of result dicts, list of velocity fields or None, schedule dict)."""
@@ -395,7 +398,8 @@ def lbm_flow_solve_batch(fluids, tau=0.8, force=(1e-6, 0.0, 0.0), max_steps=1_00
         workspace = Workspace(lbm_flow_batch_workspace([m.shape for m in fluids], nf),
                               fluids[0].device)
     p = lbm_flow_params(tau, (C.c_double * 3)(*force), max_steps, fixed_steps, check_every,
-                        LBM_STORE_FP32, tol, voxel_nm, 0, int(variant), 0, int(collision))
+                        LBM_STORE_FP32, tol, voxel_nm, 0, int(variant), 0, int(collision),
+                        LBM_BOUNDARY_PERIODIC, 0, 1.0, 1.0, float(steady_tol))
     res = (lbm_flow_result * count)()
     us = [torch.empty((3,) + tuple(m.shape), dtype=torch.float32, device=m.device)
           for m in fluids] if want_u else None
@@ -414,9 +418,10 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
                       c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000, fixed_steps=0,
                       check_every=100, tol=1e-7, want_c=False, c_init=None, want_planes=True,
                       workspace=None, resume=False, n_fluid=None, variant=LBM_VARIANT_AUTO,
-                      lattice=LBM_LATTICE_D3Q7):
+                      lattice=LBM_LATTICE_D3Q7, steady_tol=0.0):
     """Mass-transport solve on the D3Q7 lattice or (lattice=LBM_LATTICE_D3Q19) the
-    paper's D3Q19 lattice."""
+    paper's D3Q19 lattice.  steady_tol > 0: convergence also needs the spread of the
+    link-plane fluxes at or below it."""
     _vol(fluid, torch.uint8, "fluid")
     _vol(pore_diam, torch.float64, "pore_diam")
     if pore_diam.shape != fluid.shape:
@@ -429,7 +434,8 @@ def lbm_knudsen_solve(fluid, pore_diam, tau_ref=1.0, d_ref_nm=60.0, voxel_nm=1.5
         kind = LBM_WS_KNUDSEN_D3Q19 if lattice == LBM_LATTICE_D3Q19 else LBM_WS_KNUDSEN
         workspace = Workspace(lbm_workspace_size(kind, fluid.shape, n_fluid), fluid.device)
     p = lbm_knudsen_params(tau_ref, d_ref_nm, voxel_nm, c_in, c_out, T, M, max_steps, fixed_steps,
-                           check_every, int(bool(resume)), tol, int(variant), int(lattice))
+                           check_every, int(bool(resume)), tol, int(variant), int(lattice),
+                           float(steady_tol))
     r = lbm_knudsen_result()
     c = torch.empty(fluid.shape, dtype=torch.float32, device=fluid.device) if want_c else None
     nx = fluid.shape[2]
@@ -458,7 +464,7 @@ def lbm_knudsen_solve_batch(fluids, pore_diams, tau_ref=1.0, d_ref_nm=60.0, voxe
                             c_in=1.0, c_out=0.0, T=323.0, M=0.016043, max_steps=1_000_000,
                             fixed_steps=0, check_every=100, tol=1e-7, want_c=False, c_inits=None,
                             n_fluids=None, variant=LBM_VARIANT_AUTO, group_bytes=0,
-                            workspace=None):
+                            workspace=None, steady_tol=0.0):
     """D3Q7 Knudsen solves of several lattices in one batch.  c_inits: None or a list of
     float32 fields (entries may be None); group_bytes as in lbm_flow_solve_batch.  Returns
     (status, list of result dicts, list of concentration fields or None, schedule dict)."""
@@ -480,7 +486,7 @@ def lbm_knudsen_solve_batch(fluids, pore_diams, tau_ref=1.0, d_ref_nm=60.0, voxe
         workspace = Workspace(lbm_knudsen_batch_workspace([m.shape for m in fluids], nf),
                               fluids[0].device)
     p = lbm_knudsen_params(tau_ref, d_ref_nm, voxel_nm, c_in, c_out, T, M, max_steps, fixed_steps,
-                           check_every, 0, tol, int(variant), 0)
+                           check_every, 0, tol, int(variant), 0, float(steady_tol))
     res = (lbm_knudsen_result * count)()
     cs = [torch.empty(m.shape, dtype=torch.float32, device=m.device) for m in fluids] \
         if want_c else None
@@ -527,7 +533,7 @@ def lbm_props(label_stats=None, flow=None, knudsen=None, d_mean_nm=45.0, P=17236
             return None
         s = cls()
         for name, _ in cls._fields_:
-            v = d[name]
+            v = d.get(name, 0)
             if hasattr(getattr(s, name), "__len__"):
                 getattr(s, name)[:] = v
             else:

@@ -38,22 +38,61 @@ def geometry(rp):
     return pore, diam, rs
 
 
-def solve_pair(pore, diam, cfg, tol, u_init=None, c_init=None, n_fluid=None):
-    """Flow (with rho - 1 in the returned field) and Knudsen solves of one geometry;
+def solve_pair(pore, diam, cfg, tol, u_init=None, c_init=None, n_fluid=None, steady=(0.0, 0.0)):
+    """Flow (with rho - 1 in the returned field) and Knudsen solves of one geometry to
+    residual tol and the steady-state tests steady = (flow, Knudsen) (0: residual only);
     returns the two Solve objects and their wall times."""
     fp, kp = cfg["flow"], cfg["knudsen"]
     t0 = time.perf_counter()
     fr = lbm.lbm_flow_solve(pore, tau=fp["tau"], force=fp["force"], max_steps=fp["max_steps"],
                             check_every=fp["check_every"], tol=tol, voxel_nm=cfg["voxel_nm"],
-                            want_u=True, with_rho=True, u_init=u_init, n_fluid=n_fluid)
+                            want_u=True, with_rho=True, u_init=u_init, n_fluid=n_fluid,
+                            steady_tol=steady[0])
     t1 = time.perf_counter()
     kr = lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
                                voxel_nm=cfg["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
                                T=kp["T"], max_steps=kp["max_steps"],
                                check_every=kp["check_every"], tol=tol, want_c=True,
-                               c_init=c_init, n_fluid=n_fluid)
+                               c_init=c_init, n_fluid=n_fluid, steady_tol=steady[1])
     torch.cuda.current_stream().synchronize()
     return fr, kr, (t1 - t0, time.perf_counter() - t1)
+
+
+def knudsen_warm_or_rest(pore, diam, c_init, warm_max_steps=None, **kw):
+    """Knudsen solve started from the network's C, with the solve from rest as the
+    fallback.  The warm solve is kept only when it meets the solve's own stop rule (the
+    residual and, with steady_tol, the equal flux through every link plane) within
+    warm_max_steps steps (default: kw's max_steps); when it does not, or when it diverges
+    (a non-finite prediction), the solve runs again from rest with kw unchanged.
+    Returns (Solve, warm_used)."""
+    warm_kw = dict(kw)
+    if warm_max_steps is not None:
+        warm_kw["max_steps"] = int(warm_max_steps)
+    try:
+        r = lbm.lbm_knudsen_solve(pore, diam, c_init=c_init, **warm_kw)
+        if r["converged"]:
+            return r, True
+    except lbm.LbmError as e:
+        if e.status != lbm.LBM_E_DIVERGED:
+            raise
+    return lbm.lbm_knudsen_solve(pore, diam, **kw), False
+
+
+def flow_warm_or_rest(pore, u_init, warm_max_steps=None, **kw):
+    """The same for the flow solve: the warm start from u_init (with kw's with_rho, its
+    fourth plane rho - 1) is kept only when it converges by the solve's own rule within
+    warm_max_steps; otherwise the solve runs from rest.  Returns (Solve, warm_used)."""
+    warm_kw = dict(kw)
+    if warm_max_steps is not None:
+        warm_kw["max_steps"] = int(warm_max_steps)
+    try:
+        r = lbm.lbm_flow_solve(pore, u_init=u_init, **warm_kw)
+        if r["converged"]:
+            return r, True
+    except lbm.LbmError as e:
+        if e.status != lbm.LBM_E_DIVERGED:
+            raise
+    return lbm.lbm_flow_solve(pore, **kw), False
 
 
 def _scales(dev, inverse):
@@ -136,22 +175,24 @@ def train(net, data, epochs, lr=1e-3, log=print, seed=0):
     return history
 
 
-def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False):
+def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
+             steady=(0.0, 0.0)):
     """Solves each held-out geometry from rest and from the network's fields (one after
-    the other, so the wall times compare); returns one record per seed."""
+    the other, so the wall times compare) to residual tol and the steady-state tests
+    `steady` (see solve_pair); returns one record per seed."""
     rows = []
     for seed in seeds:
         rp = W.warmstart_params(seed, cfg["edge"])
         pore, diam, rs = geometry(rp)
         nf = rs["n_pore"]
-        p_f, p_k, (p_tf, p_tk) = solve_pair(pore, diam, cfg, tol, n_fluid=nf)
+        p_f, p_k, (p_tf, p_tk) = solve_pair(pore, diam, cfg, tol, n_fluid=nf, steady=steady)
         t0 = time.perf_counter()
         u0, c0 = predict(net, pore, diam)
         torch.cuda.current_stream().synchronize()
         t_inf = time.perf_counter() - t0
         w_f, w_k, (w_tf, w_tk) = solve_pair(pore, diam, cfg, tol,
                                             u_init=u0.contiguous() if flow_warm else None,
-                                            c_init=c0.contiguous(), n_fluid=nf)
+                                            c_init=c0.contiguous(), n_fluid=nf, steady=steady)
         row = dict(seed=seed, porosity=rs["porosity"], n_fluid=nf,
                    plain_steps=[p_f["steps"], p_k["steps"]], warm_steps=[w_f["steps"], w_k["steps"]],
                    plain_s=[p_tf, p_tk], warm_s=[w_tf, w_tk], inference_s=t_inf,

@@ -54,4 +54,4 @@ def test_cpu_baseline_fields():
     out = bench.cpu_baseline(W, w, 5)
     assert out["kind"] == "oracle" and out["unit"] == "MLUPS"
     assert out["value"] > 0 and out["cores"] >= 1
-    assert "5 D3Q19 and 5 D3Q7 steps" in out["sample"]
+    assert "5 D3Q19 BGK steps of the whole lattice" in out["sample"]

@@ -1,0 +1,146 @@
+"""Full-size parity with the FP64 oracle at equal step counts.
+
+The 128^3 methane workload (porosity 0.40, N(12, 3) spheres, overlap tolerance 0.3,
+seed 2, maximum-inscribed-sphere map, 2 nm voxels, CH4 at 400 K) and the 128^3 centre
+crop [192, 320)^3 of the 512^3 workload (porosity 0.25, N(16, 4), overlap tolerance 0.7,
+seed 3).  The oracle's results were written once by tests/golden/make_oracle_golden.py
+(oracle only): k, D_eff, the link-plane fluxes and the fields at 1024 seeded fluid voxels
+and 64 solid ones.  Bars: k and D_eff 1e-4 relative for binary32 storage, fields
+1e-5 of max|u| and 1e-5 absolute in C, binary64 storage 1e-9; binary16 storage at the
+bar its 11-bit significand allows (stated per test)."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1410_1921_amd import lbm, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print("[gpu-fullsize]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def load(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def sha(t):
+    return hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest()
+
+
+def recon(w):
+    rp = w["recon"]
+    pore, _, rs = lbm.lbm_reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+                                      rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
+    return pore, rs
+
+
+@pytest.fixture(scope="module")
+def c2():
+    torch.cuda.set_device(0)
+    gold = load("c2")
+    w = W.METHANE_128
+    say("reconstruct", w["name"])
+    pore, rs = recon(w)
+    assert sha(pore) == gold["mask_sha256"], "mask differs from the oracle's"
+    return w, gold, pore, rs["n_pore"]
+
+
+def check_flow(r, rec, vox, bar_k, bar_u):
+    ek = abs(r["k_lattice"] / rec["k_lattice"] - 1)
+    u = r.field.reshape(3, -1)[:, vox].T.double().cpu().numpy()
+    eu = float(np.abs(u - np.array(rec["u"])).max()) / rec["max_abs_u"]
+    say(f"steps {r['steps']}: k {r['k_lattice']:.9e} vs {rec['k_lattice']:.9e} (rel {ek:.2e}), "
+        f"u rel {eu:.2e}")
+    assert r["steps"] == rec["steps"]
+    assert ek < bar_k and eu < bar_u
+    return ek
+
+
+@pytest.mark.parametrize("key", ["flow_2000", "flow_converged"])
+def test_c2_flow_equal_steps(c2, key):
+    w, gold, pore, nf = c2
+    rec = gold[key]
+    vox = torch.tensor(gold["vox"], device="cuda")
+    r = lbm.lbm_flow_solve(pore, tau=0.8, force=(1e-6, 0, 0), fixed_steps=rec["steps"],
+                           check_every=100, n_fluid=nf, want_u=True, voxel_nm=w["voxel_nm"])
+    check_flow(r, rec, vox, 1e-4, 1e-5)
+
+
+def test_c2_knudsen_equal_steps(c2):
+    w, gold, pore, nf = c2
+    rec = gold["knudsen_100000"]
+    kp = w["knudsen"]
+    diam = lbm.lbm_pore_diameter(pore, lbm.LBM_PSD_MIS)
+    r = lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+                              voxel_nm=w["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
+                              T=kp["T"], fixed_steps=rec["steps"], check_every=100,
+                              n_fluid=nf, want_c=True)
+    vox = torch.tensor(gold["vox"], device="cuda")
+    c = r.field.reshape(-1)[vox].double().cpu().numpy()
+    ec = float(np.abs(c - np.array(rec["c"])).max())
+    ed = abs(r["Deff_lattice"] / rec["Deff_lattice"] - 1)
+    pl = np.array(rec["plane_flux"])
+    ep = float(np.abs(r["plane_flux"] - pl).max() / np.abs(pl).max())
+    say(f"knudsen {r['steps']} steps: D_eff {r['Deff_lattice']:.9e} vs {rec['Deff_lattice']:.9e} "
+        f"(rel {ed:.2e}), C {ec:.2e}, plane fluxes {ep:.2e}")
+    assert ed < 1e-4 and ec < 1e-5 and ep < 1e-4
+    assert abs(r["phi_in"] / rec["phi_in"] - 1) < 1e-4
+
+
+@pytest.fixture(scope="module")
+def crop():
+    torch.cuda.set_device(0)
+    gold = load("crop")
+    w = W.LARGE_512
+    say("reconstruct", w["name"])
+    pore, _ = recon(w)
+    assert sha(pore) == gold["mask_sha256_full"], "mask differs from the oracle's"
+    (z0, z1), (y0, y1), (x0, x1) = w["crop"]
+    sub = pore[z0:z1, y0:y1, x0:x1].contiguous()
+    del pore
+    torch.cuda.empty_cache()
+    assert sha(sub) == gold["mask_sha256"]
+    return w, gold, sub, lbm.lbm_count(sub)
+
+
+def test_mis_512_bit_exact(crop):
+    # the maximum-inscribed-sphere map of the whole 512^3 reconstruction, bit for bit
+    # against the oracle's (stored as the hash of its binary64 values)
+    w, gold, _, _ = crop
+    pore, _ = recon(w)
+    d = lbm.lbm_pore_diameter(pore, lbm.LBM_PSD_MIS)
+    del pore
+    h = hashlib.sha256(d.cpu().numpy().tobytes()).hexdigest()
+    del d
+    torch.cuda.empty_cache()
+    assert h == gold["mis_sha256_full"]
+
+
+# binary32 at the bar of the full-size workloads; binary64 as the GPU's FP64 reference;
+# binary16 at 2e-3 (its significand keeps ~3 decimal digits of each stored offset)
+@pytest.mark.parametrize("storage,bar_k,bar_u", [(lbm.LBM_STORE_FP64, 1e-9, 1e-9),
+                                                 (lbm.LBM_STORE_FP32, 1e-4, 1e-4),
+                                                 (lbm.LBM_STORE_FP16, 2e-3, 2e-2)])
+def test_crop_storage_vs_oracle(crop, storage, bar_k, bar_u):
+    w, gold, sub, nf = crop
+    rec = gold["flow_20000"]
+    vox = torch.tensor(gold["vox"], device="cuda")
+    r = lbm.lbm_flow_solve(sub, tau=0.8, force=(1e-6, 0, 0), fixed_steps=rec["steps"],
+                           check_every=100, n_fluid=nf, want_u=True, storage=storage,
+                           voxel_nm=w["voxel_nm"])
+    say("crop storage", storage)
+    check_flow(r, rec, vox, bar_k, bar_u)

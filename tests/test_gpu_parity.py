@@ -161,13 +161,20 @@ def test_flow_parity_ragged(orc, shape, seed, force):
     assert np.allclose(r["mean_rho_u"], o["mean_rho_u"], rtol=1e-4, atol=1e-4 * np.abs(force).max())
 
 
-def test_flow_slit_closed_form():
+@pytest.mark.parametrize("storage,bar", [(lbm.LBM_STORE_FP64, 1e-9), (lbm.LBM_STORE_FP32, 2e-5)])
+def test_flow_slit_closed_form(storage, bar):
+    # exact for the discrete lattice up to the storage: 4000 steps leave e^(-lambda t) =
+    # e^(-48) of the initial transient (lambda = nu pi^2 / H^2 = 0.012, the slowest decay
+    # rate), so binary64 meets the closed form to round-off; binary32 freezes once the
+    # per-step change of a stored offset drops below half its ulp (2^-24 relative),
+    # ~6e-8 / 0.012 = 5e-6 from steady state per node, of either sign: 2e-5 bounds it
+    # (measured 1.1e-5)
     h, tau = 9, 0.8
     m = W.slit(4, h + 2, 4, h, axis=1)
-    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=(1e-6, 0, 0), max_steps=100_000, tol=1e-10)
+    r = lbm.lbm_flow_solve(dev(m), tau=tau, force=(1e-6, 0, 0), fixed_steps=4000,
+                           storage=storage)
     lam = (tau - 0.5) ** 2
-    assert r["converged"]
-    assert r["k_lattice"] == pytest.approx(h / (h + 2) * (h * h + 8 * lam - 1) / 12, rel=1e-5)
+    assert r["k_lattice"] == pytest.approx(h / (h + 2) * (h * h + 8 * lam - 1) / 12, rel=bar)
 
 
 def test_flow_warm_start_and_resume(orc):
@@ -259,8 +266,10 @@ def test_knudsen_duct_exact():
                                   tol=1e-9)
         want = m.mean() * 0.25 * (tau - 0.5) * (nx + 1) / (nx - 1 + 2 * tau)
         # binary32 iteration run to its floor: the shifted storage keeps the frozen
-        # error near 4e-6 here (unshifted storage would stop at 2e-4)
-        assert r["Deff_lattice"] == pytest.approx(want, rel=2e-5)
+        # error at a few 1e-6 here (unshifted storage would stop at 2e-4)
+        err = abs(r["Deff_lattice"] / want - 1)
+        say(f"duct tau {tau}: D_eff error {err:.2e} after {r['steps']} steps")
+        assert err < 1e-5
         if tau == 1.0:
             assert r["tortuosity"] == pytest.approx(1.0, rel=1e-5)
         assert r["flux_spread"] < 1e-4

@@ -130,3 +130,23 @@ def test_storage_mismatch_on_resume_is_rejected():
     # the same storage resumes
     lbm.lbm_flow_solve(m, fixed_steps=20, workspace=a.workspace, resume=True,
                        storage=lbm.LBM_STORE_FP16)
+
+
+def test_resume_parameter_mismatch_is_rejected():
+    # a stored state continues only under the parameters it was computed with
+    m = dev(W.blob_mask((12, 12, 12), 0.6, 4))
+    a = lbm.lbm_flow_solve(m, tau=0.8, force=(1e-6, 0, 0), fixed_steps=20)
+    for kw in (dict(tau=0.9), dict(force=(2e-6, 0, 0)), dict(force=(1e-6, 1e-7, 0))):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_flow_solve(m, fixed_steps=20, workspace=a.workspace, resume=True,
+                               **dict(dict(tau=0.8, force=(1e-6, 0, 0)), **kw))
+    b = lbm.lbm_flow_solve(m, tau=0.8, force=(1e-6, 0, 0), fixed_steps=20, workspace=a.workspace,
+                           resume=True)
+    assert b["steps"] == 20
+    d = torch.full(m.shape, 5.0, dtype=torch.float64, device="cuda")
+    k = lbm.lbm_knudsen_solve(m, d, fixed_steps=20)
+    for kw in (dict(tau_ref=1.2), dict(voxel_nm=2.0), dict(d_ref_nm=50.0)):
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_knudsen_solve(m, d, fixed_steps=20, workspace=k.workspace, resume=True, **kw)
+    k2 = lbm.lbm_knudsen_solve(m, d, fixed_steps=20, workspace=k.workspace, resume=True)
+    assert k2["steps"] == 20

@@ -1,6 +1,6 @@
 """The shipped warm-start network: predictions are well formed, and on a held-out
-geometry the warm-started Knudsen solve converges in fewer steps, with D_eff as close to
-the steady state as the solve from rest (both judged against a much tighter solve)."""
+geometry the warm-started Knudsen solve reaches steady state in fewer steps, with D_eff
+within 1e-3 of the solve from rest and of a much longer solve."""
 import sys
 
 import pytest
@@ -39,24 +39,25 @@ def test_warm_knudsen_solve_saves_steps(net):
     pore, diam, rs = WS.geometry(rp)
     kp = cfg["knudsen"]
 
-    def solve(c_init, tol):
+    def solve(c_init, **kw):
         return lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
                                      voxel_nm=cfg["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
-                                     T=kp["T"], max_steps=kp["max_steps"], tol=tol,
-                                     c_init=c_init, n_fluid=rs["n_pore"])
+                                     T=kp["T"], max_steps=kp["max_steps"], c_init=c_init,
+                                     n_fluid=rs["n_pore"], **kw)
 
-    plain = solve(None, 1e-7)
+    # both forms stop at residual 1e-7 with the same flux through every link plane (spread
+    # <= 5e-4: D_eff within ~2.5e-4 of steady state); both are judged against a solve run
+    # three times as long, and against each other at 1e-3
+    plain = solve(None, tol=1e-7, steady_tol=5e-4)
     _, c0 = WS.predict(net, pore, diam)
-    warm = solve(c0.contiguous(), 1e-7)
-    # the residual bounds the change per step, not the distance to steady state: that is
-    # ~ residual / (slowest decay rate), a few percent of D_eff here, so both are judged
-    # against a solve to residual 1e-9
-    tight = solve(c0.contiguous(), 1e-9)
+    warm = solve(c0.contiguous(), tol=1e-7, steady_tol=5e-4)
+    tight = solve(None, fixed_steps=3 * plain["steps"])
     ref = tight["Deff_lattice"]
     e_plain = abs(plain["Deff_lattice"] / ref - 1)
     e_warm = abs(warm["Deff_lattice"] / ref - 1)
-    say("knudsen steps", plain["steps"], "->", warm["steps"], "(tight", tight["steps"], ")",
-        "D_eff errors vs tight: plain", e_plain, "warm", e_warm)
-    assert plain["converged"] and warm["converged"] and tight["converged"]
+    d = abs(warm["Deff_lattice"] / plain["Deff_lattice"] - 1)
+    say("knudsen steps", plain["steps"], "->", warm["steps"], "(reference", tight["steps"], ")",
+        "D_eff errors vs reference: plain", e_plain, "warm", e_warm, "between", d)
+    assert plain["converged"] and warm["converged"]
     assert warm["steps"] < plain["steps"]
-    assert e_plain < 5e-2 and e_warm < 5e-2
+    assert e_plain < 1e-3 and e_warm < 1e-3 and d < 1e-3
