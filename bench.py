@@ -150,6 +150,7 @@ def crop_precision(lbm, W, pore):
     out = {"crop": w["crop"], "n_fluid": nf}
     stores = (("fp64", lbm.LBM_STORE_FP64), ("fp32", lbm.LBM_STORE_FP32),
               ("fp16", lbm.LBM_STORE_FP16))
+    cap = 2_000_000
     for name, st in stores:
         rec = {}
         if gold is not None:
@@ -157,9 +158,11 @@ def crop_precision(lbm, W, pore):
                                    **flow_kw(w, storage=st))
             rec["k_vs_oracle_rel"] = r["k_lattice"] / gold["k_lattice"] - 1
             rec["oracle_steps"] = gold["steps"]
+        if name == "fp16":  # its residual stops decaying at the rounding floor
+            cap = 2 * out["fp32"]["steps"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = lbm.lbm_flow_solve(sub, max_steps=2_000_000, tol=TOL, steady_tol=FLOW_STEADY,
+        r = lbm.lbm_flow_solve(sub, max_steps=cap, tol=TOL, steady_tol=FLOW_STEADY,
                                n_fluid=nf, **flow_kw(w, storage=st))
         torch.cuda.synchronize()
         rec.update(time_to_converged_s=round(time.perf_counter() - t0, 3), steps=r["steps"],
@@ -170,8 +173,8 @@ def crop_precision(lbm, W, pore):
     k64 = out["fp64"]["k_lattice"]
     for name in ("fp32", "fp16"):
         out[name]["k_vs_fp64_converged_rel"] = out[name]["k_lattice"] / k64 - 1
-    out["speedup_fp16_vs_fp32"] = round(out["fp32"]["time_to_converged_s"] /
-                                        out["fp16"]["time_to_converged_s"], 3)
+    out["fp16_note"] = ("binary16 does not meet the stop rule (its residual stops decaying at "
+                        "the rounding floor); its run is capped at twice binary32's steps")
     del sub
     torch.cuda.empty_cache()
     return out
@@ -452,22 +455,19 @@ def flow_sizes(lbm, edges=(256, 320, 384, 448, 512), steps=30):
     return out
 
 
-def cpu_baseline(W, w, steps):
-    """The FP64 oracle on a bounded sample of workload `w`: its own reconstruction, and
-    `steps` D3Q19 steps of the flow on the workload's crop (the whole lattice when it has
-    none)."""
-    import numpy as np
+def cpu_baseline(W, w, steps, edge=128):
+    """The FP64 oracle on a bounded sample of workload `w`: its own reconstruction with the
+    workload's parameters on an edge^3 box (the whole lattice when the workload is no
+    larger), then `steps` D3Q19 BGK steps of the flow on it."""
     import oracle as orc
-    rp = w["recon"]
+    rp = dict(w["recon"])
+    n = tuple(min(int(e), edge) for e in rp["n"])
     t0 = time.perf_counter()
-    pore, _, info = orc.reconstruct(rp["n"], rp["porosity"], rp["d_mean"], rp["d_std"],
+    pore, _, info = orc.reconstruct(n, rp["porosity"], rp["d_mean"], rp["d_std"],
                                     rp["d_min"], rp["overlap_tol"], rp["p_overlap"], rp["seed"])
     t_rec = time.perf_counter() - t0
-    what = "the whole lattice"
-    if "crop" in w:
-        (z0, z1), (y0, y1), (x0, x1) = w["crop"]
-        pore = np.ascontiguousarray(pore[z0:z1, y0:y1, x0:x1])
-        what = "the 128^3 centre crop"
+    what = "the whole lattice" if n == tuple(rp["n"]) else \
+        f"a {n[0]}x{n[1]}x{n[2]} box drawn with the workload's parameters"
     fp = w["flow"]
     t1 = time.perf_counter()
     orc.flow_solve(pore, tau=fp["tau"], force=fp["force"], fixed_steps=steps, want_u=False)

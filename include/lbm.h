@@ -68,10 +68,11 @@ typedef int32_t lbm_status;
 #define LBM_LATTICE_D3Q19 1 /* the paper's: a_i = 1/3, 1/18, 1/36, c_s^2 = 1/3 */
 
 /* population storage of the flow solve */
-#define LBM_STORE_FP32 0 /* binary32 offsets f_i - w_i (1 + r_s), r_s a reference density
-                            (rho - 1) per 64-voxel row segment s: the segment mean of rho - 1
-                            at the last convergence check; collision in binary32 */
-#define LBM_STORE_FP16 1 /* binary16 of S (f_i - w_i (1 + r_s)), S = 2^k with S max|F| in
+#define LBM_STORE_FP32 0 /* binary32 offsets f_i - w_i (1 + r(x)), r a reference density
+                            (rho - 1) per 32-voxel half row segment, linear in x: the
+                            least-squares line through rho - 1 of its nodes at the last
+                            convergence check; collision in binary32 */
+#define LBM_STORE_FP16 1 /* binary16 of S (f_i - w_i (1 + r(x))), S = 2^k with S max|F| in
                             [1, 2) (1 when F = 0); collision in binary32 */
 #define LBM_STORE_FP64 2 /* binary64 offsets f_i - w_i, collision in binary64 */
 
@@ -294,7 +295,7 @@ lbm_status lbm_flow_step(void *workspace, size_t ws_bytes, int64_t steps, void *
 
 /* Read the post-collision populations of `count` voxels from the state in
  * `workspace`: f_h[count][19] receives f_i - w_i (double: the stored value, divided by S
- * for binary16 storage, plus w_i r_s of the node's segment for binary32 and binary16),
+ * for binary16 storage, plus w_i r(x) at the node for binary32 and binary16),
  * fluid_h[count] whether the voxel is a fluid node (rows of solid voxels are 0).
  * count <= 65536. */
 lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const int64_t *vox_h, int64_t count,

@@ -24,6 +24,15 @@ Parity status of each function (what pins it, in ``tests/test_oracle_*.py``):
   columns with different tau, mass conservation, swap and linearity.
 * ``knudsen_diffusivity`` / ``fc`` -- the paper's printed D_K(60 nm, 323 K) and the
   coefficient 64/(3 pi) of Eq. 28.
+* ``k_kozeny_carman`` (Eq. 17) -- worked examples computed by hand
+  (``tests/golden/props_worked_examples.txt``) and Carman's hydraulic-radius form with
+  the Kozeny constant 5 and the sphere's surface-to-volume ratio taken numerically from
+  ``sphere_volume``.
+* ``lattice_diffusivity``, ``time_step``, ``deff_physical``, ``k_physical``, ``m2_to_mD``
+  (Eq. 15), ``tortuosity`` (Eq. 16), ``bruggeman_alpha`` (Section 4.2) -- worked examples;
+  tortuosity 1 of a straight duct at tau = 1 and its closed form at tau = 1.4; channels
+  of reference pores diffusing at eps D_K(d_ref); alpha and tortuosity consistent; a
+  physical slit's permeability independent of the voxel size.
 * ``collide19_mrt`` / ``flow_solve(collision=MRT)`` -- the inverse of Q against the
   paper's printed Appendix A table (golden file; its misprinted row 6 noted), mass and
   momentum conservation, equal rates reducing to BGK, and the tau-independent slit

@@ -9,22 +9,22 @@
 // binary64 (collision in binary64) stores the offsets f_i - w_i.  binary32 and binary16
 // (collision in binary32) store offsets from the equilibrium at rest of a reference
 // density per row segment: h_i = S (f_i - w_i (1 + r_s)), with r_s one binary32 value per
-// 64-voxel row segment s of the node (the segments of the rank map) and S = 1 for
-// binary32, S = 2^k with S max|F| in [1, 2) for binary16.  In low-permeability media the
-// body force is held by pressure (dead ends, tortuous paths), and the density part
-// w_i (rho - 1) of f_i - w_i exceeds the velocity part by up to four decades: stored
-// relative to w_i alone, binary32 loses ~1e-3 of k on the 128^3 crop of the 512^3 workload
-// and binary16 loses u entirely.  The pressure field is smooth on the scale of a
-// segment, so relative to r_s the stored values carry the velocity and non-equilibrium
-// parts and the small density variation within the segment.  The collision itself runs
-// on offsets from the node's own segment reference (a pulled value is moved there by
-// w_i (r_source - r_own), exact when the two references are within a factor two), with
-// rho = 1 + r_own + sum_i h_i; Eq. 3's f_eq and the MRT equilibrium moments are linear
-// in the density, so only the density offset changes.  The references are segment means
-// of rho - 1 taken at each convergence check; the first sweep of the next check interval
-// reads the state relative to the old references and writes it relative to the new ones
-// (two reference arrays, ping-pong).  The references cost one cache-resident 4-byte
-// gather per pull (8.4 MB at 512^3 against 33.5 MB of rank map).
+// 32-voxel half row segment (r(x) = a + b (x mod 32), fitted to rho - 1 of its nodes) and
+// S = 1 for binary32, S = 2^k with S max|F| in [1, 2) for binary16.  In low-permeability
+// media the body force is held by pressure (dead ends, tortuous paths), and the density
+// part w_i (rho - 1) of f_i - w_i exceeds the velocity part by up to four decades: stored
+// relative to w_i alone, binary32 loses ~4e-4 of k on the 128^3 crop of the 512^3
+// workload and binary16 loses u entirely.  Where the fluid is still, the pressure is
+// hydrostatic under the body force, linear along x, so a linear reference per half
+// segment leaves the stored values the velocity and non-equilibrium parts (a constant
+// one per segment, tried first, left binary16 5.8 % off on the crop).  The collision
+// runs on offsets from the node's own reference (a pulled value is moved there by
+// w_i (r_source - r_own)), with rho = 1 + r_own + sum_i h_i; Eq. 3's f_eq and the MRT
+// equilibrium moments are linear in the density, so only the density offset changes.
+// The references are fitted at each convergence check; the first sweep after it reads
+// the state relative to the old references and writes it relative to the new ones.
+// They live in the flow's rank records beside each half's occupancy and first node id
+// (FlowHalf, 16 bytes), so a pull costs one load for both.
 #include <algorithm>
 #include <vector>
 #include <cmath>
@@ -35,7 +35,7 @@
 
 namespace lbm {
 
-constexpr uint64_t kFlowMagic = 0x4c424d464c4f5736ull;  // "LBMFLOW6"
+constexpr uint64_t kFlowMagic = 0x4c424d464c4f5737ull;  // "LBMFLOW7"
 constexpr int kFlowSums = 6;      // |du|^2, |u|^2, rho u (3), rho - 1
 constexpr int kSampleMax = 65536;
 
@@ -49,12 +49,29 @@ struct FlowHeader {
     int32_t collision;
     int32_t boundary;          // LBM_BOUNDARY_*
     double rho_in, rho_out;    // pressure boundaries
-    int32_t sref;              // 1: offsets from per-segment reference densities
-    int32_t sframe;            // the reference array the stored state is relative to
-    int32_t sref_pending;      // 1: sref[sframe ^ 1] holds references of the last check
-                               // that the next sweep moves the state to
-    int32_t pad;
+    int32_t sref;              // 1: offsets from reference densities (binary32, binary16)
+    int32_t sref_pending;      // 1: href_next holds references of the last check that the
+                               // next sweep moves the state to
 };
+
+// The flow sweep's record of a half row segment (32 voxels): its occupancy bits and the
+// id of its first fluid node, as in the rank map, beside the linear reference density
+// r(x) = a + b (x mod 32) the stored state of its nodes is relative to.
+struct alignas(16) FlowHalf {
+    uint32_t bits, base;
+    float a, b;
+};
+
+__host__ __device__ inline int64_t half_index(int64_t seg, int x) { return 2 * seg + ((x >> 5) & 1); }
+__device__ inline float half_ref(float a, float b, int x) {
+    return __builtin_fmaf(b, (float)(x & 31), a);
+}
+// Node id at bit `bit` (= x % 64) of the half record holding it, or -1 for a solid voxel.
+__device__ inline int flow_lookup(const FlowHalf &h, int bit) {
+    const int b = bit & 31;
+    if (!((h.bits >> b) & 1u)) return -1;
+    return (int)(h.base + (uint32_t)__popc(h.bits & ((1u << b) - 1u)));
+}
 
 // Pressure boundaries: the populations entering through the inlet (e_x = +1) and the
 // outlet (e_x = -1), five each, and their slot in the ghost-plane buffer
@@ -121,8 +138,9 @@ struct FlowWs {
     uint8_t *samp_flag;
     uint32_t *coords;
     void *f[2];
-    float *sref[2];  // per-segment reference densities rho - 1 (binary32, binary16)
-    float *dsnap;    // rho - 1 per node at the last check (the next references)
+    FlowHalf *fh;      // half-segment records with the references (binary32, binary16)
+    float2 *href_next; // references fitted at the last check, (a, b) per half segment
+    float *dsnap;      // rho - 1 per node at the last check
     float *usnap;
     double *partials;
     void *ghost;     // pressure boundaries: ghost-plane populations [2][5][ny nz]
@@ -150,9 +168,9 @@ static FlowWs carve_flow(void *base, const Grid &g, int64_t nf, int32_t storage)
     w.res = c.take<double>(32);
     w.total = c.take<int32_t>(1);
     w.rank = c.take<RankWord>(g.nsegs());
-    const size_t nref = storage == LBM_STORE_FP64 ? 0 : (size_t)g.nsegs();
-    w.sref[0] = c.take<float>(nref);
-    w.sref[1] = c.take<float>(nref);
+    const size_t nhalf = storage == LBM_STORE_FP64 ? 0 : 2 * (size_t)g.nsegs();
+    w.fh = c.take<FlowHalf>(nhalf);
+    w.href_next = c.take<float2>(nhalf);
     w.samp_vox = c.take<int64_t>(kSampleMax);
     w.samp_out = c.take<double>((size_t)kSampleMax * 19);
     w.samp_flag = c.take<uint8_t>(kSampleMax);
@@ -181,10 +199,10 @@ struct Sweep19 {
     const RankWord *__restrict__ rank;
     const void *__restrict__ src;
     void *__restrict__ dst;
-    const float *__restrict__ sref_src;  // segment references of the state read
-    const float *__restrict__ sref_dst;  // ... and of the state written (when reframe)
-    int reframe;                         // 1: sref_dst differs from sref_src
-    float *__restrict__ dsnap;           // check variant: rho - 1 per node
+    const FlowHalf *__restrict__ fh;       // half records with the references read
+    const float2 *__restrict__ href_next;  // references written (when reframe)
+    int reframe;                           // 1: write relative to href_next
+    float *__restrict__ dsnap;             // check variant: rho - 1 per node
     float omega, fpre, Fx, Fy, Fz, sq; // collision parameters for binary32 arithmetic
     double omega_d, fpre_d, Fd[3], sq_d;  // and for binary64 (sq: the MRT rate s_q)
     float scale, inv_scale;            // binary16 storage scale
@@ -326,12 +344,11 @@ __device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
 // the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back); rs[i] the
-// reference density of the source's segment (rs[0]: the node's own), binary32 and
-// binary16 storage.
+// reference density at the source (rs[0]: at the node), binary32 and binary16 storage.
 template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
                               const int (&ids)[19], const int (&gidx)[19], const float (&rs)[19],
-                              int64_t seg_own, double (&acc)[kFlowSums]) {
+                              int64_t half_own, double (&acc)[kFlowSums]) {
     using T = typename P::T;
     using R = typename P::R;
     LBM_D3Q19_TABLES
@@ -403,7 +420,10 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
     }
     R shift = 0;  // the first sweep of a check interval moves to the new references
     if constexpr (kRef)
-        if (a.reframe) shift = R(rs[0]) - R(a.sref_dst[seg_own]);
+        if (a.reframe) {
+            const float2 nx = a.href_next[half_own];
+            shift = R(rs[0]) - R(half_ref(nx.x, nx.y, x));
+        }
 #pragma unroll
     for (int i = 0; i < 19; i++) {
         const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
@@ -479,25 +499,39 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
         wz[k] = zs[k] * (g.ny * g.nseg);
         bx[k] = xs[k] & (kSeg - 1);
     }
-    // the 18 rank words (and segment references) are loaded as one batch, then the 19
+    // the 18 rank records (with the references) are loaded as one batch, then the 19
     // populations as another
-    RankHalf rh[19];
+    constexpr bool kRef = !std::is_same<P, StoreF64>::value;
     float rs[19];
-    const int64_t seg_own = (int64_t)wx[1] + wy[1] + wz[1];
-#pragma unroll
-    for (int i = 1; i < 19; i++) {
-        const int64_t sg = (int64_t)wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]];
-        rh[i] = rank_half(a.rank, sg, bx[1 - EX[i]]);
-        if constexpr (!std::is_same<P, StoreF64>::value) rs[i] = a.sref_src[sg];
-        else rs[i] = 0.f;
-    }
-    if constexpr (!std::is_same<P, StoreF64>::value) rs[0] = a.sref_src[seg_own];
-    else rs[0] = 0.f;
     int ids[19], gidx[19];
+    const int64_t half_own = half_index((int64_t)wx[1] + wy[1] + wz[1], x);
+    if constexpr (kRef) {
+        FlowHalf rh[19];
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            rh[i] = a.fh[half_index((int64_t)wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]],
+                                    bx[1 - EX[i]])];
+        const float2 own = *reinterpret_cast<const float2 *>(&a.fh[half_own].a);
+        rs[0] = half_ref(own.x, own.y, x);
+#pragma unroll
+        for (int i = 1; i < 19; i++) {
+            ids[i] = flow_lookup(rh[i], bx[1 - EX[i]]);
+            rs[i] = half_ref(rh[i].a, rh[i].b, bx[1 - EX[i]]);
+        }
+    } else {
+        RankHalf rh[19];
+#pragma unroll
+        for (int i = 1; i < 19; i++)
+            rh[i] = rank_half(a.rank, (int64_t)wx[1 - EX[i]] + wy[1 - EY[i]] + wz[1 - EZ[i]],
+                              bx[1 - EX[i]]);
+#pragma unroll
+        for (int i = 0; i < 19; i++) rs[i] = 0.f;
+#pragma unroll
+        for (int i = 1; i < 19; i++) ids[i] = half_lookup(rh[i], bx[1 - EX[i]]);
+    }
     ids[0] = 0;
 #pragma unroll
     for (int i = 1; i < 19; i++) {
-        ids[i] = half_lookup(rh[i], bx[1 - EX[i]]);
         gidx[i] = 0;
         if (OPEN && ((EX[i] == 1 && x == 0) || (EX[i] == -1 && x == g.nx - 1))) {
             // the source is a ghost node; its boundary node (looked up at this x) decides:
@@ -507,7 +541,7 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
             gidx[i] = ((side * 5 + GSLOT[i]) * g.nz + zs[1 - EZ[i]]) * g.ny + ys[1 - EY[i]];
         }
     }
-    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, rs, seg_own, acc);
+    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, rs, half_own, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
@@ -562,8 +596,8 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
         b.rank = a.rank + D.rk0;
         b.src = static_cast<const float *>(a.src) + 19 * n0;
         b.dst = static_cast<float *>(a.dst) + 19 * n0;
-        b.sref_src = a.sref_src + D.rk0;
-        b.sref_dst = a.sref_dst + D.rk0;
+        b.fh = a.fh + 2 * D.rk0;
+        b.href_next = a.href_next + 2 * D.rk0;
         b.dsnap = a.dsnap + n0;
         b.usnap = a.usnap + 3 * n0;
         b.u_out = D.u_out;
@@ -577,13 +611,13 @@ __global__ __launch_bounds__(256) void k_sweep19b(Sweep19 a, const BlkDesc19 *__
 // beyond boundary node b (x = 0 or nx - 1, same y, z) holds f(b) + f_eq(rho_bc, u_b) -
 // f_eq(rho_b, u_b), with rho_b, u_b the moments of b's state (u_b = (j - F/2)/rho_b, the
 // velocity of b's collision) and f_eq of Eq. 3; only the five populations entering the
-// domain are kept, as offsets from w_i (1 + r) with r the reference density of b's
-// segment (sref, null for binary64 storage), in ghost[side][slot][z ny + y].  A ghost
-// beside a solid b is solid (the sweep bounces back) and is not written.
+// domain are kept, as offsets from w_i (1 + r) with r the reference density at b (from
+// its half record fh; null for binary64 storage), in ghost[side][slot][z ny + y].  A
+// ghost beside a solid b is solid (the sweep bounces back) and is not written.
 template <class P>
 __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restrict__ rank,
                                                  const typename P::T *__restrict__ src,
-                                                 const float *__restrict__ sref,
+                                                 const FlowHalf *__restrict__ fh,
                                                  float inv_scale, float scale,
                                                  typename P::R Fx, typename P::R Fy,
                                                  typename P::R Fz, typename P::R drho_in,
@@ -601,7 +635,11 @@ __global__ __launch_bounds__(256) void k_ghost19(Grid g, const RankWord *__restr
     const int xb = side ? g.nx - 1 : 0;
     const int id = node_at(rank, g, xb, y, z);
     if (id < 0) return;
-    const R ref = sref ? R(sref[g.seg(xb, y, z)]) : R(0);
+    R ref = 0;
+    if (fh) {
+        const FlowHalf h = fh[half_index(g.seg(xb, y, z), xb)];
+        ref = R(half_ref(h.a, h.b, xb));
+    }
     R f[19], drho = 0, jx = 0, jy = 0, jz = 0;  // drho: offset from 1 + ref
 #pragma unroll
     for (int i = 0; i < 19; i++) {
@@ -642,30 +680,71 @@ __global__ __launch_bounds__(256) void k_flow_drho0(Grid g, int64_t nf,
     dsnap[n] = dr;
 }
 
-// The reference density of each row segment: the mean of rho - 1 over its fluid nodes
-// (dsnap[id], the segment's ids are consecutive from its base), 0 without any.
-__global__ __launch_bounds__(256) void k_seg_ref(int64_t nsegs, const RankWord *__restrict__ rank,
-                                                 const float *__restrict__ dsnap,
-                                                 float *__restrict__ sref) {
-    const int64_t sg = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (sg >= nsegs) return;
-    const RankWord w = rank[sg];
-    const int c = __popc(w.lo) + __popc(w.hi);
-    double sum = 0.0;
-    for (int k = 0; k < c; k++) sum += (double)dsnap[w.base + k];
-    sref[sg] = c ? (float)(sum / c) : 0.f;
+// The half records from the rank map: occupancy and first node id of each half segment
+// (their references are written by k_ref_commit).
+__global__ __launch_bounds__(256) void k_flow_halves(int64_t nhalves,
+                                                     const RankWord *__restrict__ rank,
+                                                     FlowHalf *__restrict__ fh) {
+    const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (h >= nhalves) return;
+    const RankWord w = rank[h >> 1];
+    FlowHalf r;
+    r.bits = (h & 1) ? w.hi : w.lo;
+    r.base = (h & 1) ? w.base_hi : w.base;
+    r.a = 0.f;
+    r.b = 0.f;
+    fh[h] = r;
+}
+
+// The reference of each half segment: the least-squares line a + b (x mod 32) through
+// rho - 1 of its fluid nodes (dsnap by node id; a half's ids are consecutive from its
+// base, in x order); a constant for a single node, 0 without any.
+__global__ __launch_bounds__(256) void k_half_fit(int64_t nhalves, const RankWord *__restrict__ rank,
+                                                  const float *__restrict__ dsnap,
+                                                  float2 *__restrict__ out) {
+    const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (h >= nhalves) return;
+    const RankWord w = rank[h >> 1];
+    uint32_t bits = (h & 1) ? w.hi : w.lo;
+    const uint32_t base = (h & 1) ? w.base_hi : w.base;
+    double n = 0, sx = 0, sxx = 0, sy = 0, sxy = 0;
+    for (uint32_t k = 0; bits; k++, bits &= bits - 1u) {
+        const double xv = (double)(__ffs(bits) - 1), yv = (double)dsnap[base + k];
+        n += 1.0;
+        sx += xv;
+        sxx += xv * xv;
+        sy += yv;
+        sxy += xv * yv;
+    }
+    float2 r = make_float2(0.f, 0.f);
+    if (n > 0) {
+        const double det = n * sxx - sx * sx;
+        const double b = det > 0 ? (n * sxy - sx * sy) / det : 0.0;
+        r = make_float2((float)((sy - b * sx) / n), (float)b);
+    }
+    out[h] = r;
+}
+
+// The references of the last check become those of the stored state.
+__global__ __launch_bounds__(256) void k_ref_commit(int64_t nhalves, const float2 *__restrict__ next,
+                                                    FlowHalf *__restrict__ fh) {
+    const int64_t h = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (h >= nhalves) return;
+    const float2 r = next[h];
+    fh[h].a = r.x;
+    fh[h].b = r.y;
 }
 
 // The equilibrium (Eq. 3) of rho = 1 + drho and u from u_init (planes u_x, u_y, u_z and,
 // with with_rho, rho - 1; rest and rho = 1 without it), stored as offsets from
-// w_i (1 + r) with r the segment reference (sref; null: 0, binary64); the snapshot starts
-// at that u.
+// w_i (1 + r) with r the node's reference (from its half record fh; null: 0, binary64);
+// the snapshot starts at that u.
 template <class P>
 __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t stride,
                                                    const uint32_t *__restrict__ coords,
                                                    const float *__restrict__ u_init, int with_rho,
                                                    typename P::T *__restrict__ f, float scale,
-                                                   const float *__restrict__ sref,
+                                                   const FlowHalf *__restrict__ fh,
                                                    float *__restrict__ usnap) {
     using R = typename P::R;
     LBM_D3Q19_TABLES
@@ -679,7 +758,11 @@ __global__ __launch_bounds__(256) void k_flow_init(Grid g, int64_t nf, int64_t s
         ux = u_init[v]; uy = u_init[nv + v]; uz = u_init[2 * nv + v];
         if (with_rho) dr = u_init[3 * nv + v];
     }
-    const R ref = sref ? R(sref[g.seg(x, y, z)]) : R(0);
+    R ref = 0;
+    if (fh) {
+        const FlowHalf h = fh[half_index(g.seg(x, y, z), x)];
+        ref = R(half_ref(h.a, h.b, x));
+    }
     const R rho = R(1) + dr;
     const R uu15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
@@ -697,7 +780,7 @@ template <class P>
 __global__ void k_flow_sample(Grid g, int64_t count,
                               const int64_t *__restrict__ vox, const RankWord *__restrict__ rank,
                               const typename P::T *__restrict__ f, float inv_scale,
-                              const float *__restrict__ sref, double *__restrict__ out,
+                              const FlowHalf *__restrict__ fh, double *__restrict__ out,
                               uint8_t *__restrict__ flag) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
@@ -705,10 +788,14 @@ __global__ void k_flow_sample(Grid g, int64_t count,
     const int x = (int)(v % g.nx), y = (int)((v / g.nx) % g.ny), z = (int)(v / ((int64_t)g.nx * g.ny));
     const int id = node_at(rank, g, x, y, z);
     flag[s] = id >= 0;
-    const double ref = sref && id >= 0 ? (double)sref[g.seg(x, y, z)] : 0.0;
+    double ref = 0.0;
+    if (fh && id >= 0) {
+        const FlowHalf h = fh[half_index(g.seg(x, y, z), x)];
+        ref = (double)half_ref(h.a, h.b, x);
+    }
     for (int i = 0; i < 19; i++) {
         double v = id >= 0 ? (double)from_store<P>(f[pop19(i, id)], inv_scale) : 0.0;
-        if (id >= 0)  // offsets are taken from w_i (1 + r) of the node's segment
+        if (id >= 0)  // offsets are taken from w_i (1 + r) at the node
             v += (i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0)) * ref;
         out[s * 19 + i] = v;
     }
@@ -812,9 +899,10 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, Flow
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
         a.reframe = 0;
-        a.sref_src = a.sref_dst = h.sref ? w.sref[h.sframe] : nullptr;
-        if (h.sref && h.sref_pending) {
-            a.sref_dst = w.sref[h.sframe ^ 1];
+        a.fh = h.sref ? w.fh : nullptr;
+        a.href_next = w.href_next;
+        const bool reframe = h.sref && h.sref_pending;
+        if (reframe) {
             a.reframe = 1;
             h.sref_pending = 0;
         }
@@ -826,7 +914,7 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, Flow
                     static_cast<double *>(w.ghost));
             else
                 k_ghost19<StoreF32><<<gblocks, 256, 0, s>>>(
-                    g, w.rank, static_cast<const float *>(a.src), a.sref_src, 1.f, 1.f,
+                    g, w.rank, static_cast<const float *>(a.src), a.fh, 1.f, 1.f,
                     (float)h.force[0], (float)h.force[1], (float)h.force[2],
                     (float)(h.rho_in - 1.0), (float)(h.rho_out - 1.0),
                     static_cast<float *>(w.ghost));
@@ -838,7 +926,11 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, Flow
             launch19<false>(a, m, h.storage, h.collision, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
-        if (a.reframe) h.sframe ^= 1;
+        if (reframe) {  // the stored state is now relative to the new references
+            const int64_t nh = 2 * g.nsegs();
+            k_ref_commit<<<(unsigned)((nh + 255) / 256), 256, 0, s>>>(nh, w.href_next, w.fh);
+            LBM_CHECK_LAUNCH();
+        }
     }
     return LBM_OK;
 }
@@ -847,8 +939,8 @@ static lbm_status launch_sweeps(const FlowWs &w, const Grid &g, int64_t nf, Flow
 // the next interval moves to.
 static lbm_status flow_next_refs(const FlowWs &w, const Grid &g, FlowHeader &h, hipStream_t s) {
     if (!h.sref) return LBM_OK;
-    k_seg_ref<<<(unsigned)((g.nsegs() + 255) / 256), 256, 0, s>>>(g.nsegs(), w.rank, w.dsnap,
-                                                                   w.sref[h.sframe ^ 1]);
+    const int64_t nh = 2 * g.nsegs();
+    k_half_fit<<<(unsigned)((nh + 255) / 256), 256, 0, s>>>(nh, w.rank, w.dsnap, w.href_next);
     LBM_CHECK_LAUNCH();
     h.sref_pending = 1;
     return LBM_OK;
@@ -962,8 +1054,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
     h.rho_in = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_in : 1.0;
     h.rho_out = p->boundary == LBM_BOUNDARY_PRESSURE ? p->rho_out : 1.0;
     h.sref = p->storage != LBM_STORE_FP64;
-    if (!p->resume) h.sframe = h.sref_pending = 0;
-    h.pad = 0;
+    if (!p->resume) h.sref_pending = 0;
     for (int a = 0; a < 3; a++) h.force[a] = p->force[a];
     if (!p->resume) {
         // binary16: a power of two S with S max|F| in [1, 2) (1 without a force)
@@ -977,17 +1068,22 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         const float sc = (float)h.scale;
         const int wr = p->with_rho;
         if (h.sref) {
-            // the first references: segment means of the initial density
+            // the half records, with the first references fitted to the initial density
+            const int64_t nh = 2 * g.nsegs();
+            const unsigned nhb = (unsigned)((nh + 255) / 256);
+            k_flow_halves<<<nhb, 256, 0, s>>>(nh, w.rank, w.fh);
+            LBM_CHECK_LAUNCH();
             k_flow_drho0<<<nb, 256, 0, s>>>(g, nf, w.coords, u_init, wr, w.dsnap);
             LBM_CHECK_LAUNCH();
-            k_seg_ref<<<(unsigned)((g.nsegs() + 255) / 256), 256, 0, s>>>(g.nsegs(), w.rank,
-                                                                           w.dsnap, w.sref[0]);
+            k_half_fit<<<nhb, 256, 0, s>>>(nh, w.rank, w.dsnap, w.href_next);
+            LBM_CHECK_LAUNCH();
+            k_ref_commit<<<nhb, 256, 0, s>>>(nh, w.href_next, w.fh);
             LBM_CHECK_LAUNCH();
         }
         if (h.storage == LBM_STORE_FP16)
             k_flow_init<StoreF16><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<_Float16 *>(w.f[0]), sc,
-                                                     w.sref[0], w.usnap);
+                                                     w.fh, w.usnap);
         else if (h.storage == LBM_STORE_FP64)
             k_flow_init<StoreF64><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<double *>(w.f[0]), sc,
@@ -995,7 +1091,7 @@ extern "C" lbm_status lbm_flow_solve(const int32_t n[3], const uint8_t *fluid,
         else
             k_flow_init<StoreF32><<<nb, 256, 0, s>>>(g, nf, w.stride, w.coords, u_init, wr,
                                                      static_cast<float *>(w.f[0]), sc,
-                                                     w.sref[0], w.usnap);
+                                                     w.fh, w.usnap);
         LBM_CHECK_LAUNCH();
     }
     if (u_out)
@@ -1158,7 +1254,7 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     if (h.storage == LBM_STORE_FP16)
         k_flow_sample<StoreF16><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const _Float16 *>(w.f[h.cur]), inv,
-                                                   w.sref[h.sframe], w.samp_out, w.samp_flag);
+                                                   w.fh, w.samp_out, w.samp_flag);
     else if (h.storage == LBM_STORE_FP64)
         k_flow_sample<StoreF64><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const double *>(w.f[h.cur]), inv,
@@ -1166,7 +1262,7 @@ extern "C" lbm_status lbm_flow_sample(void *workspace, size_t ws_bytes, const in
     else
         k_flow_sample<StoreF32><<<nb, 256, 0, s>>>(g, count, w.samp_vox, w.rank,
                                                    static_cast<const float *>(w.f[h.cur]), inv,
-                                                   w.sref[h.sframe], w.samp_out, w.samp_flag);
+                                                   w.fh, w.samp_out, w.samp_flag);
     LBM_CHECK_LAUNCH();
     LBM_TRY_HIP(hipMemcpyAsync(f_h, w.samp_out, sizeof(double) * 19 * count, hipMemcpyDeviceToHost, s));
     LBM_TRY_HIP(hipMemcpyAsync(fluid_h, w.samp_flag, count, hipMemcpyDeviceToHost, s));
@@ -1185,7 +1281,8 @@ struct BatchWs {
     RankWord *rank;
     uint32_t *coords;
     float *f[2];
-    float *sref[2];  // per-segment reference densities (rank-map order)
+    FlowHalf *fh;       // half records with the references (rank-map order, 2 per segment)
+    float2 *href_next;
     float *dsnap;
     float *usnap;
     double *partials;
@@ -1210,8 +1307,8 @@ static BatchWs carve_batch(void *base, int count, const int32_t *n_h, const int6
     w.total = c.take<int32_t>(count);
     w.res = c.take<double>((size_t)count * kFlowSums);
     w.rank = c.take<RankWord>(w.nrank);
-    w.sref[0] = c.take<float>(w.nrank);
-    w.sref[1] = c.take<float>(w.nrank);
+    w.fh = c.take<FlowHalf>(2 * (size_t)w.nrank);
+    w.href_next = c.take<float2>(2 * (size_t)w.nrank);
     w.coords = c.take<uint32_t>(w.stride);
     w.f[0] = c.take<float>((size_t)19 * w.stride);
     w.f[1] = c.take<float>((size_t)19 * w.stride);
@@ -1243,13 +1340,13 @@ struct LatRef {
     int64_t nsegs, rk0, n0;
 };
 
-// `steps` sweeps of the lattices of group g from buffer cur and reference frame sframe;
-// with `pending` the first one moves the state to the references of the last check; the
-// last one checks, then the group's per-lattice sums go to w.res and the segment means of
-// each lattice's rho - 1 become its next references (as in the single solve).
+// `steps` sweeps of the lattices of group g from buffer cur; with `pending` the first one
+// moves the state to the references of the last check; the last one checks, then the
+// group's per-lattice sums go to w.res and each lattice's references are fitted to its
+// checked rho - 1 (as in the single solve).
 static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, int32_t collision,
-                              const BatchGroup &g, int cur, int sframe, bool pending,
-                              int64_t steps, bool check_last, const std::vector<LatRef> &lr,
+                              const BatchGroup &g, int cur, bool pending, int64_t steps,
+                              bool check_last, const std::vector<LatRef> &lr,
                               const std::vector<int32_t> &lat_ids_h, hipStream_t s) {
     const int64_t n_live = g.n_blk;
     a.launched_live = n_live;
@@ -1259,17 +1356,21 @@ static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, i
     for (int64_t t = 0; t < steps; t++) {
         a.src = w.f[cur];
         a.dst = w.f[cur ^ 1];
-        a.sref_src = a.sref_dst = w.sref[sframe];
-        a.reframe = 0;
-        if (pending && t == 0) {
-            a.sref_dst = w.sref[sframe ^ 1];
-            a.reframe = 1;
-        }
+        a.fh = w.fh;
+        a.href_next = w.href_next;
+        a.reframe = pending && t == 0;
         if (check_last && t == steps - 1) launch19b<true>(a, m, collision, descs, s);
         else launch19b<false>(a, m, collision, descs, s);
         LBM_CHECK_LAUNCH();
         cur ^= 1;
-        if (a.reframe) sframe ^= 1;
+        if (a.reframe)  // the group's lattices are now relative to their new references
+            for (int32_t k = 0; k < g.n_lat; k++) {
+                const LatRef &L = lr[lat_ids_h[g.lat_off + k]];
+                const int64_t nh = 2 * L.nsegs;
+                k_ref_commit<<<(unsigned)((nh + 255) / 256), 256, 0, s>>>(
+                    nh, w.href_next + 2 * L.rk0, w.fh + 2 * L.rk0);
+                LBM_CHECK_LAUNCH();
+            }
     }
     if (check_last) {
         k_lat_reduce<kFlowSums><<<(unsigned)g.n_lat, 256, 0, s>>>(w.partials, w.lats,
@@ -1278,8 +1379,9 @@ static lbm_status batch_steps(const BatchWs &w, Sweep19 a, const Variant19 &m, i
         if (steps > 0)
             for (int32_t k = 0; k < g.n_lat; k++) {
                 const LatRef &L = lr[lat_ids_h[g.lat_off + k]];
-                k_seg_ref<<<(unsigned)((L.nsegs + 255) / 256), 256, 0, s>>>(
-                    L.nsegs, w.rank + L.rk0, w.dsnap + L.n0, w.sref[sframe ^ 1] + L.rk0);
+                const int64_t nh = 2 * L.nsegs;
+                k_half_fit<<<(unsigned)((nh + 255) / 256), 256, 0, s>>>(
+                    nh, w.rank + L.rk0, w.dsnap + L.n0, w.href_next + 2 * L.rk0);
                 LBM_CHECK_LAUNCH();
             }
     }
@@ -1363,10 +1465,12 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         st = layout_fill(g, w.rank + rk0, w.coords + n0, s);
         if (st != LBM_OK) return st;
         const int64_t b1 = b0 + blocks_for(nf), span = (b1 - b0) * 256;
-        // from rest: every reference density 0
-        LBM_TRY_HIP(hipMemsetAsync(w.sref[0] + rk0, 0, sizeof(float) * g.nsegs(), s));
+        // from rest: the half records with every reference 0
+        k_flow_halves<<<(unsigned)((2 * g.nsegs() + 255) / 256), 256, 0, s>>>(
+            2 * g.nsegs(), w.rank + rk0, w.fh + 2 * rk0);
+        LBM_CHECK_LAUNCH();
         k_flow_init<StoreF32><<<(unsigned)blocks_for(nf), 256, 0, s>>>(
-            g, nf, span, w.coords + n0, nullptr, 0, w.f[0] + 19 * n0, 1.f, w.sref[0] + rk0,
+            g, nf, span, w.coords + n0, nullptr, 0, w.f[0] + 19 * n0, 1.f, w.fh + 2 * rk0,
             w.usnap + 3 * n0);
         LBM_CHECK_LAUNCH();
         lref[l] = LatRef{g.nsegs(), rk0, n0};
@@ -1429,7 +1533,7 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
     const int64_t limit = p->fixed_steps > 0 ? p->fixed_steps : p->max_steps;
     const int nc = p->check_every;
     const bool use_graph = !(p->variant & LBM_VARIANT_NOGRAPH);
-    int cur = 0, sframe = 0;
+    int cur = 0;
     bool pending = false;  // references of a check not yet entered (none before the first)
     int64_t t = 0;
     double sweep_ms = 0.0, updates = 0.0, tune_ms = 0.0;
@@ -1455,14 +1559,14 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         const int64_t chunk = std::min<int64_t>(nc - (t % nc), limit - t);
         if (use_graph && chunk == nc && pending) {
             // capture what is missing first, so that the timed region holds kernels only;
-            // one graph per group and (buffer, reference frame) at the start of the interval
-            const int key = cur * 2 + sframe;
+            // one graph per group and buffer at the start of the interval
+            const int key = cur;
             for (size_t gi = 0; gi < groups.size(); gi++) {
                 hipGraphExec_t &ex = R.exec[gi * BatchRes::kKeys + key];
                 if (ex) continue;
                 LBM_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 st = batch_steps(w, a, group_mode(groups[gi]), p->collision, groups[gi], cur,
-                                 sframe, true, chunk, true, lref, lat_ids_h, s);
+                                 true, chunk, true, lref, lat_ids_h, s);
                 hipGraph_t graph = nullptr;
                 hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (st != LBM_OK) {
@@ -1479,8 +1583,8 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
         } else {
             LBM_TRY_HIP(hipEventRecord(R.e0, s));
             for (const BatchGroup &g : groups) {
-                st = batch_steps(w, a, group_mode(g), p->collision, g, cur, sframe, pending,
-                                 chunk, true, lref, lat_ids_h, s);
+                st = batch_steps(w, a, group_mode(g), p->collision, g, cur, pending, chunk,
+                                 true, lref, lat_ids_h, s);
                 if (st != LBM_OK) return st;
             }
         }
@@ -1505,8 +1609,7 @@ extern "C" lbm_status lbm_flow_solve_batch(int32_t count, const int32_t *n_h,
             regroup_now = tune_k < kBatchBudgets || budget != cand[kBatchBudgets - 1];
         }
         cur ^= (int)(chunk & 1);
-        if (pending) sframe ^= 1;  // the interval moved to the last check's references
-        pending = true;            // and its check formed the next ones
+        pending = true;  // the interval's check formed the next references
         t += chunk;
         std::vector<int32_t> keep;
         for (int l : act) {

@@ -167,7 +167,8 @@ def test_props_relations(lib, orc):
     assert out["k_apparent_m2"] == pytest.approx(2.25e-19 * out["fc_dgm"], rel=1e-14)
     assert out["mean_free_path_m"] == pytest.approx(orc.mean_free_path(1.73e-5, 17236893.0, 323.0),
                                                     rel=1e-14)
-    assert out["bruggeman_alpha"] == pytest.approx(math.log(0.1) / math.log(0.4), rel=1e-14)
+    assert out["bruggeman_alpha"] == pytest.approx(orc.bruggeman_alpha(0.1, 0.4), rel=1e-14)
+    assert out["tortuosity"] == 4.0 and out["Deff_m2s"] == pytest.approx(0.1 * dk, rel=1e-15)
     partial = lib.lbm_props(g, None, None)
     assert math.isnan(partial["k_m2"]) and partial["porosity"] == 0.4
 

@@ -145,6 +145,10 @@ def test_flow_parity_32(orc):
     assert r["residual"] == pytest.approx(o["residual"], rel=1e-3)
     assert abs(r["mass_dev"]) < 1e-3
     say("k", r["k_lattice"], o["k_lattice"], "mlups", r["mlups"])
+    # Eq. 15: k in m^2 and mD against the oracle's conversion of its own k
+    dx = w["voxel_nm"] * 1e-9
+    assert r["k_m2"] == pytest.approx(orc.k_physical(o["k_lattice"], dx), rel=1e-4)
+    assert r["k_mD"] == pytest.approx(orc.m2_to_mD(orc.k_physical(o["k_lattice"], dx)), rel=1e-4)
 
 
 @pytest.mark.parametrize("shape,seed,force", [((13, 21, 10), 3, (1e-5, 2e-6, -3e-6)),
@@ -242,6 +246,23 @@ def test_knudsen_parity_32(orc):
     assert np.allclose(r["plane_flux"], o["plane_flux"], rtol=1e-4, atol=1e-6)
     assert r["residual"] == pytest.approx(o["residual"], rel=1e-3)
     say("Deff", r["Deff_lattice"], o["Deff_lattice"])
+    # the reported physical quantities against the oracle's relations (Eqs. 11, 15, 16)
+    # applied to the oracle's own solve
+    eps = pore_o.mean()
+    dk = orc.knudsen_diffusivity(kp["d_ref_nm"] * 1e-9, kp["T"])
+    assert r["DK_ref_m2s"] == pytest.approx(dk, rel=1e-12)
+    assert r["Deff_m2s"] == pytest.approx(orc.deff_physical(o["Deff_lattice"], 0.25, kp["tau_ref"],
+                                                            dk), rel=1e-4)
+    assert r["tortuosity"] == pytest.approx(
+        orc.tortuosity(eps, orc.lattice_diffusivity(0.25, kp["tau_ref"]), o["Deff_lattice"]),
+        rel=1e-4)
+    props = lbm.lbm_props(None, None, r, d_mean_nm=rp["d_mean"] * w["voxel_nm"], T=kp["T"])
+    assert math.isnan(props["bruggeman_alpha"])  # needs the porosity from labelling
+    _, _, ls = lbm.lbm_label(pore_g)
+    props = lbm.lbm_props(ls, None, r, d_mean_nm=rp["d_mean"] * w["voxel_nm"], T=kp["T"])
+    assert props["bruggeman_alpha"] == pytest.approx(
+        orc.bruggeman_alpha(o["Deff_lattice"] / orc.lattice_diffusivity(0.25, kp["tau_ref"]), eps),
+        rel=1e-3)
 
 
 @pytest.mark.parametrize("shape,seed", [((19, 10, 14), 2), ((33, 7, 5), 8)])
