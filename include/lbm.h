@@ -183,6 +183,21 @@ lbm_status lbm_label(const int32_t n[3], const uint8_t *pore, int32_t *label, ui
                      lbm_label_stats *stats_h, void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------------
+ * lbm_label without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same labelling, counts and results as lbm_label, with its scratch (counters and the
+ * two per-voxel face-flag arrays) in a static device array of 32 MiB + 256 B that each
+ * device holds from the first call until the process ends.  It calls no hipMalloc,
+ * hipFree or allocating library routine, and clears its scratch with kernels.
+ * Volumes above LBM_LABEL_NOALLOC_MAX_VOXELS (256^3) fail with LBM_E_NOMEM.  Every call
+ * on one device shares that device's scratch: calls that overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * ---------------------------------------------------------------------------- */
+#define LBM_LABEL_NOALLOC_MAX_VOXELS (16777216LL)
+lbm_status lbm_label_noalloc(const int32_t n[3], const uint8_t *pore, int32_t *label,
+                             uint8_t *transport, lbm_label_stats *stats_h, void *stream);
+
+/* ------------------------------------------------------------------------------
  * Local pore diameter in voxels (double, 0 at solid voxels).
  * LBM_PSD_CHORD13 (Section 4.1): per pore voxel, the mean of its pore chords along
  *   13 directions (3 axes, 6 face diagonals, 4 body diagonals), each chord the run

@@ -3,8 +3,10 @@
 // squared Euclidean distance map with its maximum-inscribed-sphere pore width.
 // Everything is integer except the final FP64 formulas, which are evaluated in the
 // stated order (this file is compiled with -ffp-contract=off).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "lbm_internal.h"
@@ -305,26 +307,34 @@ size_t diam_ws_bytes_n(const int32_t n[3]) {
 }
 }  // namespace lbm
 
-extern "C" lbm_status lbm_label(const int32_t n[3], const uint8_t *pore, int32_t *label,
-                                uint8_t *transport, lbm_label_stats *stats_h, void *workspace,
-                                size_t ws_bytes, void *stream) {
-    lbm_status st = check_n(n);
-    if (st != LBM_OK) return st;
-    LBM_REQUIRE(pore && label && stats_h && workspace, LBM_E_INVAL, "lbm_label: null argument");
-    LBM_REQUIRE(ws_bytes >= label_ws_bytes_n(n), LBM_E_NOMEM, "lbm_label: workspace too small");
-    st = check_device();
-    if (st != LBM_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const Grid g = make_grid(n);
-    Carver c(workspace);
-    unsigned long long *counts = c.take<unsigned long long>(4);
-    uint8_t *fin = c.take<uint8_t>(g.nvox());
-    uint8_t *fout = c.take<uint8_t>(g.nvox());
+namespace lbm {
+// Zero fill of scratch memory by a kernel (no memset node in a caller's captured graph).
+__global__ __launch_bounds__(256) void k_zero_bytes(uint8_t *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
+// The labelling passes on scratch holding 4 counters and two voxel flag arrays (cleared
+// here: by memsets, or by fill kernels when `fill` is set), then the stats (host sync).
+static lbm_status label_run(const Grid &g, const uint8_t *pore, int32_t *label, uint8_t *transport,
+                            lbm_label_stats *stats_h, unsigned long long *counts, uint8_t *fin,
+                            uint8_t *fout, bool fill, hipStream_t s) {
     const int64_t nv = g.nvox();
     const unsigned blocks = (unsigned)((nv + 255) / 256);
-    LBM_TRY_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(unsigned long long), s));
-    LBM_TRY_HIP(hipMemsetAsync(fin, 0, nv, s));
-    LBM_TRY_HIP(hipMemsetAsync(fout, 0, nv, s));
+    if (fill) {
+        k_zero_bytes<<<1, 256, 0, s>>>(reinterpret_cast<uint8_t *>(counts),
+                                        4 * sizeof(unsigned long long));
+        LBM_CHECK_LAUNCH();
+        const unsigned zb = (unsigned)std::min<int64_t>((nv + 255) / 256, 4096);
+        k_zero_bytes<<<zb, 256, 0, s>>>(fin, nv);
+        LBM_CHECK_LAUNCH();
+        k_zero_bytes<<<zb, 256, 0, s>>>(fout, nv);
+        LBM_CHECK_LAUNCH();
+    } else {
+        LBM_TRY_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(unsigned long long), s));
+        LBM_TRY_HIP(hipMemsetAsync(fin, 0, nv, s));
+        LBM_TRY_HIP(hipMemsetAsync(fout, 0, nv, s));
+    }
     k_ccl_init<<<blocks, 256, 0, s>>>(nv, pore, label);
     LBM_CHECK_LAUNCH();
     k_ccl_merge<<<blocks, 256, 0, s>>>(g, pore, label);
@@ -344,6 +354,71 @@ extern "C" lbm_status lbm_label(const int32_t n[3], const uint8_t *pore, int32_t
     stats_h->porosity = (double)h[0] / (double)nv;
     stats_h->connectivity = h[0] ? (double)h[1] / (double)h[0] : 0.0;
     return LBM_OK;
+}
+
+// Scratch of lbm_label_noalloc: 256 bytes of counters and the two face-flag arrays of a
+// volume of up to LBM_LABEL_NOALLOC_MAX_VOXELS voxels (32 MiB + 256 B in all), one copy per
+// device for the life of the process.  Host code uses the per-device address from
+// hipGetSymbolAddress, never the symbol itself.
+constexpr int64_t kNoallocVox = LBM_LABEL_NOALLOC_MAX_VOXELS;
+static __device__ __align__(256) uint8_t scratch[256 + 2 * kNoallocVox];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static lbm_status scratch_address(void **out) {
+    int dev = -1;
+    LBM_TRY_HIP(hipGetDevice(&dev));
+    LBM_REQUIRE(dev >= 0 && dev < kMaxDevices, LBM_E_DEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        LBM_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        LBM_REQUIRE(p, LBM_E_DEVICE, "no address for the scratch array on device %d", dev);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace lbm
+
+extern "C" lbm_status lbm_label(const int32_t n[3], const uint8_t *pore, int32_t *label,
+                                uint8_t *transport, lbm_label_stats *stats_h, void *workspace,
+                                size_t ws_bytes, void *stream) {
+    lbm_status st = check_n(n);
+    if (st != LBM_OK) return st;
+    LBM_REQUIRE(pore && label && stats_h && workspace, LBM_E_INVAL, "lbm_label: null argument");
+    LBM_REQUIRE(ws_bytes >= label_ws_bytes_n(n), LBM_E_NOMEM, "lbm_label: workspace too small");
+    st = check_device();
+    if (st != LBM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid g = make_grid(n);
+    Carver c(workspace);
+    unsigned long long *counts = c.take<unsigned long long>(4);
+    uint8_t *fin = c.take<uint8_t>(g.nvox());
+    uint8_t *fout = c.take<uint8_t>(g.nvox());
+    return label_run(g, pore, label, transport, stats_h, counts, fin, fout, false, s);
+}
+
+extern "C" lbm_status lbm_label_noalloc(const int32_t n[3], const uint8_t *pore, int32_t *label,
+                                        uint8_t *transport, lbm_label_stats *stats_h,
+                                        void *stream) {
+    lbm_status st = check_n(n);
+    if (st != LBM_OK) return st;
+    LBM_REQUIRE(pore && label && stats_h, LBM_E_INVAL, "lbm_label_noalloc: null argument");
+    const Grid g = make_grid(n);
+    LBM_REQUIRE(g.nvox() <= kNoallocVox, LBM_E_NOMEM,
+                "lbm_label_noalloc: %lld voxels exceed its scratch of %lld voxels",
+                (long long)g.nvox(), (long long)kNoallocVox);
+    st = check_device();
+    if (st != LBM_OK) return st;
+    void *base = nullptr;
+    st = scratch_address(&base);
+    if (st != LBM_OK) return st;
+    uint8_t *b = static_cast<uint8_t *>(base);
+    return label_run(g, pore, label, transport, stats_h, reinterpret_cast<unsigned long long *>(b),
+                     b + 256, b + 256 + g.nvox(), true, static_cast<hipStream_t>(stream));
 }
 
 extern "C" lbm_status lbm_pore_diameter(const int32_t n[3], const uint8_t *pore, int32_t method,

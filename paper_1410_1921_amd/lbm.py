@@ -119,6 +119,7 @@ _SIGS = {
     "lbm_reconstruct": ([C.POINTER(lbm_recon_params), _P, _P, C.c_int64,
                          C.POINTER(lbm_recon_stats), _P], C.c_int32),
     "lbm_label": ([_P, _P, _P, _P, C.POINTER(lbm_label_stats), _P, C.c_size_t, _P], C.c_int32),
+    "lbm_label_noalloc": ([_P, _P, _P, _P, C.POINTER(lbm_label_stats), _P], C.c_int32),
     "lbm_pore_diameter": ([_P, _P, C.c_int32, _P, _P, C.c_size_t, _P], C.c_int32),
     "lbm_count": ([_P, _P, C.POINTER(C.c_int64), _P, C.c_size_t, _P], C.c_int32),
     "lbm_flow_solve": ([_P, _P, C.POINTER(lbm_flow_params), C.POINTER(lbm_flow_result), _P, _P,
@@ -292,6 +293,17 @@ def lbm_label(pore, want_transport=True):
     st = lbm_label_stats()
     _check(load().lbm_label(_n3(pore.shape), _ptr(pore), _ptr(label), _ptr(tr), C.byref(st),
                             ws.ptr, ws.nbytes, _stream()), "lbm_label")
+    return label, tr, _as_dict(st)
+
+
+def lbm_label_noalloc(pore, want_transport=True):
+    """lbm_label on the library's static scratch (no workspace; volumes up to 256^3)."""
+    _vol(pore, torch.uint8, "pore")
+    label = torch.empty(pore.shape, dtype=torch.int32, device=pore.device)
+    tr = torch.empty(pore.shape, dtype=torch.uint8, device=pore.device) if want_transport else None
+    st = lbm_label_stats()
+    _check(load().lbm_label_noalloc(_n3(pore.shape), _ptr(pore), _ptr(label), _ptr(tr),
+                                    C.byref(st), _stream()), "lbm_label_noalloc")
     return label, tr, _as_dict(st)
 
 

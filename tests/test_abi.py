@@ -27,7 +27,7 @@ def _declared(header=HEADER):
 def test_every_declared_symbol_is_exported(lib):
     L = lib.load()
     names = _declared() + _declared(os.path.join(ROOT, "include", "lbm_nn.h"))
-    assert len(names) == 20 + 15
+    assert len(names) == 21 + 15
     for name in names:
         assert hasattr(L, name), name
     # and the binding wraps each of them
