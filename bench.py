@@ -40,8 +40,9 @@ BYTES_D3Q7 = 60    # 7 loads + 7 stores of binary32 + 1/tau_g
 BYTES_D3Q19D = 156  # the D3Q19 diffusion lattice: 19 loads + 19 stores + 1/tau_g
 STEPS_PER_BENCH_STEP = 1000
 # the solves' stop rule: residual 1e-7 and the steady-state test (flow: estimated distance
-# to steady state <= 1e-3; Knudsen: link-plane flux spread <= 5e-4)
-TOL, FLOW_STEADY, KN_STEADY = 1e-7, 1e-3, 5e-4
+# to steady state <= 1e-3; Knudsen: link-plane flux spread <= 2e-3, which holds the outlet
+# D_eff within ~1e-3 of its steady value and the plane-mean D_eff far closer)
+TOL, FLOW_STEADY, KN_STEADY = 1e-7, 1e-3, 2e-3
 SWEEP19 = "k_sweep19<StoreF32, false, true, 0, false, unsigned int>"
 SWEEP7 = "k_sweep7<false, false, unsigned int>"
 
@@ -159,7 +160,7 @@ def crop_precision(lbm, W, pore):
             rec["k_vs_oracle_rel"] = r["k_lattice"] / gold["k_lattice"] - 1
             rec["oracle_steps"] = gold["steps"]
         if name == "fp16":  # its residual stops decaying at the rounding floor
-            cap = 2 * out["fp32"]["steps"]
+            cap = out["fp32"]["steps"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = lbm.lbm_flow_solve(sub, max_steps=cap, tol=TOL, steady_tol=FLOW_STEADY,
@@ -174,7 +175,7 @@ def crop_precision(lbm, W, pore):
     for name in ("fp32", "fp16"):
         out[name]["k_vs_fp64_converged_rel"] = out[name]["k_lattice"] / k64 - 1
     out["fp16_note"] = ("binary16 does not meet the stop rule (its residual stops decaying at "
-                        "the rounding floor); its run is capped at twice binary32's steps")
+                        "the rounding floor); its run is capped at binary32's steps")
     del sub
     torch.cuda.empty_cache()
     return out
@@ -235,18 +236,21 @@ def pipelines_128(lbm, W):
                   "stage_s": {k: round(v, 3) for k, v in p["t"].items()},
                   "flow_steps": fr["steps"], "knudsen_steps": kr["steps"],
                   "k_lattice": fr["k_lattice"], "k_mD": fr["k_mD"],
-                  "Deff_lattice": kr["Deff_lattice"], "Deff_m2s": kr["Deff_m2s"],
+                  "Deff_lattice": kr["Deff_lattice"], "Deff_planes": kr["Deff_planes"],
+                  "Deff_m2s": kr["Deff_m2s"],
                   "tortuosity": kr["tortuosity"], "flux_spread": kr["flux_spread"],
                   "flow_mlups": round(fr["mlups"], 1), "knudsen_mlups": round(kr["mlups"], 1),
                   "connectivity": p["label"]["connectivity"],
                   "bruggeman_alpha": p["props"]["bruggeman_alpha"]},
         "warm_start": {"time_to_converged_s": round(q["t"]["total"], 3),
                        "knudsen_steps": kw_["steps"], "warm_used": q["warm_used"],
-                       "Deff_lattice": kw_["Deff_lattice"], "flux_spread": kw_["flux_spread"],
+                       "Deff_lattice": kw_["Deff_lattice"], "Deff_planes": kw_["Deff_planes"],
+                       "flux_spread": kw_["flux_spread"],
                        "applied_to": "Knudsen C (the flow starts from rest)"},
         "speedup": round(p["t"]["total"] / q["t"]["total"], 3),
         "knudsen_speedup": round(p["t"]["knudsen"] / q["t"]["knudsen"], 3),
         "deff_rel_diff": abs(kw_["Deff_lattice"] / kr["Deff_lattice"] - 1),
+        "deff_planes_rel_diff": abs(kw_["Deff_planes"] / kr["Deff_planes"] - 1),
         "k_rel_diff": abs(q["flow"]["k_lattice"] / fr["k_lattice"] - 1),
         "k_sweep7": {"kernel": SWEEP7, "ms_per_launch": per7,
                      "achieved_gbs": round(kr["n_fluid"] * BYTES_D3Q7 / (per7 * 1e-3) / 1e9, 1),
@@ -254,11 +258,13 @@ def pipelines_128(lbm, W):
     }
 
 
-def batch_geometry(lbm, W, count):
-    """The first `count` reconstructions of the batch workload with their pore maps."""
+def batch_geometry(lbm, W, count, max_edge=1024):
+    """The first `count` reconstructions of the batch workload with an edge of at most
+    max_edge, with their pore maps."""
     import torch
     fl, dm, nf = [], [], []
-    for rp in W.batch_params(W.BATCH["count"])[:count]:
+    sel = [rp for rp in W.batch_params(W.BATCH["count"]) if rp["n"][0] <= max_edge][:count]
+    for rp in sel:
         pore, rs = recon(lbm, rp)
         fl.append(pore)
         nf.append(rs["n_pore"])
@@ -318,14 +324,14 @@ def batch_throughput(lbm, W, flow_steps, kn_steps):
     return out
 
 
-def batch_converge(lbm, W, count, net):
+def batch_converge(lbm, W, count, net, max_edge=96):
     """Time to the converged k and D_eff (residual 1e-7 and the steady-state test) of the
-    first `count` lattices of the batch workload: plain (one solve after the other, from
-    rest) against batched (autotuned groups, graphs) with the Knudsen solves warm-started
-    by the network."""
+    first `count` lattices of the batch workload with an edge of at most max_edge: plain
+    (one solve after the other, from rest) against batched (autotuned groups, graphs)
+    with the Knudsen solves warm-started by the network."""
     import torch
     from paper_1410_1921_amd import warmstart as WS
-    fl, dm, nf = batch_geometry(lbm, W, count)
+    fl, dm, nf = batch_geometry(lbm, W, count, max_edge)
     fp = W.BATCH["flow"]
     ka = _kn_args(W)
     kp = W.BATCH["knudsen"]
@@ -359,7 +365,9 @@ def batch_converge(lbm, W, count, net):
     perc = [i for i, p in enumerate(plain_f) if p["converged"] and p["k_lattice"] > 1e-12]
     dk = [abs(bf[i]["k_lattice"] / plain_f[i]["k_lattice"] - 1) for i in perc]
     dd = [abs(bk[i]["Deff_lattice"] / plain_k[i]["Deff_lattice"] - 1) for i in perc]
-    return {"workload": W.BATCH["name"], "lattices": count, "n_fluid": int(sum(nf)),
+    ddp = [abs(bk[i]["Deff_planes"] / plain_k[i]["Deff_planes"] - 1) for i in perc]
+    return {"workload": W.BATCH["name"], "lattices": len(fl), "n_fluid": int(sum(nf)),
+            "selection": f"the first {len(fl)} lattices with an edge of at most {max_edge}",
             "edges": [int(f.shape[0]) for f in fl],
             "stop_rule": {"tol": TOL, "flow_steady_dist": FLOW_STEADY,
                           "knudsen_flux_spread": KN_STEADY},
@@ -375,6 +383,7 @@ def batch_converge(lbm, W, count, net):
             "percolating": len(perc),
             "k_rel_diff_max": max(dk) if dk else 0.0,
             "deff_rel_diff_max": max(dd) if dd else 0.0,
+            "deff_planes_rel_diff_max": max(ddp) if ddp else 0.0,
             "schedule": {"flow": sf, "knudsen": sk}}
 
 
@@ -409,7 +418,8 @@ def warm_eval(lbm, W, seeds):
     96^3): plain against warm-started solves, one after the other, to steady state."""
     from paper_1410_1921_amd import warmstart as WS
     net = WS.load_network()
-    cfg = dict(W.WARMSTART)
+    # flows without a path along x never meet the stop rule (u decays to 0): capped
+    cfg = dict(W.WARMSTART, flow=dict(W.WARMSTART["flow"], max_steps=60_000))
     rows = WS.evaluate(net, seeds, cfg, tol=TOL, log=lambda *a: log(*a),
                        steady=(FLOW_STEADY, KN_STEADY))
     return {"seeds": [int(s) for s in seeds], "summary": WS.summary(rows), "rows": rows}
@@ -511,8 +521,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline line only")
     ap.add_argument("--batch-steps", type=int, default=500,
                     help="fixed steps of each lattice in the batch-workload leg")
-    ap.add_argument("--batch-converge", type=int, default=3, metavar="COUNT",
-                    help="lattices of the batch workload in the time-to-converged leg")
+    ap.add_argument("--batch-converge", type=int, default=8, metavar="COUNT",
+                    help="lattices of the batch workload (edges up to 96) in the "
+                         "time-to-converged leg")
     ap.add_argument("--only-512", action="store_true",
                     help="only the 512^3 geometry and sweeps, after 2 GiB copies by the library's "
                          "copy kernel that calibrate the HBM byte counters (profiling runs)")

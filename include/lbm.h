@@ -430,6 +430,11 @@ typedef struct {
     double sweep_ms, mlups, gbps;        /* gbps with 60 (D3Q7) or 156 (D3Q19) algorithmic
                                             bytes per update */
     double steady_dist;                  /* as in lbm_flow_result, for C */
+    double Deff_planes;                  /* Eq. 14 with the mean of the nx + 1 link-plane
+                                            fluxes in place of the outlet's: equal to
+                                            Deff_lattice at steady state, nearer to it
+                                            before (each slow mode's flux profile along x
+                                            averages out) */
 } lbm_knudsen_result;
 
 lbm_status lbm_knudsen_solve(const int32_t n[3], const uint8_t *fluid, const double *pore_diam,

@@ -356,9 +356,13 @@ def knudsen_solve(fluid, tau_g_field, c_in=1.0, c_out=0.0, max_steps=1_000_000, 
                                  check_every, tol, cp, g, c, planes, out)
     if st < 0:
         raise OracleError(st, "knudsen_solve")
-    return {"status": st, "steps": int(out[0]), "Deff_lattice": out[1], "residual": out[2],
-            "phi_out": out[3], "phi_in": out[4], "sum_c": out[5], "converged": bool(out[6]),
-            "c": c, "plane_flux": planes, "g": g}
+    res = {"status": st, "steps": int(out[0]), "Deff_lattice": out[1], "residual": out[2],
+           "phi_out": out[3], "phi_in": out[4], "sum_c": out[5], "converged": bool(out[6]),
+           "c": c, "plane_flux": planes, "g": g}
+    if planes is not None:
+        # Eq. 14 with the mean link-plane flux in place of the outlet's
+        res["Deff_planes"] = planes.mean() / (ny * nz) * (nx + 1) / (c_in - c_out)
+    return res
 
 
 def diffusion19_init(fluid, c_init=None):

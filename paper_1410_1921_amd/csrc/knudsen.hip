@@ -812,6 +812,7 @@ static void kn_result(lbm_knudsen_result *r, const lbm_knudsen_params *p, const 
     }
     mean /= (double)(g.nx + 1);
     r->flux_spread = mean != 0.0 ? (mx - mn) / std::fabs(mean) : INFINITY;
+    r->Deff_planes = mean / ((double)g.ny * g.nz) * (double)(g.nx + 1) / dc;
     r->sweep_ms = sweep_ms;
     r->mlups = sweep_ms > 0 ? updates / (sweep_ms * 1e3) : 0.0;
     const double bytes = lattice == LBM_LATTICE_D3Q19 ? 156.0 : 60.0;  // 2 x q x 4 + 1/tau_g

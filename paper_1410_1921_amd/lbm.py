@@ -91,7 +91,7 @@ class lbm_knudsen_result(C.Structure):
                 ("tortuosity_local", C.c_double), ("phi_in", C.c_double), ("phi_out", C.c_double),
                 ("flux_spread", C.c_double), ("residual", C.c_double), ("sum_c", C.c_double),
                 ("sweep_ms", C.c_double), ("mlups", C.c_double), ("gbps", C.c_double),
-                ("steady_dist", C.c_double)]
+                ("steady_dist", C.c_double), ("Deff_planes", C.c_double)]
 
 
 class lbm_props_params(C.Structure):

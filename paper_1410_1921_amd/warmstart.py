@@ -179,7 +179,10 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
              steady=(0.0, 0.0)):
     """Solves each held-out geometry from rest and from the network's fields (one after
     the other, so the wall times compare) to residual tol and the steady-state tests
-    `steady` (see solve_pair); returns one record per seed."""
+    `steady` (see solve_pair); the warm-started solves fall back to the solve from rest
+    when they do not converge.  Without flow_warm the flow starts from rest in both forms,
+    one computation counted in both.  Returns one record per seed."""
+    fp, kp = cfg["flow"], cfg["knudsen"]
     rows = []
     for seed in seeds:
         rp = W.warmstart_params(seed, cfg["edge"])
@@ -190,14 +193,30 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
         u0, c0 = predict(net, pore, diam)
         torch.cuda.current_stream().synchronize()
         t_inf = time.perf_counter() - t0
-        w_f, w_k, (w_tf, w_tk) = solve_pair(pore, diam, cfg, tol,
-                                            u_init=u0.contiguous() if flow_warm else None,
-                                            c_init=c0.contiguous(), n_fluid=nf, steady=steady)
+        if flow_warm:
+            t0 = time.perf_counter()
+            w_f, _ = flow_warm_or_rest(
+                pore, u0.contiguous(), tau=fp["tau"], force=fp["force"],
+                max_steps=fp["max_steps"], check_every=fp["check_every"], tol=tol,
+                voxel_nm=cfg["voxel_nm"], with_rho=True, n_fluid=nf, steady_tol=steady[0])
+            torch.cuda.current_stream().synchronize()
+            w_tf = time.perf_counter() - t0
+        else:
+            w_f, w_tf = p_f, p_tf
+        t0 = time.perf_counter()
+        w_k, used = knudsen_warm_or_rest(
+            pore, diam, c0.contiguous(), tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+            voxel_nm=cfg["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"], T=kp["T"],
+            max_steps=kp["max_steps"], check_every=kp["check_every"], tol=tol, n_fluid=nf,
+            steady_tol=steady[1])
+        torch.cuda.current_stream().synchronize()
+        w_tk = time.perf_counter() - t0
         row = dict(seed=seed, porosity=rs["porosity"], n_fluid=nf,
                    plain_steps=[p_f["steps"], p_k["steps"]], warm_steps=[w_f["steps"], w_k["steps"]],
                    plain_s=[p_tf, p_tk], warm_s=[w_tf, w_tk], inference_s=t_inf,
                    converged=[bool(p_f["converged"]), bool(p_k["converged"]),
                               bool(w_f["converged"]), bool(w_k["converged"])],
+                   warm_used=bool(used),
                    k_plain=p_f["k_lattice"], k_warm=w_f["k_lattice"],
                    deff_plain=p_k["Deff_lattice"], deff_warm=w_k["Deff_lattice"])
         rows.append(row)
@@ -232,7 +251,8 @@ def summary(rows):
                 k_rel_diff_median=float(np.median(dk)), k_rel_diff_max=float(dk.max()),
                 deff_rel_diff_median=float(np.median(dd)), deff_rel_diff_max=float(dd.max()),
                 knudsen_converged=[sum(r["converged"][1] for r in rows),
-                                   sum(r["converged"][3] for r in rows)])
+                                   sum(r["converged"][3] for r in rows)],
+                warm_used=sum(bool(r.get("warm_used", True)) for r in rows))
 
 
 def default_weights():

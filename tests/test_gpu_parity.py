@@ -244,6 +244,7 @@ def test_knudsen_parity_32(orc):
     assert r["phi_in"] == pytest.approx(o["phi_in"], rel=1e-4)
     assert np.abs(r.field.cpu().numpy() - o["c"]).max() < 1e-5
     assert np.allclose(r["plane_flux"], o["plane_flux"], rtol=1e-4, atol=1e-6)
+    assert r["Deff_planes"] == pytest.approx(o["Deff_planes"], rel=1e-4)
     assert r["residual"] == pytest.approx(o["residual"], rel=1e-3)
     say("Deff", r["Deff_lattice"], o["Deff_lattice"])
     # the reported physical quantities against the oracle's relations (Eqs. 11, 15, 16)

@@ -126,3 +126,19 @@ def test_collision_conserves(orc):
     gout, c = orc.collide7(gin, 1.0)
     w = np.array([0.25] + [0.125] * 6)
     assert np.allclose(gout, w * c, atol=1e-16)
+
+
+def test_plane_mean_estimator(orc):
+    # D_eff from the mean link-plane flux: equal to the outlet's at steady state, and
+    # nearer to the steady value during the approach (the flux profile of each decaying
+    # mode along x averages out over the planes)
+    pore = W.square_duct(30, 3, pad=1)
+    nx = pore.shape[2]
+    tau = 1.0
+    want = pore.mean() * 0.25 * (tau - 0.5) * (nx + 1) / (nx - 1 + 2 * tau)
+    tg = np.where(pore == 1, tau, 1.0)
+    early = orc.knudsen_solve(pore, tg, 1.0, 0.0, fixed_steps=300, want_c=False)
+    assert abs(early["Deff_planes"] / want - 1) < 0.2 * abs(early["Deff_lattice"] / want - 1)
+    done = orc.knudsen_solve(pore, tg, 1.0, 0.0, tol=1e-13, max_steps=200_000, want_c=False)
+    assert done["Deff_planes"] == pytest.approx(want, rel=1e-9)
+    assert done["Deff_lattice"] == pytest.approx(want, rel=1e-9)
