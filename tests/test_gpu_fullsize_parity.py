@@ -138,10 +138,10 @@ def test_mis_512_bit_exact(crop):
 
 # binary32 at the bar of the full-size workloads; binary64, the GPU's FP64 reference, at
 # 1e-8 (both sides round at 1e-16 per operation in different orders, and 20 000 steps of
-# a slowly decaying iteration carry that to 1.2e-9 here); binary16, whose 11-bit
-# significand rounds the velocity part of every stored value to ~5e-4 each step, at 1e-2
-# (measured 6.0e-3 in k, 7.8e-3 of max|u|)
-@pytest.mark.parametrize("storage,bar_k,bar_u", [(lbm.LBM_STORE_FP64, 1e-8, 1e-8),
+# a slowly decaying iteration carry that to 1.2e-9 here; u itself is returned in
+# binary32, 6e-8 relative); binary16, whose 11-bit significand rounds the velocity part of
+# every stored value to ~5e-4 each step, at 1e-2 (measured 6.0e-3 in k, 7.8e-3 of max|u|)
+@pytest.mark.parametrize("storage,bar_k,bar_u", [(lbm.LBM_STORE_FP64, 1e-8, 1e-7),
                                                  (lbm.LBM_STORE_FP32, 1e-4, 1e-4),
                                                  (lbm.LBM_STORE_FP16, 1e-2, 2e-2)])
 def test_crop_storage_vs_oracle(crop, storage, bar_k, bar_u):
