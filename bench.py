@@ -52,7 +52,12 @@ SWEEP7 = "k_sweep7<false, false, unsigned int>"
 # WRITE_SIZE all of the bytes written).  A figure holds only while the kernel's sources
 # are those that were profiled (hash of the files).
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
-COUNTERS = {}
+COUNTERS = {
+    SWEEP19: dict(
+        workload="recon512_eps0.25_d16", fetch_kib=2217149.8, write_kib=2490368.6,
+        files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
+               "paper_1410_1921_amd/csrc/common.hip"), sha="27a0426197a890f5"),
+}
 
 
 def log(*a):
@@ -534,7 +539,9 @@ def main():
                     help="only the time to converged k of the 512^3 workload, binary32 and "
                          "binary16")
     ap.add_argument("--only-warm-eval", type=int, default=0, metavar="COUNT",
-                    help="only the learned warm start on the first COUNT held-out geometries")
+                    help="only the learned warm start on COUNT held-out geometries")
+    ap.add_argument("--warm-eval-start", type=int, default=0, metavar="INDEX",
+                    help="first held-out geometry of --only-warm-eval")
     ap.add_argument("--only-batch-converge", type=int, default=0, metavar="COUNT",
                     help="only the time-to-converged leg of the batch workload")
     ap.add_argument("--only-flow-sizes", action="store_true")
@@ -554,7 +561,8 @@ def main():
         print(json.dumps({"flow_sizes": flow_sizes(lbm)}), flush=True)
         return
     if args.only_warm_eval:
-        seeds = list(W.WARMSTART["test_seeds"])[:args.only_warm_eval]
+        i0 = args.warm_eval_start
+        seeds = list(W.WARMSTART["test_seeds"])[i0:i0 + args.only_warm_eval]
         print(json.dumps({"warm_eval": warm_eval(lbm, W, seeds)}), flush=True)
         return
     if args.only_batch_converge:
