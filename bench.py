@@ -43,6 +43,10 @@ STEPS_PER_BENCH_STEP = 1000
 # to steady state <= 1e-3; Knudsen: link-plane flux spread <= 2e-3, which holds the outlet
 # D_eff within ~1e-3 of its steady value and the plane-mean D_eff far closer)
 TOL, FLOW_STEADY, KN_STEADY = 1e-7, 1e-3, 2e-3
+# the batch and held-out lattices (edges up to 96, most fast to converge): flux spread
+# <= 5e-4, so that each form's outlet D_eff is within ~2.5e-4 of steady state and two
+# forms within 1e-3 of each other
+KN_STEADY_EVAL = 5e-4
 SWEEP19 = "k_sweep19<StoreF32, false, true, 0, false, unsigned int>"
 SWEEP7 = "k_sweep7<false, false, unsigned int>"
 
@@ -53,6 +57,10 @@ SWEEP7 = "k_sweep7<false, false, unsigned int>"
 # are those that were profiled (hash of the files).
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 COUNTERS = {
+    SWEEP7: dict(
+        workload="recon128_eps0.40_d12_mis_ch4_400K", fetch_kib=15340.9, write_kib=22966.8,
+        files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
+               "paper_1410_1921_amd/csrc/common.hip"), sha="b62b1248619e5586"),
     SWEEP19: dict(
         workload="recon512_eps0.25_d16", fetch_kib=2217149.8, write_kib=2490368.6,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
@@ -259,7 +267,8 @@ def pipelines_128(lbm, W):
         "k_rel_diff": abs(q["flow"]["k_lattice"] / fr["k_lattice"] - 1),
         "k_sweep7": {"kernel": SWEEP7, "ms_per_launch": per7,
                      "achieved_gbs": round(kr["n_fluid"] * BYTES_D3Q7 / (per7 * 1e-3) / 1e9, 1),
-                     "bound": "cache"},
+                     "bound": "cache", "traffic": traffic_gb(SWEEP7, w["name"]),
+                     "traffic_unit": "GB per launch"},
     }
 
 
@@ -343,7 +352,7 @@ def batch_converge(lbm, W, count, net, max_edge=96):
     fkw = dict(tau=fp["tau"], force=fp["force"], max_steps=fp["max_steps"],
                check_every=fp["check_every"], tol=TOL, steady_tol=FLOW_STEADY,
                voxel_nm=W.BATCH["voxel_nm"])
-    kkw = dict(max_steps=kp["max_steps"], tol=TOL, steady_tol=KN_STEADY, **ka)
+    kkw = dict(max_steps=kp["max_steps"], tol=TOL, steady_tol=KN_STEADY_EVAL, **ka)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plain_f = [lbm.lbm_flow_solve(f, n_fluid=n, **fkw) for f, n in zip(fl, nf)]
@@ -375,7 +384,11 @@ def batch_converge(lbm, W, count, net, max_edge=96):
             "selection": f"the first {len(fl)} lattices with an edge of at most {max_edge}",
             "edges": [int(f.shape[0]) for f in fl],
             "stop_rule": {"tol": TOL, "flow_steady_dist": FLOW_STEADY,
-                          "knudsen_flux_spread": KN_STEADY},
+                          "knudsen_flux_spread": KN_STEADY_EVAL},
+            "form": "batched + warm-started Knudsen, binary32 state; binary16 is left out "
+                    "(on the 512^3 crop it is 1.19 x faster per sweep but 6e-3 off in k and "
+                    "its residual stalls at its rounding floor, so it never meets the stop "
+                    "rule)",
             "plain_s": round(t_plain, 2), "plain_flow_s": round(t_pf, 2),
             "batched_warm_s": round(t_batch, 2), "batched_flow_s": round(t_bf, 2),
             "inference_s": round(t_inf, 2), "speedup": round(t_plain / t_batch, 3),
@@ -426,7 +439,7 @@ def warm_eval(lbm, W, seeds):
     # flows without a path along x never meet the stop rule (u decays to 0): capped
     cfg = dict(W.WARMSTART, flow=dict(W.WARMSTART["flow"], max_steps=60_000))
     rows = WS.evaluate(net, seeds, cfg, tol=TOL, log=lambda *a: log(*a),
-                       steady=(FLOW_STEADY, KN_STEADY))
+                       steady=(FLOW_STEADY, KN_STEADY_EVAL))
     return {"seeds": [int(s) for s in seeds], "summary": WS.summary(rows), "rows": rows}
 
 
@@ -624,7 +637,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "n": list(w["recon"]["n"]), "n_fluid": nf,
                    "lattice": "D3Q19 BGK + Guo force, half-way bounce-back, periodic",
-                   "storage": "f32 offsets from per-segment reference densities",
+                   "storage": "f32 offsets from linear reference densities per half row "
+                              "segment",
                    "solve_steps_per_step": STEPS_PER_BENCH_STEP,
                    "check_every": w["flow"]["check_every"]},
         "roofline": {"kernel": SWEEP19, "bound": "hbm", "achieved": round(achieved, 1),

@@ -218,30 +218,32 @@ __device__ inline void write_partials7(double (&acc)[NV], int64_t row, bool vali
         for (int k = 0; k < NV; k++) part[row * NV + k] = out[k];
 }
 
-// The update of fluid node n: its 6 pull sources through the rank map.
+// The update of fluid node n: its 6 pull sources.  A row's fluid nodes are consecutive
+// in the list, in x order, so the node at x - 1 (x + 1), when fluid, is n - 1 (n + 1):
+// the entry's coordinates tell, loaded from the cache lines of n's own; the four sources
+// in the neighbouring rows come from the rank map.
 template <bool CHECK, bool NT, class Off>
 __device__ inline void sweep7_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
     const uint32_t c = a.coords[n];
+    const uint32_t cm = n > 0 ? a.coords[n - 1] : 0xffffffffu;
+    const uint32_t cp = n + 1 < a.nf ? a.coords[n + 1] : 0xffffffffu;
     const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
     const Grid &g = a.g;
-    const int xm = x - 1, xp = x + 1;  // ghost planes beyond the x faces
     const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    // neighbour voxels in direction order 1..6 (source x - e_i); beyond an x face the
-    // node itself stands in, its id is replaced by -2 (ghost plane)
-    const int x1 = xm >= 0 ? xm : x, x2 = xp < g.nx ? xp : x;
-    const int nxs[7] = {x, x1, x2, x, x, x, x};
+    // rows of the sources 3..6 (source x - e_i)
     const int nys[7] = {y, y, y, ym, yp, y, y};
     const int nzs[7] = {z, z, z, z, z, zm, zp};
     RankWord rw[7];
 #pragma unroll
-    for (int i = 1; i < 7; i++) rw[i] = a.rank[g.seg(nxs[i], nys[i], nzs[i])];
+    for (int i = 3; i < 7; i++) rw[i] = a.rank[g.seg(x, nys[i], nzs[i])];
     int ids[7];
     ids[0] = 0;
+    // beyond an x face the source is the ghost plane (-2)
+    ids[1] = x == 0 ? -2 : (cm == pack_xyz(x - 1, y, z) ? (int)(n - 1) : -1);
+    ids[2] = x == g.nx - 1 ? -2 : (cp == pack_xyz(x + 1, y, z) ? (int)(n + 1) : -1);
 #pragma unroll
-    for (int i = 1; i < 7; i++) ids[i] = rank_lookup(rw[i], nxs[i] & (kSeg - 1));
-    if (xm < 0) ids[1] = -2;
-    if (xp >= g.nx) ids[2] = -2;
+    for (int i = 3; i < 7; i++) ids[i] = rank_lookup(rw[i], x & (kSeg - 1));
     node7<CHECK, NT, Off>(a, n, x, y, z, ids, acc);
 }
 
@@ -265,6 +267,10 @@ template <bool CHECK, bool NT, class Off>
 __device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[kKnSums]) {
     LBM_D3Q19_TABLES
     const uint32_t c = a.coords[n];
+    // the sources x -+ 1 in the node's own row are the list's neighbouring entries (see
+    // sweep7_node); the other 16 come from the rank map
+    const uint32_t cm = n > 0 ? a.coords[n - 1] : 0xffffffffu;
+    const uint32_t cp = n + 1 < a.nf ? a.coords[n + 1] : 0xffffffffu;
     const int x = c & 1023, y = (c >> 10) & 1023, z = c >> 20;
     const Grid &g = a.g;
     const bool gm = x == 0, gp = x == g.nx - 1;  // x - 1, x + 1 beyond a face
@@ -274,15 +280,19 @@ __device__ inline void sweep19d_node(const Sweep7 &a, int64_t n, double (&acc)[k
     zs[0] = z == 0 ? g.nz - 1 : z - 1; zs[1] = z; zs[2] = z == g.nz - 1 ? 0 : z + 1;
     RankWord rw[19];
 #pragma unroll
-    for (int i = 1; i < 19; i++)
+    for (int i = 3; i < 19; i++)
         rw[i] = a.rank[g.seg(xs[1 - EX[i]], ys[1 - EY[i]], zs[1 - EZ[i]])];
     int ids[19];
     ids[0] = 0;
+    static_assert(EY[1] == 0 && EZ[1] == 0 && EX[1] == 1 && EY[2] == 0 && EZ[2] == 0 && EX[2] == -1,
+                  "directions 1, 2 are +x, -x");
+    ids[1] = cm == pack_xyz(x - 1, y, z) && !gm ? (int)(n - 1) : -1;
+    ids[2] = cp == pack_xyz(x + 1, y, z) && !gp ? (int)(n + 1) : -1;
 #pragma unroll
-    for (int i = 1; i < 19; i++) {
-        ids[i] = rank_lookup(rw[i], xs[1 - EX[i]] & (kSeg - 1));
+    for (int i = 3; i < 19; i++) ids[i] = rank_lookup(rw[i], xs[1 - EX[i]] & (kSeg - 1));
+#pragma unroll
+    for (int i = 1; i < 19; i++)
         if ((EX[i] == 1 && gm) || (EX[i] == -1 && gp)) ids[i] = -2;
-    }
     const float om = a.omega[n];
     const Shift sh = a.shift[x + 1];
     // element offsets popq(q, i, node): 32-bit while q * stride fits, 64-bit beyond

@@ -58,19 +58,21 @@ def solve_pair(pore, diam, cfg, tol, u_init=None, c_init=None, n_fluid=None, ste
     return fr, kr, (t1 - t0, time.perf_counter() - t1)
 
 
-def knudsen_warm_or_rest(pore, diam, c_init, warm_max_steps=None, **kw):
+def knudsen_warm_or_rest(pore, diam, c_init, warm_max_steps=None, fallback=True, **kw):
     """Knudsen solve started from the network's C, with the solve from rest as the
     fallback.  The warm solve is kept only when it meets the solve's own stop rule (the
     residual and, with steady_tol, the equal flux through every link plane) within
     warm_max_steps steps (default: kw's max_steps); when it does not, or when it diverges
-    (a non-finite prediction), the solve runs again from rest with kw unchanged.
-    Returns (Solve, warm_used)."""
+    (a non-finite prediction), the solve runs again from rest with kw unchanged.  With
+    fallback=False (the caller knows the solve from rest does not converge within kw's
+    max_steps either) a warm solve that does not converge is kept; divergence still
+    falls back.  Returns (Solve, warm_used)."""
     warm_kw = dict(kw)
     if warm_max_steps is not None:
         warm_kw["max_steps"] = int(warm_max_steps)
     try:
         r = lbm.lbm_knudsen_solve(pore, diam, c_init=c_init, **warm_kw)
-        if r["converged"]:
+        if r["converged"] or not fallback:
             return r, True
     except lbm.LbmError as e:
         if e.status != lbm.LBM_E_DIVERGED:
@@ -180,7 +182,8 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
     """Solves each held-out geometry from rest and from the network's fields (one after
     the other, so the wall times compare) to residual tol and the steady-state tests
     `steady` (see solve_pair); the warm-started solves fall back to the solve from rest
-    when they do not converge.  Without flow_warm the flow starts from rest in both forms,
+    when they do not converge (when that solve converged: otherwise the rerun would
+    repeat it).  Without flow_warm the flow starts from rest in both forms,
     one computation counted in both.  A geometry with no pore component joining x = 0 to
     x = nx - 1 (Section 4.1's connectivity) carries no flux in either solve: k = D_eff = 0
     at steady state, so it is recorded without solving (no_path).  Returns one record per
@@ -220,7 +223,7 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
             pore, diam, c0.contiguous(), tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
             voxel_nm=cfg["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"], T=kp["T"],
             max_steps=kp["max_steps"], check_every=kp["check_every"], tol=tol, n_fluid=nf,
-            steady_tol=steady[1])
+            steady_tol=steady[1], fallback=bool(p_k["converged"]))
         torch.cuda.current_stream().synchronize()
         w_tk = time.perf_counter() - t0
         row = dict(seed=seed, porosity=rs["porosity"], n_fluid=nf,
@@ -230,7 +233,8 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
                               bool(w_f["converged"]), bool(w_k["converged"])],
                    warm_used=bool(used),
                    k_plain=p_f["k_lattice"], k_warm=w_f["k_lattice"],
-                   deff_plain=p_k["Deff_lattice"], deff_warm=w_k["Deff_lattice"])
+                   deff_plain=p_k["Deff_lattice"], deff_warm=w_k["Deff_lattice"],
+                   deff_planes_plain=p_k["Deff_planes"], deff_planes_warm=w_k["Deff_planes"])
         rows.append(row)
         log(f"held-out seed {seed}: steps flow {row['plain_steps'][0]} -> {row['warm_steps'][0]}, "
             f"knudsen {row['plain_steps'][1]} -> {row['warm_steps'][1]}; time "
@@ -241,9 +245,9 @@ def evaluate(net, seeds, cfg=W.WARMSTART, tol=1e-7, log=print, flow_warm=False,
 def summary(rows):
     """Step and time ratios over the geometries that were solved (all: those with a path
     along x) and over those whose solves from rest both converged within their caps
-    (converged: the time-to-converged comparison; on the others the warm-started Knudsen
-    solve that reaches its cap is run again from rest, doubling its time); agreement of k
-    and D_eff where both forms converged; the count of geometries without a path."""
+    (converged: the time-to-converged comparison); agreement of k and of D_eff (at the
+    outlet and the link-plane mean) where both forms converged; the count of geometries
+    without a path."""
     no_path = [r for r in rows if r.get("no_path")]
     rows = [r for r in rows if not r.get("no_path")]
 
@@ -265,9 +269,14 @@ def summary(rows):
     dk = np.array([abs(r["k_warm"] / r["k_plain"] - 1) for r in both_k]) if both_k else np.zeros(1)
     dd = np.array([abs(r["deff_warm"] / r["deff_plain"] - 1) for r in both_d if r["deff_plain"] > 0]) \
         if both_d else np.zeros(1)
+    dp = np.array([abs(r["deff_planes_warm"] / r["deff_planes_plain"] - 1) for r in both_d
+                   if r.get("deff_planes_plain", 0) > 0])
+    dp = dp if dp.size else np.zeros(1)
     return dict(all=part(rows), converged=part(conv), no_path=len(no_path),
                 k_rel_diff_median=float(np.median(dk)), k_rel_diff_max=float(dk.max()),
                 deff_rel_diff_median=float(np.median(dd)), deff_rel_diff_max=float(dd.max()),
+                deff_planes_rel_diff_median=float(np.median(dp)),
+                deff_planes_rel_diff_max=float(dp.max()),
                 knudsen_converged=[sum(r["converged"][1] for r in rows),
                                    sum(r["converged"][3] for r in rows)],
                 warm_used=sum(bool(r.get("warm_used", True)) for r in rows))
