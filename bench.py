@@ -464,6 +464,41 @@ def copy_ceiling(lbm, nbytes=1 << 30, reps=5):
     return round(best, 1)
 
 
+def copy_sizes(lbm, sizes_mb=(8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 2048), reps=50):
+    """Copy rate of the library's copy kernel against the working-set size: `reps` copies
+    of each size captured in one HIP graph, replayed 4 times, timed with HIP events
+    (read + write bytes per second).  Sizes up to 256 MB each way fit in the Infinity
+    Cache."""
+    import torch
+    out = {}
+    for mb in sizes_mb:
+        n = mb << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        lbm.lbm_copy_probe(dst, src)
+        torch.cuda.synchronize()
+        k = reps if mb <= 256 else 10
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(k):
+                lbm.lbm_copy_probe(dst, src)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(4):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / (4 * k)
+        assert torch.equal(dst, src)
+        out[mb] = {"us": round(us, 2), "gbs": round(2 * n / (us * 1e-6) / 1e9, 1)}
+        log("copy", mb, "MB each way", out[mb])
+        del src, dst, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def flow_sizes(lbm, edges=(256, 320, 384, 448, 512), steps=30):
     """Time per fluid-node update of the binary32 flow sweep against lattice size
     (reconstructions drawn like the 512^3 workload), best of 2."""
@@ -555,9 +590,13 @@ def main():
                     help="only the learned warm start on COUNT held-out geometries")
     ap.add_argument("--warm-eval-start", type=int, default=0, metavar="INDEX",
                     help="first held-out geometry of --only-warm-eval")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only the batch workload's fixed-step throughput (--batch-steps)")
     ap.add_argument("--only-batch-converge", type=int, default=0, metavar="COUNT",
                     help="only the time-to-converged leg of the batch workload")
     ap.add_argument("--only-flow-sizes", action="store_true")
+    ap.add_argument("--only-copy-sizes", action="store_true",
+                    help="only the copy kernel's rate against the working-set size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path's multi-GPU "
@@ -572,6 +611,13 @@ def main():
     lbm.load()
     if args.only_flow_sizes:
         print(json.dumps({"flow_sizes": flow_sizes(lbm)}), flush=True)
+        return
+    if args.only_copy_sizes:
+        print(json.dumps({"copy_sizes": copy_sizes(lbm)}), flush=True)
+        return
+    if args.only_batch:
+        print(json.dumps({"batch": batch_throughput(lbm, W, args.batch_steps, args.batch_steps)}),
+              flush=True)
         return
     if args.only_warm_eval:
         i0 = args.warm_eval_start
