@@ -130,7 +130,8 @@ def sweep_ms(lbm, workspace, steps):
 
 
 def sweeps_512(lbm, W, pore, nf, steps):
-    """Per-launch times of the binary16, MRT and TRT sweeps on the 512^3 workload."""
+    """Per-launch times of the binary16, MRT and TRT flow sweeps and of the D3Q7 sweep on
+    the 512^3 workload."""
     import torch
     w = W.LARGE_512
     out = {}
@@ -144,6 +145,29 @@ def sweeps_512(lbm, W, pore, nf, steps):
                      "achieved_gbs": round(nf * bpu / (ms * 1e-3) / 1e9, 1)}
         del r
         torch.cuda.empty_cache()
+    # the D3Q7 mass-transport sweep streaming the same lattice from HBM (tau_g from the
+    # 13-direction chord map, the methane settings); HIP events around plain sweeps
+    kp = W.METHANE_128["knudsen"]
+    diam = lbm.lbm_pore_diameter(pore, lbm.LBM_PSD_CHORD13)
+    r = lbm.lbm_knudsen_solve(pore, diam, tau_ref=kp["tau_ref"], d_ref_nm=kp["d_ref_nm"],
+                              voxel_nm=w["voxel_nm"], c_in=kp["c_in"], c_out=kp["c_out"],
+                              T=kp["T"], fixed_steps=20, check_every=kp["check_every"],
+                              n_fluid=nf)
+    s = torch.cuda.current_stream()
+    lbm.lbm_knudsen_step(r.workspace, 10)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    lbm.lbm_knudsen_step(r.workspace, steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out["d3q7"] = {"kernel": "k_sweep7<false, true, unsigned int>", "ms_per_launch": round(ms, 5),
+                   "mlups": round(nf / (ms * 1e3), 1), "bytes_per_update": BYTES_D3Q7,
+                   "achieved_gbs": round(nf * BYTES_D3Q7 / (ms * 1e-3) / 1e9, 1),
+                   "bound": "hbm"}
+    del r, diam
+    torch.cuda.empty_cache()
     return out
 
 

@@ -104,6 +104,11 @@ def test_warm_start_fallback(geom):
                                       warm_max_steps=plain["steps"] // 4, **kw)
     assert not used
     assert r["steps"] == plain["steps"] and r["Deff_lattice"] == plain["Deff_lattice"]
+    # without the fallback (a caller whose solve from rest did not converge either) the
+    # unconverged warm solve is returned as it stands
+    r, used = WS.knudsen_warm_or_rest(pore, diam, bad.float().contiguous(),
+                                      warm_max_steps=plain["steps"] // 4, fallback=False, **kw)
+    assert used and not r["converged"] and r["steps"] <= plain["steps"] // 4
     # a non-finite prediction diverges at its first check: the same fallback
     nan = torch.full(pore.shape, float("nan"), dtype=torch.float32, device="cuda")
     r, used = WS.knudsen_warm_or_rest(pore, diam, nan, **kw)
