@@ -291,7 +291,7 @@ def pipelines_128(lbm, W):
         "k_rel_diff": abs(q["flow"]["k_lattice"] / fr["k_lattice"] - 1),
         "k_sweep7": {"kernel": SWEEP7, "ms_per_launch": per7,
                      "achieved_gbs": round(kr["n_fluid"] * BYTES_D3Q7 / (per7 * 1e-3) / 1e9, 1),
-                     "bound": "cache", "traffic": traffic_gb(SWEEP7, w["name"]),
+                     "bound": "cache", "traffic": traffic_gb(SWEEP7, W.METHANE_128["name"]),
                      "traffic_unit": "GB per launch"},
     }
 
