@@ -130,8 +130,8 @@ def sweep_ms(lbm, workspace, steps):
 
 
 def sweeps_512(lbm, W, pore, nf, steps):
-    """Per-launch times of the binary16, MRT and TRT flow sweeps and of the D3Q7 sweep on
-    the 512^3 workload."""
+    """Per-launch times of the binary16, MRT and TRT flow sweeps, of a step with pressure
+    boundaries, and of the D3Q7 sweep on the 512^3 workload."""
     import torch
     w = W.LARGE_512
     out = {}
@@ -145,6 +145,19 @@ def sweeps_512(lbm, W, pore, nf, steps):
                      "achieved_gbs": round(nf * bpu / (ms * 1e-3) / 1e9, 1)}
         del r
         torch.cuda.empty_cache()
+    # pressure boundaries in x (Section 3.3) instead of the body force: per step, the
+    # ghost-plane kernel and the sweep with open x faces
+    fp = w["flow"]
+    r = lbm.lbm_flow_solve(pore, tau=fp["tau"], force=(0.0, 0.0, 0.0), pressure=(1.0001, 0.9999),
+                           check_every=fp["check_every"], voxel_nm=w["voxel_nm"],
+                           fixed_steps=20, n_fluid=nf)
+    ms = sweep_ms(lbm, r.workspace, steps)
+    out["pressure"] = {"ms_per_step": round(ms, 5), "mlups": round(nf / (ms * 1e3), 1),
+                       "bytes_per_update": BYTES_D3Q19,
+                       "achieved_gbs": round(nf * BYTES_D3Q19 / (ms * 1e-3) / 1e9, 1),
+                       "note": "ghost planes + sweep with open x faces, per step"}
+    del r
+    torch.cuda.empty_cache()
     # the D3Q7 mass-transport sweep streaming the same lattice from HBM (tau_g from the
     # 13-direction chord map, the methane settings); HIP events around plain sweeps
     kp = W.METHANE_128["knudsen"]
