@@ -343,11 +343,12 @@ __device__ inline void trt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
 }
 
 // The update of fluid node n at (x, y, z) whose 18 pull sources are resolved: ids[i] is
-// the node at x - e_i, or -1 when that voxel is solid (half-way bounce-back); rs[i] the
-// reference density at the source (rs[0]: at the node), binary32 and binary16 storage.
+// the node at x - e_i, -1 when that voxel is solid (half-way bounce-back), -2 a ghost
+// node beyond an x face (pressure boundaries); rs[i] the reference density at the source
+// (rs[0]: at the node), binary32 and binary16 storage.
 template <class P, bool CHECK, bool NT, int COLL, bool OPEN, class Off>
 __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
-                              const int (&ids)[19], const int (&gidx)[19], const float (&rs)[19],
+                              const int (&ids)[19], const float (&rs)[19],
                               int64_t half_own, double (&acc)[kFlowSums]) {
     using T = typename P::T;
     using R = typename P::R;
@@ -368,11 +369,23 @@ __device__ inline void node19(const Sweep19 &a, int64_t n, int x, int y, int z,
 #pragma unroll
     for (int i = 0; i < 19; i++) f[i] = from_store<P>(src[off[i]], a.inv_scale);
     if constexpr (OPEN) {
-        // sources beyond an x face: the ghost planes of the pressure boundaries (-2)
-        const T *__restrict__ gh = static_cast<const T *>(a.ghost);
+        // sources beyond an x face: the ghost planes of the pressure boundaries (-2), at
+        // [side][slot][z_s ny + y_s] with (y_s, z_s) the source's row (periodic in y, z);
+        // only the boundary nodes take this branch, so the indices are formed here
+        LBM_GHOST_TABLES
+        if (x == 0 || x == a.g.nx - 1) {
+            const T *__restrict__ gh = static_cast<const T *>(a.ghost);
+            const int ny = a.g.ny, nz = a.g.nz;
 #pragma unroll
-        for (int i = 1; i < 19; i++)
-            if (EX[i] != 0 && ids[i] == -2) f[i] = from_store<P>(gh[gidx[i]], a.inv_scale);
+            for (int i = 1; i < 19; i++) {
+                if (EX[i] == 0 || ids[i] != -2) continue;
+                const int side = EX[i] == 1 ? 0 : 1;
+                int ys = y - EY[i], zs = z - EZ[i];
+                ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+                zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+                f[i] = from_store<P>(gh[((side * 5 + GSLOT[i]) * nz + zs) * ny + ys], a.inv_scale);
+            }
+        }
     }
     constexpr bool kRef = !std::is_same<T, double>::value;
     if constexpr (kRef) {
@@ -503,7 +516,7 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
     // populations as another
     constexpr bool kRef = !std::is_same<P, StoreF64>::value;
     float rs[19];
-    int ids[19], gidx[19];
+    int ids[19];
     const int64_t half_own = half_index((int64_t)wx[1] + wy[1] + wz[1], x);
     if constexpr (kRef) {
         FlowHalf rh[19];
@@ -532,16 +545,13 @@ __device__ inline void sweep19_node(const Sweep19 &a, int64_t n, double (&acc)[k
     ids[0] = 0;
 #pragma unroll
     for (int i = 1; i < 19; i++) {
-        gidx[i] = 0;
         if (OPEN && ((EX[i] == 1 && x == 0) || (EX[i] == -1 && x == g.nx - 1))) {
             // the source is a ghost node; its boundary node (looked up at this x) decides:
             // fluid -> the ghost's population, solid -> bounce back
             ids[i] = ids[i] >= 0 ? -2 : -1;
-            const int side = EX[i] == 1 ? 0 : 1;
-            gidx[i] = ((side * 5 + GSLOT[i]) * g.nz + zs[1 - EZ[i]]) * g.ny + ys[1 - EY[i]];
         }
     }
-    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, gidx, rs, half_own, acc);
+    node19<P, CHECK, NT, COLL, OPEN, Off>(a, n, x, y, z, ids, rs, half_own, acc);
 }
 
 // One stream-collide step, one fluid node per thread.  CHECK also forms the FP64 partial
