@@ -536,6 +536,60 @@ def copy_sizes(lbm, sizes_mb=(8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 512, 204
     return out
 
 
+def network_timing(lbm, W, reps=10):
+    """The warm-start U-Net on one 96^3 geometry of the warm-start laws: inference
+    (forward) and training steps (forward, masked loss, every gradient, Adam), HIP events
+    on the current stream, mean over `reps` after one untimed pass each.  FLOP: 2 x 27 x
+    cin x cout per voxel and 3x3x3 convolution, three such products per training step
+    (forward, input gradient, weight gradient)."""
+    import torch
+    from paper_1410_1921_amd import warmstart as WS
+    from paper_1410_1921_amd.unet import UNet
+    net = WS.load_network()
+    edge = W.WARMSTART["edge"]
+    pore, diam, rs = WS.geometry(W.warmstart_params(6000, edge))
+    shape = tuple(pore.shape)
+    x0 = WS.network_input(pore, diam)
+    fwd_flop = 0
+    for name, ci, co in net.layers:
+        level = net._level(name)
+        fwd_flop += 2 * 27 * ci * co * (edge >> level) ** 3
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_inf = timed(lambda: net.forward(shape, x0))
+    trainee = UNet(n_out=WS.N_OUT, seed=1)
+    target = torch.zeros((WS.N_OUT, pore.numel()), dtype=torch.float32, device="cuda")
+    mask = pore.reshape(-1).contiguous()
+    wt = torch.tensor(WS.LOSS_WT, dtype=torch.float32, device="cuda")
+
+    def step():
+        trainee.loss_and_grad(shape, x0, target, mask, wt, float(rs["n_pore"]))
+        trainee.adam(lr=1e-4)
+
+    ms_train = timed(step)
+    peak = 2500.0  # dense bf16 MFMA, TFLOP/s
+    out = {"edge": edge, "layers": len(net.layers), "forward_gflop": round(fwd_flop / 1e9, 2),
+           "inference_ms": round(ms_inf, 3),
+           "inference_tflops": round(fwd_flop / (ms_inf * 1e-3) / 1e12, 2),
+           "train_step_ms": round(ms_train, 3),
+           "train_tflops": round(3 * fwd_flop / (ms_train * 1e-3) / 1e12, 2),
+           "peak_tflops": peak}
+    out["train_frac"] = round(out["train_tflops"] / peak, 4)
+    log("network", out)
+    return out
+
+
 def flow_sizes(lbm, edges=(256, 320, 384, 448, 512), steps=30):
     """Time per fluid-node update of the binary32 flow sweep against lattice size
     (reconstructions drawn like the 512^3 workload), best of 2."""
@@ -632,6 +686,8 @@ def main():
     ap.add_argument("--only-batch-converge", type=int, default=0, metavar="COUNT",
                     help="only the time-to-converged leg of the batch workload")
     ap.add_argument("--only-flow-sizes", action="store_true")
+    ap.add_argument("--only-network", action="store_true",
+                    help="only the warm-start U-Net: inference and training-step timing")
     ap.add_argument("--only-copy-sizes", action="store_true",
                     help="only the copy kernel's rate against the working-set size")
     args = ap.parse_args()
@@ -648,6 +704,9 @@ def main():
     lbm.load()
     if args.only_flow_sizes:
         print(json.dumps({"flow_sizes": flow_sizes(lbm)}), flush=True)
+        return
+    if args.only_network:
+        print(json.dumps({"network": network_timing(lbm, W)}), flush=True)
         return
     if args.only_copy_sizes:
         print(json.dumps({"copy_sizes": copy_sizes(lbm)}), flush=True)
