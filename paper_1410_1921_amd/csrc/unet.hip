@@ -153,6 +153,96 @@ __global__ __launch_bounds__(64) void k_conv3d_wgrad(NnGrid g, const uint16_t *_
         for (int j = 0; j < 4; j++) part_b[ch * cout + cb * 16 + 4 * q + j] = accb[j];
 }
 
+// The same weight gradient on grids whose three sizes are multiples of 4, with its
+// operands staged in LDS.  The voxels go in bricks of 4 x 4 x 4 (x fastest inside a
+// brick); one matrix-core step takes K = 16 voxels, one z plane of a brick.  A wave owns
+// one chunk of bricks (blockIdx.x), one block of 16 output channels and one of 16 input
+// channels (blockIdx.y), and all 27 taps: per brick it copies the brick's gy (64 voxels x
+// 16 channels) and the 6 x 6 x 6 halo of x around it (zero outside the grid) into LDS as
+// loaded, voxel-major, and reads each operand across voxels from there, so every tap
+// reuses one load of gy and one of x.  Partial sums as in k_conv3d_wgrad.
+__global__ __launch_bounds__(64) void k_conv3d_wgrad_bricks(NnGrid g, const uint16_t *__restrict__ x,
+                                                            int x_cs, int cin,
+                                                            const uint16_t *__restrict__ gy,
+                                                            int g_cs, int cout, int64_t bricks,
+                                                            float *__restrict__ part,
+                                                            float *__restrict__ part_b) {
+    __shared__ __align__(16) uint16_t sg[64 * 16];   // [brick voxel][channel]
+    __shared__ __align__(16) uint16_t sx[216 * 16];  // [halo voxel][channel]
+    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+    const int64_t ch = blockIdx.x;
+    const int ncb = cout / 16;
+    const int cb = (int)blockIdx.y % ncb, ib = (int)blockIdx.y / ncb;
+    const int bx = g.nx / 4, by = g.ny / 4, bz = g.nz / 4;
+    const int64_t nb = (int64_t)bx * by * bz;
+    const int64_t b_lo = ch * bricks;
+    const int64_t b_hi = b_lo + bricks < nb ? b_lo + bricks : nb;
+    const bool want_b = ib == 0;
+    f32x4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 accb = f32x4{0.f, 0.f, 0.f, 0.f};
+    const short one = (short)0x3f80;  // bfloat16 1.0
+    const bf16x4 ones = bf16x4{one, one, one, one};
+    for (int64_t b = b_lo; b < b_hi; b++) {
+        const int x0 = 4 * (int)(b % bx), y0 = 4 * (int)((b / bx) % by), z0 = 4 * (int)(b / ((int64_t)bx * by));
+        __syncthreads();  // the previous brick's operands are read
+        {
+            // lane k copies brick voxel k = x + 4 y + 16 z: 16 channels, 32 bytes
+            const int64_t v = ((int64_t)(z0 + (lane >> 4)) * g.ny + y0 + ((lane >> 2) & 3)) * g.nx +
+                              x0 + (lane & 3);
+            const uint4 *src = reinterpret_cast<const uint4 *>(gy + v * g_cs + cb * 16);
+            uint4 *dst = reinterpret_cast<uint4 *>(sg + lane * 16);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
+        for (int h = lane; h < 216; h += 64) {
+            const int sxv = x0 - 1 + h % 6, syv = y0 - 1 + (h / 6) % 6, szv = z0 - 1 + h / 36;
+            uint4 lo = uint4{0u, 0u, 0u, 0u}, hi = uint4{0u, 0u, 0u, 0u};
+            if (sxv >= 0 && sxv < g.nx && syv >= 0 && syv < g.ny && szv >= 0 && szv < g.nz) {
+                const int64_t v = ((int64_t)szv * g.ny + syv) * g.nx + sxv;
+                const uint4 *src = reinterpret_cast<const uint4 *>(x + v * x_cs + ib * 16);
+                lo = src[0];
+                hi = src[1];
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(sx + h * 16);
+            dst[0] = lo;
+            dst[1] = hi;
+        }
+        __syncthreads();
+        // A[m = output channel r][k = 4 q + j] = gy at brick voxel (j, q, s) of plane s
+        bf16x4 a[4];
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) a[sp][j] = (short)sg[(16 * sp + 4 * q + j) * 16 + r];
+        if (want_b)
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++) accb = mfma16(a[sp], ones, accb);
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++) {
+                // B[k = 4 q + j][n = input channel r] = x at that voxel + (dx, dy, dz)
+                bf16x4 bv;
+                const int h0 = (1 + dx) + 6 * (q + 1 + dy) + 36 * (sp + 1 + dz);
+#pragma unroll
+                for (int j = 0; j < 4; j++) bv[j] = (short)sx[(h0 + j) * 16 + r];
+                acc[t] = mfma16(a[sp], bv, acc[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 27; t++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            part[((ch * 27 + t) * cout + cb * 16 + 4 * q + j) * cin + ib * 16 + r] = acc[t][j];
+    if (want_b && r == 0)
+#pragma unroll
+        for (int j = 0; j < 4; j++) part_b[ch * cout + cb * 16 + 4 * q + j] = accb[j];
+}
+
 // out[i] (+)= sum_c part[c * count + i] over c = 0 .. nparts - 1 in order.
 __global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, int64_t nparts,
                                                    int64_t count, float *__restrict__ out,
@@ -427,9 +517,9 @@ static lbm_status check_grid(const int32_t n[3], NnGrid &g) {
 static bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 static int64_t wgrad_chunk(int64_t nvox) {
-    int64_t nch = nvox / 2048;
+    int64_t nch = nvox / 1024;
     if (nch < 1) nch = 1;
-    if (nch > 512) nch = 512;
+    if (nch > 1024) nch = 1024;
     int64_t chunk = (nvox + nch - 1) / nch;
     return (chunk + 15) / 16 * 16;
 }
@@ -494,9 +584,23 @@ extern "C" lbm_status lbm_nn_conv3d_wgrad(const int32_t n[3], const uint16_t *x,
     st = check_device();
     if (st != LBM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t chunk = wgrad_chunk(g.nvox), nch = (g.nvox + chunk - 1) / chunk;
+    const int64_t chunk = wgrad_chunk(g.nvox);
+    int64_t nch = (g.nvox + chunk - 1) / chunk;  // the workspace's partial rows
     float *part = static_cast<float *>(workspace);
     float *part_b = part + nch * 27 * (int64_t)cout * cin;
+    // the brick kernel copies 16-channel rows as 16-byte vectors: aligned rows only
+    const bool rows16 = x_cs % 8 == 0 && g_cs % 8 == 0 && reinterpret_cast<uintptr_t>(x) % 16 == 0 &&
+                        reinterpret_cast<uintptr_t>(gy) % 16 == 0;
+    if (g.nx % 4 == 0 && g.ny % 4 == 0 && g.nz % 4 == 0 && rows16) {
+        // bricks of 64 voxels, as many per chunk as the chunk has voxels (rounded up):
+        // at most nch chunks
+        const int64_t nb = g.nvox / 64, bricks = (chunk + 63) / 64;
+        const int64_t nbc = (nb + bricks - 1) / bricks;
+        k_conv3d_wgrad_bricks<<<dim3((unsigned)nbc, (unsigned)((cout / 16) * (cin / 16))), 64, 0, s>>>(
+            g, x, x_cs, cin, gy, g_cs, cout, bricks, part, part_b);
+        LBM_CHECK_LAUNCH();
+        nch = nbc;
+    } else {
     const dim3 grid((unsigned)nch, 27, (unsigned)(cout / 16));
     switch (cin) {
     case 16: k_conv3d_wgrad<1><<<grid, 64, 0, s>>>(g, x, x_cs, gy, g_cs, cout, chunk, part, part_b); break;
@@ -509,6 +613,7 @@ extern "C" lbm_status lbm_nn_conv3d_wgrad(const int32_t n[3], const uint16_t *x,
     default: set_error("lbm_nn_conv3d_wgrad: cin %d not supported", cin); return LBM_E_INVAL;
     }
     LBM_CHECK_LAUNCH();
+    }
     const int64_t count = (int64_t)27 * cout * cin;
     k_sum_parts<<<nblk(count), 256, 0, s>>>(part, nch, count, dw, accumulate);
     LBM_CHECK_LAUNCH();

@@ -94,17 +94,26 @@ def test_conv3d_input_gradient(shape, cin, cout):
     assert ok
 
 
-@pytest.mark.parametrize("shape,cin,cout", [((6, 8, 10), 16, 16), ((4, 6, 8), 96, 32),
-                                            ((2, 4, 6), 64, 128), ((8, 8, 8), 48, 16)])
-def test_conv3d_weight_gradient(shape, cin, cout):
+# grids with a size not divisible by 4 take the per-tap kernel; the others the brick
+# kernel (operands staged in LDS), also through strided channel views (x_off, g_off:
+# channel offsets of the views in wider tensors, as for the decoder's concatenations)
+@pytest.mark.parametrize("shape,cin,cout,x_off,g_off",
+                         [((6, 8, 10), 16, 16, 0, 0), ((4, 6, 8), 96, 32, 0, 0),
+                          ((2, 4, 6), 64, 128, 0, 0), ((8, 8, 8), 48, 16, 0, 0),
+                          ((8, 12, 16), 16, 16, 0, 0), ((4, 8, 12), 32, 64, 16, 0),
+                          ((12, 12, 12), 128, 128, 0, 0), ((4, 4, 4), 192, 64, 0, 32),
+                          ((8, 4, 12), 48, 16, 16, 16), ((4, 4, 8), 16, 16, 4, 0)])
+def test_conv3d_weight_gradient(shape, cin, cout, x_off, g_off):
     rng = np.random.default_rng(11 + cout)
     x = bf16(rng.standard_normal((cin,) + shape))
     g = bf16(rng.standard_normal((cout,) + shape))
-    say("conv wgrad", shape, cin, cout)
+    say("conv wgrad", shape, cin, cout, x_off, g_off)
     dw = torch.zeros(27 * cout * cin, dtype=torch.float32, device="cuda")
     db = torch.zeros(cout, dtype=torch.float32, device="cuda")
     ws = torch.empty(nn.lbm_nn_wgrad_workspace(shape, cin, cout), dtype=torch.uint8, device="cuda")
-    nn.lbm_nn_conv3d_wgrad(shape, View(to_dev_cl(x)), cin, View(to_dev_cl(g)), cout, dw, db, ws)
+    xd = View(to_dev_cl(x, cin + x_off, x_off), x_off, cin)
+    gd = View(to_dev_cl(g, cout + g_off, g_off), g_off, cout)
+    nn.lbm_nn_conv3d_wgrad(shape, xd, cin, gd, cout, dw, db, ws)
     _, gw, gb = N.conv3d_bwd(x, np.zeros((27, cout, cin)), g)
     gw_gpu = dw.cpu().numpy().astype(np.float64).reshape(27, cout, cin)
     # binary32 sums of bf16 products: ~1e-6 of the sum of |terms|
@@ -112,8 +121,7 @@ def test_conv3d_weight_gradient(shape, cin, cout):
     assert np.abs(gw_gpu - gw).max() <= tol, np.abs(gw_gpu - gw).max()
     assert np.abs(db.cpu().numpy() - gb).max() <= tol
     # accumulate adds
-    nn.lbm_nn_conv3d_wgrad(shape, View(to_dev_cl(x)), cin, View(to_dev_cl(g)), cout, dw, db, ws,
-                           accumulate=True)
+    nn.lbm_nn_conv3d_wgrad(shape, xd, cin, gd, cout, dw, db, ws, accumulate=True)
     assert np.abs(dw.cpu().numpy().astype(np.float64).reshape(27, cout, cin) - 2 * gw).max() <= 2 * tol
 
 
