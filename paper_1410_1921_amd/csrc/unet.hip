@@ -98,6 +98,71 @@ __global__ __launch_bounds__(256) void k_conv3d(NnGrid g, const uint16_t *__rest
     }
 }
 
+// The same convolution on grids whose three sizes are multiples of 4: one wave per brick
+// of 4 x 4 x 4 voxels (blockIdx.x, x fastest) and block of 16 output channels
+// (blockIdx.y), the brick's four z planes of 16 voxels as four output tiles that share
+// each weight load.  Per block of 16 input channels the wave copies the 6 x 6 x 6 halo of
+// x around its brick (zero outside the grid) into LDS as loaded, voxel-major, and reads
+// each tap's shifted operand from there.
+__global__ __launch_bounds__(64) void k_conv3d_bricks(NnGrid g, const uint16_t *__restrict__ x, int x_cs,
+                                                      int cin, const uint16_t *__restrict__ w,
+                                                      int cout, const float *__restrict__ bias,
+                                                      uint16_t *__restrict__ y, int y_cs, int relu,
+                                                      int flip) {
+    __shared__ __align__(16) uint16_t sx[216 * 16];  // [halo voxel][channel]
+    const int lane = threadIdx.x, r = lane & 15, q = lane >> 4;
+    const int bx = g.nx / 4, by = g.ny / 4;
+    const int64_t b = blockIdx.x;
+    const int nb = blockIdx.y;
+    const int x0 = 4 * (int)(b % bx), y0 = 4 * (int)((b / bx) % by), z0 = 4 * (int)(b / ((int64_t)bx * by));
+    f32x4 acc[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++) acc[sp] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < cin; kc += 16) {
+        __syncthreads();  // the previous channel block's operands are read
+        for (int h = lane; h < 216; h += 64) {
+            const int sxv = x0 - 1 + h % 6, syv = y0 - 1 + (h / 6) % 6, szv = z0 - 1 + h / 36;
+            uint4 lo = uint4{0u, 0u, 0u, 0u}, hi = uint4{0u, 0u, 0u, 0u};
+            if (sxv >= 0 && sxv < g.nx && syv >= 0 && syv < g.ny && szv >= 0 && szv < g.nz) {
+                const int64_t v = ((int64_t)szv * g.ny + syv) * g.nx + sxv;
+                const uint4 *src = reinterpret_cast<const uint4 *>(x + v * x_cs + kc);
+                lo = src[0];
+                hi = src[1];
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(sx + h * 16);
+            dst[0] = lo;
+            dst[1] = hi;
+        }
+        __syncthreads();
+        const uint16_t *wp = w + ((int64_t)nb * 16 + r) * cin + kc + 4 * q;
+        for (int t = 0; t < 27; t++) {
+            int dx, dy, dz;
+            tap_offset(t, flip, dx, dy, dz);
+            // B[k = 4 q .. 4 q + 3][n = r]: w[t][nb 16 + r][kc + 4 q ..]
+            const bf16x4 bw = *reinterpret_cast<const bf16x4 *>(wp + (int64_t)t * cout * cin);
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++) {
+                // A[m = r][k = 4 q ..]: plane voxel r = (r & 3, r >> 2) of plane sp, shifted
+                const int h = (1 + (r & 3) + dx) + 6 * (1 + (r >> 2) + dy) + 36 * (1 + sp + dz);
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(sx + h * 16 + 4 * q);
+                acc[sp] = mfma16(a, bw, acc[sp]);
+            }
+        }
+    }
+    // D[m = 4 q + j][n = r]: plane voxel (j, q) of plane sp, output channel nb 16 + r
+    const int c = nb * 16 + r;
+    const float bc = bias ? bias[c] : 0.f;
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            float v = acc[sp][j] + bc;
+            if (relu) v = v > 0.f ? v : 0.f;
+            const int64_t vox = ((int64_t)(z0 + sp) * g.ny + y0 + q) * g.nx + x0 + j;
+            y[vox * y_cs + c] = f2bf(v);
+        }
+}
+
 // Partial weight gradients over one chunk of voxels for tap t = blockIdx.y and output
 // block cb = blockIdx.z: part[chunk][t][co][ci] = sum_v g[v][co] x[v + d_t][ci] for
 // NBI blocks of 16 input channels; the centre tap also forms part_b[chunk][co] = sum_v
@@ -546,6 +611,18 @@ extern "C" lbm_status lbm_nn_conv3d(const int32_t n[3], const uint16_t *x, int32
     const unsigned grid = (unsigned)((g.nvox / 16 + 3) / 4);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int relu = (flags & LBM_NN_RELU) != 0, flip = (flags & LBM_NN_FLIP) != 0;
+    // bricks: grid sizes multiples of 4 and 16-byte input rows (the halo is copied as
+    // 16-byte vectors)
+    if (g.nx % 4 == 0 && g.ny % 4 == 0 && g.nz % 4 == 0 && x_cs % 8 == 0 &&
+        reinterpret_cast<uintptr_t>(x) % 16 == 0) {
+        LBM_REQUIRE(cout == 16 || cout == 32 || cout == 48 || cout == 64 || cout == 96 ||
+                        cout == 128 || cout == 192,
+                    LBM_E_INVAL, "lbm_nn_conv3d: cout %d not supported", cout);
+        k_conv3d_bricks<<<dim3((unsigned)(g.nvox / 64), (unsigned)(cout / 16)), 64, 0, s>>>(
+            g, x, x_cs, cin, w, cout, bias, y, y_cs, relu, flip);
+        LBM_CHECK_LAUNCH();
+        return LBM_OK;
+    }
     switch (cout) {
     case 16: k_conv3d<1><<<grid, 256, 0, s>>>(g, x, x_cs, cin, w, bias, y, y_cs, relu, flip); break;
     case 32: k_conv3d<2><<<grid, 256, 0, s>>>(g, x, x_cs, cin, w, bias, y, y_cs, relu, flip); break;

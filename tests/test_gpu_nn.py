@@ -54,9 +54,13 @@ def close(gpu, ref, rel=BF, floor=1e-3):
     return bool((err <= bound).all()), float(err.max()), float(np.abs(ref).max())
 
 
+# sizes not all divisible by 4 take the per-voxel-tile kernel, the others the brick
+# kernel (input halo staged in LDS)
 @pytest.mark.parametrize("shape,cin,cout", [((6, 8, 10), 16, 16), ((4, 6, 8), 32, 48),
                                             ((3, 4, 8), 192, 64), ((2, 4, 4), 64, 128),
-                                            ((5, 4, 4), 96, 32)])
+                                            ((5, 4, 4), 96, 32), ((8, 12, 16), 16, 16),
+                                            ((4, 8, 4), 32, 48), ((12, 12, 12), 128, 128),
+                                            ((4, 4, 8), 192, 64), ((8, 4, 4), 96, 32)])
 def test_conv3d_forward(shape, cin, cout):
     rng = np.random.default_rng(cin * 7 + cout)
     x = bf16(rng.standard_normal((cin,) + shape))
@@ -78,7 +82,8 @@ def test_conv3d_forward(shape, cin, cout):
 
 
 @pytest.mark.parametrize("shape,cin,cout", [((4, 6, 8), 48, 16), ((2, 4, 6), 192, 64),
-                                            ((4, 4, 4), 16, 32)])
+                                            ((4, 4, 4), 16, 32), ((8, 8, 12), 32, 16),
+                                            ((12, 12, 12), 64, 128)])
 def test_conv3d_input_gradient(shape, cin, cout):
     rng = np.random.default_rng(3 + cin)
     w = bf16(rng.standard_normal((27, cout, cin)) * 0.1)
