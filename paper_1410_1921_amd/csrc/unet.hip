@@ -308,15 +308,28 @@ __global__ __launch_bounds__(64) void k_conv3d_wgrad_bricks(NnGrid g, const uint
         for (int j = 0; j < 4; j++) part_b[ch * cout + cb * 16 + 4 * q + j] = accb[j];
 }
 
-// out[i] (+)= sum_c part[c * count + i] over c = 0 .. nparts - 1 in order.
+// out[i] (+)= sum_c part[c * count + i] over c = 0 .. nparts - 1 in a fixed order: 16
+// threads per output each sum one contiguous sixteenth of the partials in order, then
+// the sixteen sums are added in order (256 threads: 16 outputs x 16 groups).
 __global__ __launch_bounds__(256) void k_sum_parts(const float *__restrict__ part, int64_t nparts,
                                                    int64_t count, float *__restrict__ out,
                                                    int accumulate) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= count) return;
+    __shared__ float lds[16][17];
+    const int o = threadIdx.x & 15, gr = threadIdx.x >> 4;
+    const int64_t i = (int64_t)blockIdx.x * 16 + o;
+    const int64_t per = (nparts + 15) / 16;
+    const int64_t c0 = gr * per, c1 = c0 + per < nparts ? c0 + per : nparts;
     float s = 0.f;
-    for (int64_t c = 0; c < nparts; c++) s += part[c * count + i];
-    out[i] = accumulate ? out[i] + s : s;
+    if (i < count)
+        for (int64_t c = c0; c < c1; c++) s += part[c * count + i];
+    lds[gr][o] = s;
+    __syncthreads();
+    if (gr == 0 && i < count) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; k++) t += lds[k][o];
+        out[i] = accumulate ? out[i] + t : t;
+    }
 }
 
 // wt[t][ci][co] = w[t][co][ci] (bf16), the weights of the input-gradient convolution.
@@ -692,10 +705,10 @@ extern "C" lbm_status lbm_nn_conv3d_wgrad(const int32_t n[3], const uint16_t *x,
     LBM_CHECK_LAUNCH();
     }
     const int64_t count = (int64_t)27 * cout * cin;
-    k_sum_parts<<<nblk(count), 256, 0, s>>>(part, nch, count, dw, accumulate);
+    k_sum_parts<<<(unsigned)((count + 15) / 16), 256, 0, s>>>(part, nch, count, dw, accumulate);
     LBM_CHECK_LAUNCH();
     if (db) {
-        k_sum_parts<<<nblk(cout), 256, 0, s>>>(part_b, nch, cout, db, accumulate);
+        k_sum_parts<<<(unsigned)((cout + 15) / 16), 256, 0, s>>>(part_b, nch, cout, db, accumulate);
         LBM_CHECK_LAUNCH();
     }
     return LBM_OK;
