@@ -506,12 +506,14 @@ __global__ __launch_bounds__(256) void k_head_wgrad(int64_t nvox, const uint16_t
     }
 }
 
-// Fixed-order sums: the loss, gwh[o][c] and gbh[o].
+// Fixed-order sums: the loss (each thread one contiguous 1/256 of the block partials in
+// order, then the 256 sums in order), gwh[o][c] and gbh[o].
 __global__ __launch_bounds__(256) void k_head_final(const double *__restrict__ loss_part, int64_t nb,
                                                     const double *__restrict__ part, int64_t nch,
                                                     int no, double *__restrict__ loss,
                                                     float *__restrict__ gwh, float *__restrict__ gbh) {
     constexpr int NV = kHeadCin + 1;
+    __shared__ double lds[256];
     const int k = threadIdx.x;
     if (k < no * NV) {
         double s = 0.0;
@@ -520,10 +522,15 @@ __global__ __launch_bounds__(256) void k_head_final(const double *__restrict__ l
         if (c < kHeadCin) gwh[o * kHeadCin + c] = (float)s;
         else gbh[o] = (float)s;
     }
+    const int64_t per = (nb + 255) / 256, b0 = k * per, b1 = b0 + per < nb ? b0 + per : nb;
+    double s = 0.0;
+    for (int64_t b = b0; b < b1; b++) s += loss_part[b];
+    lds[k] = s;
+    __syncthreads();
     if (k == 0) {
-        double s = 0.0;
-        for (int64_t b = 0; b < nb; b++) s += loss_part[b];
-        *loss = s;
+        double t = 0.0;
+        for (int i = 0; i < 256; i++) t += lds[i];
+        *loss = t;
     }
 }
 
