@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 
 #include "../../include/lbm_nn.h"
 #include "lbm_internal.h"
@@ -343,82 +344,160 @@ __global__ __launch_bounds__(256) void k_transpose_w(const uint16_t *__restrict_
     wt[(t * cin + ci) * cout + co] = w[i];
 }
 
+// The elementwise layers take V consecutive channels per thread: V = 4 (one 8-byte
+// access) when the channel count, the strides and the pointers allow it, else V = 1.
+template <int V>
+__device__ inline void ldv(const uint16_t *p, uint16_t (&o)[V]) {
+    if constexpr (V == 4) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        o[0] = (uint16_t)(u.x & 0xffffu); o[1] = (uint16_t)(u.x >> 16);
+        o[2] = (uint16_t)(u.y & 0xffffu); o[3] = (uint16_t)(u.y >> 16);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++) o[k] = p[k];
+    }
+}
+template <int V>
+__device__ inline void stv(uint16_t *p, const uint16_t (&o)[V]) {
+    if constexpr (V == 4) {
+        uint2 u;
+        u.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+        u.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+        *reinterpret_cast<uint2 *>(p) = u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++) p[k] = o[k];
+    }
+}
+
 // 2x2x2 mean of the fine grid n (even sizes) onto the coarse grid.
+template <int V>
 __global__ __launch_bounds__(256) void k_pool2(NnGrid f, int c, const uint16_t *__restrict__ x,
                                                int x_cs, uint16_t *__restrict__ y, int y_cs,
                                                int accumulate) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int cx = f.nx / 2, cy = f.ny / 2, cz = f.nz / 2;
     const int64_t ncv = (int64_t)cx * cy * cz;
-    if (i >= ncv * c) return;
-    const int64_t v = i / c;
-    const int ch = (int)(i % c);
+    const int cv = c / V;
+    if (i >= ncv * cv) return;
+    const int64_t v = i / cv;
+    const int ch = (int)(i % cv) * V;
     const int X = (int)(v % cx), Y = (int)((v / cx) % cy), Z = (int)(v / ((int64_t)cx * cy));
-    float s = 0.f;
-    for (int k = 0; k < 8; k++) {
-        const int64_t fv = ((int64_t)(2 * Z + (k >> 2)) * f.ny + 2 * Y + ((k >> 1) & 1)) * f.nx + 2 * X + (k & 1);
-        s += bf2f(x[fv * x_cs + ch]);
+    float s[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) s[k] = 0.f;
+    for (int m = 0; m < 8; m++) {
+        const int64_t fv = ((int64_t)(2 * Z + (m >> 2)) * f.ny + 2 * Y + ((m >> 1) & 1)) * f.nx + 2 * X + (m & 1);
+        uint16_t e[V];
+        ldv<V>(x + fv * x_cs + ch, e);
+#pragma unroll
+        for (int k = 0; k < V; k++) s[k] += bf2f(e[k]);
     }
-    s *= 0.125f;
-    if (accumulate) s += bf2f(y[v * y_cs + ch]);
-    y[v * y_cs + ch] = f2bf(s);
+    uint16_t o[V];
+    if (accumulate) ldv<V>(y + v * y_cs + ch, o);
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        float t = s[k] * 0.125f;
+        if (accumulate) t += bf2f(o[k]);
+        o[k] = f2bf(t);
+    }
+    stv<V>(y + v * y_cs + ch, o);
 }
 
 // Adjoint of the mean pooling: each fine voxel gets 1/8 of its parent's gradient.
+template <int V>
 __global__ __launch_bounds__(256) void k_pool2_bwd(NnGrid f, int c, const uint16_t *__restrict__ gy,
                                                    int gy_cs, uint16_t *__restrict__ gx, int gx_cs,
                                                    int accumulate) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= f.nvox * c) return;
-    const int64_t v = i / c;
-    const int ch = (int)(i % c);
+    const int cv = c / V;
+    if (i >= f.nvox * cv) return;
+    const int64_t v = i / cv;
+    const int ch = (int)(i % cv) * V;
     const int x = (int)(v % f.nx), y = (int)((v / f.nx) % f.ny), z = (int)(v / ((int64_t)f.nx * f.ny));
     const int64_t pv = ((int64_t)(z / 2) * (f.ny / 2) + y / 2) * (f.nx / 2) + x / 2;
-    float s = 0.125f * bf2f(gy[pv * gy_cs + ch]);
-    if (accumulate) s += bf2f(gx[v * gx_cs + ch]);
-    gx[v * gx_cs + ch] = f2bf(s);
+    uint16_t e[V], o[V];
+    ldv<V>(gy + pv * gy_cs + ch, e);
+    if (accumulate) ldv<V>(gx + v * gx_cs + ch, o);
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        float t = 0.125f * bf2f(e[k]);
+        if (accumulate) t += bf2f(o[k]);
+        o[k] = f2bf(t);
+    }
+    stv<V>(gx + v * gx_cs + ch, o);
 }
 
 // Nearest upsampling from the coarse grid to the fine grid f (each fine voxel copies its
 // parent), and its adjoint (each parent sums its 8 children).
+template <int V>
 __global__ __launch_bounds__(256) void k_up2(NnGrid f, int c, const uint16_t *__restrict__ x,
                                              int x_cs, uint16_t *__restrict__ y, int y_cs) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= f.nvox * c) return;
-    const int64_t v = i / c;
-    const int ch = (int)(i % c);
+    const int cv = c / V;
+    if (i >= f.nvox * cv) return;
+    const int64_t v = i / cv;
+    const int ch = (int)(i % cv) * V;
     const int xx = (int)(v % f.nx), yy = (int)((v / f.nx) % f.ny), zz = (int)(v / ((int64_t)f.nx * f.ny));
     const int64_t pv = ((int64_t)(zz / 2) * (f.ny / 2) + yy / 2) * (f.nx / 2) + xx / 2;
-    y[v * y_cs + ch] = x[pv * x_cs + ch];
+    uint16_t e[V];
+    ldv<V>(x + pv * x_cs + ch, e);
+    stv<V>(y + v * y_cs + ch, e);
 }
 
+template <int V>
 __global__ __launch_bounds__(256) void k_up2_bwd(NnGrid f, int c, const uint16_t *__restrict__ gy,
                                                  int gy_cs, uint16_t *__restrict__ gx, int gx_cs) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int cx = f.nx / 2, cy = f.ny / 2, cz = f.nz / 2;
-    if (i >= (int64_t)cx * cy * cz * c) return;
-    const int64_t v = i / c;
-    const int ch = (int)(i % c);
+    const int cv = c / V;
+    if (i >= (int64_t)cx * cy * cz * cv) return;
+    const int64_t v = i / cv;
+    const int ch = (int)(i % cv) * V;
     const int X = (int)(v % cx), Y = (int)((v / cx) % cy), Z = (int)(v / ((int64_t)cx * cy));
-    float s = 0.f;
-    for (int k = 0; k < 8; k++) {
-        const int64_t fv = ((int64_t)(2 * Z + (k >> 2)) * f.ny + 2 * Y + ((k >> 1) & 1)) * f.nx + 2 * X + (k & 1);
-        s += bf2f(gy[fv * gy_cs + ch]);
+    float s[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) s[k] = 0.f;
+    for (int m = 0; m < 8; m++) {
+        const int64_t fv = ((int64_t)(2 * Z + (m >> 2)) * f.ny + 2 * Y + ((m >> 1) & 1)) * f.nx + 2 * X + (m & 1);
+        uint16_t e[V];
+        ldv<V>(gy + fv * gy_cs + ch, e);
+#pragma unroll
+        for (int k = 0; k < V; k++) s[k] += bf2f(e[k]);
     }
-    gx[v * gx_cs + ch] = f2bf(s);
+    uint16_t o[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) o[k] = f2bf(s[k]);
+    stv<V>(gx + v * gx_cs + ch, o);
 }
 
 // g = gy where the layer's output y > 0, else 0 (the ReLU gradient).
+template <int V>
 __global__ __launch_bounds__(256) void k_relu_bwd(int64_t nvox, int c, const uint16_t *__restrict__ y,
                                                   int y_cs, const uint16_t *__restrict__ gy,
                                                   int gy_cs, uint16_t *__restrict__ gout, int g_cs) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= nvox * c) return;
-    const int64_t v = i / c;
-    const int ch = (int)(i % c);
-    const uint16_t yv = y[v * y_cs + ch];
+    const int cv = c / V;
+    if (i >= nvox * cv) return;
+    const int64_t v = i / cv;
+    const int ch = (int)(i % cv) * V;
+    uint16_t yv[V], gv[V], o[V];
+    ldv<V>(y + v * y_cs + ch, yv);
+    ldv<V>(gy + v * gy_cs + ch, gv);
     // positive bfloat16: sign bit clear and not zero
-    gout[v * g_cs + ch] = (yv != 0 && !(yv & 0x8000u)) ? gy[v * gy_cs + ch] : (uint16_t)0;
+#pragma unroll
+    for (int k = 0; k < V; k++) o[k] = (yv[k] != 0 && !(yv[k] & 0x8000u)) ? gv[k] : (uint16_t)0;
+    stv<V>(gout + v * g_cs + ch, o);
+}
+
+// 8-byte channel groups for c channels at the given strides and pointers
+static bool vec4(int c, std::initializer_list<int> cs, std::initializer_list<const void *> ptrs) {
+    if (c % 4) return false;
+    for (int s : cs)
+        if (s % 4) return false;
+    for (const void *p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) % 8) return false;
+    return true;
 }
 
 constexpr int kHeadMaxOut = 8;
@@ -748,7 +827,11 @@ extern "C" lbm_status lbm_nn_pool2(const int32_t n_fine[3], int32_t c, const uin
     NnGrid g;
     lbm_status st = pool_args(n_fine, c, x, x_cs, y, y_cs, g);
     if (st != LBM_OK) return st;
-    k_pool2<<<nblk(g.nvox / 8 * c), 256, 0, static_cast<hipStream_t>(stream)>>>(g, c, x, x_cs, y, y_cs, accumulate);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (vec4(c, {x_cs, y_cs}, {x, y}))
+        k_pool2<4><<<nblk(g.nvox / 8 * (c / 4)), 256, 0, s>>>(g, c, x, x_cs, y, y_cs, accumulate);
+    else
+        k_pool2<1><<<nblk(g.nvox / 8 * c), 256, 0, s>>>(g, c, x, x_cs, y, y_cs, accumulate);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
@@ -759,7 +842,11 @@ extern "C" lbm_status lbm_nn_pool2_bwd(const int32_t n_fine[3], int32_t c, const
     NnGrid g;
     lbm_status st = pool_args(n_fine, c, gy, gy_cs, gx, gx_cs, g);
     if (st != LBM_OK) return st;
-    k_pool2_bwd<<<nblk(g.nvox * c), 256, 0, static_cast<hipStream_t>(stream)>>>(g, c, gy, gy_cs, gx, gx_cs, accumulate);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (vec4(c, {gy_cs, gx_cs}, {gy, gx}))
+        k_pool2_bwd<4><<<nblk(g.nvox * (c / 4)), 256, 0, s>>>(g, c, gy, gy_cs, gx, gx_cs, accumulate);
+    else
+        k_pool2_bwd<1><<<nblk(g.nvox * c), 256, 0, s>>>(g, c, gy, gy_cs, gx, gx_cs, accumulate);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
@@ -769,7 +856,11 @@ extern "C" lbm_status lbm_nn_up2(const int32_t n_fine[3], int32_t c, const uint1
     NnGrid g;
     lbm_status st = pool_args(n_fine, c, x, x_cs, y, y_cs, g);
     if (st != LBM_OK) return st;
-    k_up2<<<nblk(g.nvox * c), 256, 0, static_cast<hipStream_t>(stream)>>>(g, c, x, x_cs, y, y_cs);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (vec4(c, {x_cs, y_cs}, {x, y}))
+        k_up2<4><<<nblk(g.nvox * (c / 4)), 256, 0, s>>>(g, c, x, x_cs, y, y_cs);
+    else
+        k_up2<1><<<nblk(g.nvox * c), 256, 0, s>>>(g, c, x, x_cs, y, y_cs);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
@@ -779,7 +870,11 @@ extern "C" lbm_status lbm_nn_up2_bwd(const int32_t n_fine[3], int32_t c, const u
     NnGrid g;
     lbm_status st = pool_args(n_fine, c, gy, gy_cs, gx, gx_cs, g);
     if (st != LBM_OK) return st;
-    k_up2_bwd<<<nblk(g.nvox / 8 * c), 256, 0, static_cast<hipStream_t>(stream)>>>(g, c, gy, gy_cs, gx, gx_cs);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (vec4(c, {gy_cs, gx_cs}, {gy, gx}))
+        k_up2_bwd<4><<<nblk(g.nvox / 8 * (c / 4)), 256, 0, s>>>(g, c, gy, gy_cs, gx, gx_cs);
+    else
+        k_up2_bwd<1><<<nblk(g.nvox / 8 * c), 256, 0, s>>>(g, c, gy, gy_cs, gx, gx_cs);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }
@@ -792,7 +887,11 @@ extern "C" lbm_status lbm_nn_relu_bwd(int64_t nvox, int32_t c, const uint16_t *y
     lbm_status st = check_device();
     if (st != LBM_OK) return st;
     if (nvox == 0) return LBM_OK;
-    k_relu_bwd<<<nblk(nvox * c), 256, 0, static_cast<hipStream_t>(stream)>>>(nvox, c, y, y_cs, gy, gy_cs, g, g_cs);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (vec4(c, {y_cs, gy_cs, g_cs}, {y, gy, g}))
+        k_relu_bwd<4><<<nblk(nvox * (c / 4)), 256, 0, s>>>(nvox, c, y, y_cs, gy, gy_cs, g, g_cs);
+    else
+        k_relu_bwd<1><<<nblk(nvox * c), 256, 0, s>>>(nvox, c, y, y_cs, gy, gy_cs, g, g_cs);
     LBM_CHECK_LAUNCH();
     return LBM_OK;
 }

@@ -130,10 +130,11 @@ def test_conv3d_weight_gradient(shape, cin, cout, x_off, g_off):
     assert np.abs(dw.cpu().numpy().astype(np.float64).reshape(27, cout, cin) - 2 * gw).max() <= 2 * tol
 
 
-def test_pool_and_upsample():
+# c = 16: four channels per thread; c = 6: one (the channel count is not a multiple of 4)
+@pytest.mark.parametrize("c", [16, 6])
+def test_pool_and_upsample(c):
     rng = np.random.default_rng(7)
     shape = (4, 6, 8)
-    c = 16
     x = bf16(rng.standard_normal((c,) + shape))
     xc = bf16(rng.standard_normal((c, 2, 3, 4)))
     y = torch.zeros((2 * 3 * 4, c), dtype=torch.bfloat16, device="cuda")
@@ -150,6 +151,20 @@ def test_pool_and_upsample():
     gu = torch.zeros((2 * 3 * 4, c), dtype=torch.bfloat16, device="cuda")
     nn.lbm_nn_up2_bwd(shape, c, View(to_dev_cl(x)), View(gu))
     assert close(from_dev_cl(gu, (2, 3, 4)), N.upsample2_bwd(x))[0]
+
+
+@pytest.mark.parametrize("c", [16, 6])
+def test_relu_gradient(c):
+    # g = gy where y > 0 (exactly: a selection of bf16 values), through strided views
+    rng = np.random.default_rng(5)
+    shape = (4, 6, 8)
+    y = bf16(rng.standard_normal((c,) + shape))
+    y[:, 0, 0, :2] = 0.0  # zeros pass nothing
+    gy = bf16(rng.standard_normal((c,) + shape))
+    g = torch.zeros((y[0].size, c + 8), dtype=torch.bfloat16, device="cuda")
+    nn.lbm_nn_relu_bwd(c, View(to_dev_cl(y)), View(to_dev_cl(gy)), View(g, 8, c))
+    assert np.array_equal(from_dev_cl(g, shape, 8, c), np.where(y > 0, gy, 0.0))
+    assert (g[:, :8].float() == 0).all()
 
 
 def test_head_loss_and_gradients():
