@@ -468,11 +468,12 @@ def c3_converge(lbm, W, pore, nf):
     return out
 
 
-def warm_eval(lbm, W, seeds):
+def warm_eval(lbm, W, seeds, weights=None):
     """The learned warm start on held-out geometries (the warm-start workload's laws at
-    96^3): plain against warm-started solves, one after the other, to steady state."""
+    96^3): plain against warm-started solves, one after the other, to steady state
+    (weights: another weights file than the shipped one)."""
     from paper_1410_1921_amd import warmstart as WS
-    net = WS.load_network()
+    net = WS.load_network(weights)
     # flows without a path along x never meet the stop rule (u decays to 0): capped
     cfg = dict(W.WARMSTART, flow=dict(W.WARMSTART["flow"], max_steps=60_000))
     rows = WS.evaluate(net, seeds, cfg, tol=TOL, log=lambda *a: log(*a),
@@ -681,6 +682,8 @@ def main():
                     help="only the learned warm start on COUNT held-out geometries")
     ap.add_argument("--warm-eval-start", type=int, default=0, metavar="INDEX",
                     help="first held-out geometry of --only-warm-eval")
+    ap.add_argument("--warm-eval-weights", default=None, metavar="NPZ",
+                    help="network weights for --only-warm-eval (default: the shipped ones)")
     ap.add_argument("--only-batch", action="store_true",
                     help="only the batch workload's fixed-step throughput (--batch-steps)")
     ap.add_argument("--only-batch-converge", type=int, default=0, metavar="COUNT",
@@ -718,7 +721,8 @@ def main():
     if args.only_warm_eval:
         i0 = args.warm_eval_start
         seeds = list(W.WARMSTART["test_seeds"])[i0:i0 + args.only_warm_eval]
-        print(json.dumps({"warm_eval": warm_eval(lbm, W, seeds)}), flush=True)
+        print(json.dumps({"warm_eval": warm_eval(lbm, W, seeds, args.warm_eval_weights)}),
+              flush=True)
         return
     if args.only_batch_converge:
         from paper_1410_1921_amd import warmstart as WS

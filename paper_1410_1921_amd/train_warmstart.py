@@ -24,6 +24,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0, help="weight initialisation")
     ap.add_argument("--out", default=None, help="weights file (.npz)")
     ap.add_argument("--load", default=None, help="start from these weights, skip training")
+    ap.add_argument("--finetune", action="store_true",
+                    help="train further from the --load weights instead of skipping training")
+    ap.add_argument("--first-seed", type=int, default=0, help="index of the first training seed")
+    ap.add_argument("--steady", action="store_true",
+                    help="targets solved to the steady-state rule (residual 1e-7, flow distance "
+                         "1e-3, Knudsen flux spread 5e-4); geometries that miss it are left out")
+    ap.add_argument("--kn-cap", type=int, default=None, help="Knudsen step cap of the targets")
     ap.add_argument("--eval", type=int, default=0, help="held-out geometries (seeds 6000+)")
     ap.add_argument("--eval-json", default=None)
     args = ap.parse_args()
@@ -40,13 +47,19 @@ def main():
     cfg = W.WARMSTART
     report = {"config": {"edge": cfg["edge"], "train": args.train, "epochs": args.epochs,
                          "lr": args.lr, "tol_targets": args.tol}}
-    if args.load:
+    if args.load and not args.finetune:
         net = UNet.load(args.load)
     else:
-        net = UNet(n_out=WS.N_OUT, seed=args.seed)
-        seeds = list(cfg["train_seeds"])[:args.train]
+        net = UNet.load(args.load) if args.load else UNet(n_out=WS.N_OUT, seed=args.seed)
+        seeds = list(cfg["train_seeds"])[args.first_seed:args.first_seed + args.train]
         t0 = time.perf_counter()
-        data = WS.make_dataset(seeds, cfg, tol=args.tol, workers=args.workers, log=log)
+        if args.steady:
+            data = WS.make_dataset(seeds, cfg, tol=1e-7, workers=args.workers, log=log,
+                                   steady=(1e-3, 5e-4), kn_cap=args.kn_cap)
+        else:
+            data = WS.make_dataset(seeds, cfg, tol=args.tol, workers=args.workers, log=log,
+                                   kn_cap=args.kn_cap)
+        report["samples"] = len(data)
         report["data_s"] = time.perf_counter() - t0
         t0 = time.perf_counter()
         report["loss"] = WS.train(net, data, args.epochs, lr=args.lr, log=log)

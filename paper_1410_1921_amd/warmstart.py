@@ -127,12 +127,18 @@ def predict(net, pore, diam):
     return fields[:4].reshape((4,) + shape), fields[4].reshape(shape)
 
 
-def make_dataset(seeds, cfg=W.WARMSTART, tol=1e-6, workers=8, flow_cap=60_000, log=print):
+def make_dataset(seeds, cfg=W.WARMSTART, tol=1e-6, workers=8, flow_cap=60_000, log=print,
+                 steady=(0.0, 0.0), kn_cap=None):
     """Solves each seed's geometry from rest (concurrently, one stream per worker) and
     keeps the network input and target on the device.  The flow solve stops at flow_cap
     steps: geometries without a path along x have u = 0 at steady state, where the
-    relative residual measures the decay rate of the transient and never reaches tol."""
+    relative residual measures the decay rate of the transient and never reaches tol.
+    With a steady-state test (steady, as in solve_pair) the Knudsen solve stops at kn_cap
+    steps (default: the configuration's), and a geometry whose Knudsen solve does not
+    meet the test is left out (its target would not be the steady state)."""
     cfg = dict(cfg, flow=dict(cfg["flow"], max_steps=min(cfg["flow"]["max_steps"], flow_cap)))
+    if kn_cap is not None:
+        cfg["knudsen"] = dict(cfg["knudsen"], max_steps=int(kn_cap))
     data = [None] * len(seeds)
     t_start = time.perf_counter()
 
@@ -141,7 +147,13 @@ def make_dataset(seeds, cfg=W.WARMSTART, tol=1e-6, workers=8, flow_cap=60_000, l
         with torch.cuda.stream(s):
             rp = W.warmstart_params(seeds[k], cfg["edge"])
             pore, diam, rs = geometry(rp)
-            fr, kr, (tf, tk) = solve_pair(pore, diam, cfg, tol, n_fluid=rs["n_pore"])
+            fr, kr, (tf, tk) = solve_pair(pore, diam, cfg, tol, n_fluid=rs["n_pore"],
+                                          steady=steady)
+            if steady[1] > 0 and not kr["converged"]:
+                s.synchronize()
+                log(f"sample {k + 1}/{len(seeds)} seed {seeds[k]}: Knudsen not steady in "
+                    f"{kr['steps']} steps, left out")
+                return
             item = dict(seed=seeds[k], shape=tuple(pore.shape), x0=network_input(pore, diam),
                         tgt=targets(fr, kr, pore), mask=pore.reshape(-1).clone(),
                         n_mask=float(rs["n_pore"]), steps=(fr["steps"], kr["steps"]),
@@ -154,7 +166,7 @@ def make_dataset(seeds, cfg=W.WARMSTART, tol=1e-6, workers=8, flow_cap=60_000, l
     with cf.ThreadPoolExecutor(max_workers=workers) as ex:
         for f in [ex.submit(work, k) for k in range(len(seeds))]:
             f.result()
-    return data
+    return [d for d in data if d is not None]
 
 
 def train(net, data, epochs, lr=1e-3, log=print, seed=0):
