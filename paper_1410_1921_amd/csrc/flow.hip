@@ -263,21 +263,52 @@ constexpr int mrt_class(int k) {
                                                        : 1;
 }
 
+// Rows of Q are even or odd under e -> -e (density, energy and stress moments even; the
+// momentum, heat flux and third-order moments odd), so each transform works on the sums
+// and differences of the nine pairs of opposite velocities.
+constexpr int kMrtOpp[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+constexpr bool mrt_even(int k) {
+    LBM_MRT_Q
+    for (int i = 0; i < 19; i++)
+        if (MQ[k][i] != MQ[k][kMrtOpp[i]]) return false;
+    return true;
+}
+constexpr bool mrt_odd(int k) {
+    LBM_MRT_Q
+    for (int i = 0; i < 19; i++)
+        if (MQ[k][i] != -MQ[k][kMrtOpp[i]]) return false;
+    return true;
+}
+constexpr bool mrt_rows_split() {
+    for (int k = 0; k < 19; k++)
+        if (!mrt_even(k) && !mrt_odd(k)) return false;
+    return true;
+}
+static_assert(mrt_rows_split(), "every row of Q is even or odd under e -> -e");
+
 template <class R>
 __device__ inline void mrt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R ux, R uy, R uz,
                                    R Fx, R Fy, R Fz, R s_nu, R s_q, R (&out)[19]) {
     LBM_D3Q19_TABLES
     LBM_MRT_Q
     const R W0 = R(1) / R(3), W1 = R(1) / R(18), W2 = R(1) / R(36);
-    R srcv[19];
     const R uF = ux * Fx + uy * Fy + uz * Fz;
+    // pair sums and differences of f and of Guo's source w_i [3 (e.F - u.F) + 9 (e.u)(e.F)]
+    // (the source's sum over a pair is 2 w_i [9 (e.u)(e.F) - 3 u.F], its difference
+    // 6 w_i e.F)
+    R fs[19], fd[19], ss[19], sd[19];
 #pragma unroll
-    for (int i = 0; i < 19; i++) {
-        const R w = i == 0 ? W0 : (i < 7 ? W1 : W2);
+    for (int i = 1; i < 19; i++) {
+        if (OPP[i] < i) continue;
+        const R w = i < 7 ? W1 : W2;
         const R eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
         const R eF = EX[i] * Fx + EY[i] * Fy + EZ[i] * Fz;
-        srcv[i] = w * (R(3) * (eF - uF) + R(9) * eu * eF);
+        fs[i] = f[i] + f[OPP[i]];
+        fd[i] = f[i] - f[OPP[i]];
+        ss[i] = R(2) * w * (R(9) * eu * eF - R(3) * uF);
+        sd[i] = R(6) * w * eF;
     }
+    const R s0 = W0 * (R(-3) * uF);
     const R jj = jx * jx + jy * jy + jz * jz;
     const R t9 = R(3) * jx * jx - jj, t11 = jy * jy - jz * jz;
     const R meq[19] = {drho, R(-11) * drho + R(19) * jj, R(3) * drho - R(5.5) * jj,
@@ -287,25 +318,44 @@ __device__ inline void mrt_collide(const R (&f)[19], R drho, R jx, R jy, R jz, R
     R ms[19];
 #pragma unroll
     for (int k = 0; k < 19; k++) {
+        const bool ev = mrt_even(k);
         R m = 0, fm = 0;
+        if (ev && MQ[k][0] != 0) {
+            m = R(MQ[k][0]) * f[0];
+            fm = R(MQ[k][0]) * s0;
+        }
 #pragma unroll
-        for (int i = 0; i < 19; i++) {
-            if (MQ[k][i] == 0) continue;
-            m += R(MQ[k][i]) * f[i];
-            fm += R(MQ[k][i]) * srcv[i];
+        for (int i = 1; i < 19; i++) {
+            if (OPP[i] < i || MQ[k][i] == 0) continue;
+            m += R(MQ[k][i]) * (ev ? fs[i] : fd[i]);
+            fm += R(MQ[k][i]) * (ev ? ss[i] : sd[i]);
         }
         const R sk = mrt_class(k) == 0 ? R(0) : (mrt_class(k) == 1 ? s_nu : s_q);
-        ms[k] = (m - sk * (m - meq[k]) + (R(1) - R(0.5) * sk) * fm) / R(mrt_norm2(k));
+        ms[k] = (m - sk * (m - meq[k]) + (R(1) - R(0.5) * sk) * fm) * R(1.0 / mrt_norm2(k));
+    }
+    // back through Q^T / |Q_k|^2: for each pair the even rows give E, the odd ones O, and
+    // the pair's members are E + O and E - O
+    {
+        R v = 0;
+#pragma unroll
+        for (int k = 0; k < 19; k++)
+            if (mrt_even(k) && MQ[k][0] != 0) v += R(MQ[k][0]) * ms[k];
+        out[0] = v;
     }
 #pragma unroll
-    for (int i = 0; i < 19; i++) {
-        R v = 0;
+    for (int i = 1; i < 19; i++) {
+        if (OPP[i] < i) continue;
+        R e = 0, o = 0;
 #pragma unroll
         for (int k = 0; k < 19; k++) {
             if (MQ[k][i] == 0) continue;
-            v += R(MQ[k][i]) * ms[k];
+            if (mrt_even(k))
+                e += R(MQ[k][i]) * ms[k];
+            else
+                o += R(MQ[k][i]) * ms[k];
         }
-        out[i] = v;
+        out[i] = e + o;
+        out[OPP[i]] = e - o;
     }
 }
 
