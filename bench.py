@@ -62,9 +62,9 @@ COUNTERS = {
         files=("paper_1410_1921_amd/csrc/knudsen.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
                "paper_1410_1921_amd/csrc/common.hip"), sha="b62b1248619e5586"),
     SWEEP19: dict(
-        workload="recon512_eps0.25_d16", fetch_kib=2217150.5, write_kib=2490368.6,
+        workload="recon512_eps0.25_d16", fetch_kib=2217149.4, write_kib=2490369.7,
         files=("paper_1410_1921_amd/csrc/flow.hip", "paper_1410_1921_amd/csrc/lbm_internal.h",
-               "paper_1410_1921_amd/csrc/common.hip"), sha="0aef368bdf5025fb"),
+               "paper_1410_1921_amd/csrc/common.hip"), sha="3613d5c4e8f11afe"),
 }
 
 
